@@ -1,0 +1,250 @@
+"""Oracle for the Magnus-expansion time-evolution path.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import or call this module; the product path never does.
+
+A plain, slow, obviously-correct CPU implementation in NumPy complex128 /
+float64.  It shares no code with the HIP library and imports nothing from this
+repository.  Every function follows the paper (arXiv 2411.09982, Sec. 4.1) step
+by step, with no blocking, fusion or reordering:
+
+  coefficients   Eq. magnus-first-order-coeff (first order) and the double
+                 integral of Eq. magnus-avg (second order), evaluated exactly for
+                 a zero-order-hold signal;
+  H-bar_n        Eq. magnus-first-order-term plus the second-order term of
+                 Eq. magnus-avg with H(t) of Eq. magnus-generic-ham;
+  propagator     U_n = exp(-i H-bar_n), by Hermitian eigendecomposition;
+  chain          psi_n = U_n psi_{n-1}, P = U_M ... U_1 (stroboscopic, Sec. 4.1).
+
+Readings of the paper this file takes (the paper is silent or garbled there):
+  * sample i of u holds on [t0 + i dt, t0 + (i+1) dt) (zero-order hold), and the
+    N samples split into M equal intervals of s = N / M samples;
+  * the series is read per interval [t_n, t_n + Delta t] and truncated at order
+    1 or 2; the second-order term uses t2 < t1 and the prefactor -i/2;
+  * U_n = exp(-i H-bar_n) with hbar = 1; the generator is Omega_n = -i H-bar_n;
+  * later intervals multiply on the left.
+
+Layout of the second-order coefficient table c2[M][K + K(K-1)/2]:
+  columns 0..K-1        c20[n,k] weights the commutator [H0, H_k];
+  column  K + p(k,l)    c2[n,(k,l)] weights [H_k, H_l] for k < l, with pairs in
+                        row-major order (0,1), (0,2), ..., (0,K-1), (1,2), ...
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Higham (2005), "The scaling and squaring method for the matrix exponential
+# revisited", Table 2.3: largest 1-norm for which the [13/13] Pade approximant
+# reaches double-precision backward error.
+THETA13_F64 = 5.371920351148152
+
+
+# ------------------------------------------------------------------ checks
+
+def check_inputs(H0, Hk, u, M, hermitian_tol=1e-12):
+    """Validate shapes, finiteness, Hermiticity and N % M == 0; raise ValueError."""
+    H0 = np.asarray(H0)
+    Hk = np.asarray(Hk)
+    u = np.asarray(u)
+    if H0.ndim != 2 or H0.shape[0] != H0.shape[1]:
+        raise ValueError("H0 must be square")
+    d = H0.shape[0]
+    if Hk.ndim != 3 or Hk.shape[1:] != (d, d):
+        raise ValueError("Hk must be [K][d][d]")
+    if u.ndim != 2 or u.shape[0] != Hk.shape[0]:
+        raise ValueError("u must be [K][N]")
+    if np.iscomplexobj(u) or not np.all(np.isfinite(u)):
+        raise ValueError("u must be real and finite")
+    N = u.shape[1]
+    if M <= 0 or N % M != 0:
+        raise ValueError("N must be a positive multiple of M")
+    for H in [H0, *Hk]:
+        scale = max(np.abs(H).max(), 1e-300)
+        if np.abs(H - H.conj().T).max() > hermitian_tol * scale:
+            raise ValueError("operators must be Hermitian")
+
+
+def pair_index(k: int, l: int, K: int) -> int:
+    """Column of the (k, l), k < l, commutator coefficient in the c2 table."""
+    assert 0 <= k < l < K
+    return K + k * K - k * (k + 1) // 2 + (l - k - 1)
+
+
+# ------------------------------------------------------------ coefficients
+
+def interval_coefficients(u, dt_sample, M, order):
+    """Per-interval Magnus coefficients of a zero-order-hold control signal.
+
+    First order (Eq. magnus-first-order-coeff): c1[n,k] is the integral of u_k
+    over interval n, i.e. dt * sum of its s samples.
+
+    Second order (Eq. magnus-avg, second line, with H of Eq. magnus-generic-ham):
+    the commutator [H(t1), H(t2)] expands into
+        sum_k (u_k(t2) - u_k(t1)) [H0, H_k]
+      + sum_{k<l} (u_k(t1) u_l(t2) - u_l(t1) u_k(t2)) [H_k, H_l],
+    and the double integral over t2 < t1 inside the interval is exact for a
+    piecewise-constant signal:
+        c20[n,k]   = dt^2 * sum_j (s - 1 - 2 j) u_k[j]
+        c2[n,(kl)] = dt^2 * sum_j sum_{i<j} (u_k[j] u_l[i] - u_l[j] u_k[i])
+    (j indexes the samples of the interval; same-cell pairs cancel).
+    """
+    u = np.asarray(u, dtype=np.float64)
+    K, N = u.shape
+    s = N // M
+    dt = float(dt_sample)
+    c1 = np.empty((M, K))
+    c2 = np.zeros((M, K + K * (K - 1) // 2)) if order == 2 else None
+    w = (s - 1 - 2 * np.arange(s)).astype(np.float64)
+    for n in range(M):
+        seg = u[:, n * s:(n + 1) * s]
+        for k in range(K):
+            c1[n, k] = dt * math.fsum(seg[k])
+        if order == 2:
+            for k in range(K):
+                c2[n, k] = dt * dt * math.fsum(w * seg[k])
+            # exclusive prefix sums P_k[j] = sum_{i<j} u_k[i]
+            P = np.zeros_like(seg)
+            P[:, 1:] = np.cumsum(seg[:, :-1], axis=1)
+            for k in range(K):
+                for l in range(k + 1, K):
+                    c2[n, pair_index(k, l, K)] = dt * dt * math.fsum(
+                        np.concatenate([seg[k] * P[l], -(seg[l] * P[k])]))
+    return c1, c2
+
+
+# -------------------------------------------------------- effective H-bar
+
+def commutator(A, B):
+    return A @ B - B @ A
+
+
+def effective_hamiltonians(H0, Hk, c1, c2, dt_interval, order):
+    """H-bar_n for every interval (Eq. magnus-first-order-term; Eq. magnus-avg).
+
+    H-bar_n = Delta t H0 + sum_k c1[n,k] H_k
+            - (i/2) (sum_k c20[n,k] [H0,H_k] + sum_{k<l} c2[n,(kl)] [H_k,H_l])   (order 2)
+    """
+    H0 = np.asarray(H0, dtype=np.complex128)
+    Hk = np.asarray(Hk, dtype=np.complex128)
+    K, d = Hk.shape[0], H0.shape[0]
+    M = c1.shape[0]
+    comms = []
+    if order == 2:
+        comms = [(k, commutator(H0, Hk[k])) for k in range(K)]
+        comms += [(pair_index(k, l, K), commutator(Hk[k], Hk[l]))
+                  for k in range(K) for l in range(k + 1, K)]
+    out = np.empty((M, d, d), dtype=np.complex128)
+    for n in range(M):
+        H = dt_interval * H0
+        for k in range(K):
+            H = H + c1[n, k] * Hk[k]
+        if order == 2:
+            S = np.zeros((d, d), dtype=np.complex128)
+            for col, C in comms:
+                S = S + c2[n, col] * C
+            H = H - 0.5j * S
+        out[n] = 0.5 * (H + H.conj().T)
+    return out
+
+
+def generators(H0, Hk, c1, c2, dt_interval, order):
+    """Omega_n = -i H-bar_n (skew-Hermitian), so that U_n = exp(Omega_n)."""
+    return -1j * effective_hamiltonians(H0, Hk, c1, c2, dt_interval, order)
+
+
+# ------------------------------------------------------------- exponential
+
+def propagator_from_hamiltonian(Hbar):
+    """U = exp(-i H-bar) = V diag(exp(-i lambda)) V^dag from eigh of the Hermitian H-bar."""
+    Hbar = np.asarray(Hbar, dtype=np.complex128)
+    if Hbar.ndim == 2:
+        lam, V = np.linalg.eigh(Hbar)
+        return (V * np.exp(-1j * lam)) @ V.conj().T
+    return np.stack([propagator_from_hamiltonian(h) for h in Hbar])
+
+
+def expm_skew_hermitian(Omega):
+    """exp(Omega) for skew-Hermitian Omega, via eigh of i*Omega (which is Hermitian)."""
+    Omega = np.asarray(Omega, dtype=np.complex128)
+    H = 1j * Omega
+    H = 0.5 * (H + np.conj(np.swapaxes(H, -1, -2)))
+    return propagator_from_hamiltonian(H)
+
+
+def norm1(A):
+    """Matrix 1-norm: largest column sum of absolute values."""
+    return float(np.abs(np.asarray(A)).sum(axis=-2).max())
+
+
+def scaling_exponent(Omega):
+    """Number of squarings s of the [13/13] scaling-and-squaring method (Higham 2005):
+    s = max(0, ceil(log2(||Omega||_1 / theta_13))), in float64."""
+    nrm = norm1(Omega)
+    if nrm <= THETA13_F64:
+        return 0
+    return max(0, int(math.ceil(math.log2(nrm / THETA13_F64))))
+
+
+# -------------------------------------------------------------------- chain
+
+def propagate_state(U, psi0, trajectory=False):
+    """Stroboscopic state chain psi_n = U_n psi_{n-1}, n = 1..M."""
+    psi = np.asarray(psi0, dtype=np.complex128).copy()
+    traj = [psi.copy()]
+    for Un in U:
+        psi = Un @ psi
+        traj.append(psi.copy())
+    return (psi, np.stack(traj)) if trajectory else psi
+
+
+def propagate_product(U):
+    """P = U_M ... U_2 U_1 (later intervals on the left)."""
+    d = U.shape[-1]
+    P = np.eye(d, dtype=np.complex128)
+    for Un in U:
+        P = Un @ P
+    return P
+
+
+# ------------------------------------------------------------------ metrics
+
+def propagator_infidelity(U_ref, U):
+    """1 - |tr(U_ref^dag U)|^2 / d^2 (global-phase insensitive)."""
+    U_ref = np.asarray(U_ref, dtype=np.complex128)
+    U = np.asarray(U, dtype=np.complex128)
+    d = U.shape[-1]
+    tr = np.einsum("...ij,...ij->...", U_ref.conj(), U)
+    return 1.0 - np.abs(tr) ** 2 / (d * d)
+
+
+def state_infidelity(psi_ref, psi):
+    """1 - |<psi_ref|psi>|^2 (the state error of Sec. 4.3)."""
+    return 1.0 - abs(np.vdot(np.asarray(psi_ref), np.asarray(psi))) ** 2
+
+
+def unitarity_error(U):
+    U = np.asarray(U, dtype=np.complex128)
+    d = U.shape[-1]
+    G = np.conj(np.swapaxes(U, -1, -2)) @ U
+    return float(np.abs(G - np.eye(d)).max())
+
+
+# --------------------------------------------------------------------- job
+
+def run(H0, Hk, u, dt_sample, M, order, psi0=None, product=False, check=True):
+    """The whole path on the CPU: coefficients -> Omega_n -> U_n -> chain."""
+    if check:
+        check_inputs(H0, Hk, u, M)
+    N = np.asarray(u).shape[1]
+    dt_interval = dt_sample * (N // M)
+    c1, c2 = interval_coefficients(u, dt_sample, M, order)
+    Hbar = effective_hamiltonians(H0, Hk, c1, c2, dt_interval, order)
+    U = propagator_from_hamiltonian(Hbar)
+    out = dict(c1=c1, c2=c2, Hbar=Hbar, Omega=-1j * Hbar, U=U)
+    if psi0 is not None:
+        out["psi"], out["traj"] = propagate_state(U, psi0, trajectory=True)
+    if product:
+        out["P"] = propagate_product(U)
+    return out

@@ -1,0 +1,68 @@
+"""Plant plausible mistakes in a copy of the oracle and check that the pins catch each.
+
+Each mutant is the oracle's own source with one edit (a wrong sign, index,
+dropped term or transposed product), loaded as a separate module on the CPU; the
+pin tests are then run against it and at least one must fail.
+"""
+import importlib.util
+import inspect
+import os
+import types
+
+import pytest
+
+import oracle.magnus as om
+import tests.test_oracle_pins as pins
+
+MUTANTS = {
+    "c20_weight_index": ("w = (s - 1 - 2 * np.arange(s))", "w = (s + 1 - 2 * np.arange(s))"),
+    "order2_sign": ("H = H - 0.5j * S", "H = H + 0.5j * S"),
+    "chain_transposed": ("P = Un @ P", "P = P @ Un"),
+    "exp_sign": ("np.exp(-1j * lam)", "np.exp(1j * lam)"),
+    "pair_sign": ("seg[k] * P[l], -(seg[l] * P[k])", "seg[k] * P[l], (seg[l] * P[k])"),
+    "drive_index": ("H = H + c1[n, k] * Hk[k]", "H = H + c1[n, k] * Hk[0]"),
+    "dropped_sample": ("c1[n, k] = dt * math.fsum(seg[k])", "c1[n, k] = dt * math.fsum(seg[k][1:])"),
+    "commutator_swapped": ("comms = [(k, commutator(H0, Hk[k]))", "comms = [(k, commutator(Hk[k], H0))"),
+    "missing_conj": ("@ V.conj().T", "@ V.T"),
+    "c20_missing_dt": ("c2[n, k] = dt * dt * math.fsum(w * seg[k])", "c2[n, k] = dt * math.fsum(w * seg[k])"),
+    "scaling_floor": ("int(math.ceil(math.log2(nrm / THETA13_F64)))", "int(math.floor(math.log2(nrm / THETA13_F64)))"),
+    "state_adjoint": ("psi = Un @ psi", "psi = Un.conj().T @ psi"),
+    "drift_dropped": ("H = dt_interval * H0", "H = 0.0 * H0"),
+}
+
+
+def _load_mutant(name):
+    src = inspect.getsource(om)
+    old, new = MUTANTS[name]
+    assert src.count(old) >= 1, name
+    mod = types.ModuleType(f"oracle_mutant_{name}")
+    exec(compile(src.replace(old, new), f"<mutant {name}>", "exec"), mod.__dict__)
+    return mod
+
+
+def _pin_calls():
+    for fname, fn in sorted(vars(pins).items()):
+        if not fname.startswith("test_") or not callable(fn):
+            continue
+        marks = getattr(fn, "pytestmark", [])
+        params = [m for m in marks if m.name == "parametrize"]
+        if params:
+            argname, values = params[0].args
+            for v in values:
+                yield fname, (lambda fn=fn, argname=argname, v=v: fn(**{argname: v}))
+        else:
+            yield fname, fn
+
+
+@pytest.mark.filterwarnings("ignore")
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, monkeypatch):
+    mutant = _load_mutant(name)
+    monkeypatch.setattr(pins, "oracle", mutant)
+    caught = []
+    for fname, call in _pin_calls():
+        try:
+            call()
+        except Exception:
+            caught.append(fname)
+    assert caught, f"no pin caught mutant {name}"
