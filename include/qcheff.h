@@ -1,0 +1,201 @@
+/*
+ * qcheff.h - C ABI of the MI355X (gfx950) Magnus time-evolution library
+ *            libqcheff_magnus.so.
+ *
+ * The path follows arXiv 2411.09982, Sec. 4.1: a drive Hamiltonian
+ *     H(t) = H0 + sum_k u_k(t) H_k                        (Eq. magnus-generic-ham)
+ * sampled on N time cells and cut into M equal Magnus intervals.  For interval n
+ * the library forms the effective Hamiltonian H-bar_n (first order:
+ * Eq. magnus-first-order-term with the coefficients of
+ * Eq. magnus-first-order-coeff; second order: the double-commutator term of
+ * Eq. magnus-avg), the generator Omega_n = -i H-bar_n, the propagator
+ * U_n = exp(Omega_n), and chains the propagators stroboscopically.
+ *
+ * Conventions shared by every entry point
+ *   - hbar = 1.  Times in the caller's unit (ns), frequencies in rad per unit.
+ *   - Array pointers are DEVICE pointers unless stated otherwise.  Matrices are
+ *     dense, row-major, contiguous; element (i, j) of item b of a [B][d][d]
+ *     batch sits at offset (b*d + i)*d + j.  Complex numbers are interleaved
+ *     (re, im) pairs: QCHEFF_C128 = two doubles (16 B), QCHEFF_C64 = two floats
+ *     (8 B) - the memory layout of std::complex, C99 _Complex and
+ *     torch.complex128 / torch.complex64.
+ *   - The caller owns every buffer.  The library never allocates or frees caller
+ *     memory; scratch memory is the caller's workspace (ws, ws_bytes), sized with
+ *     qcheff_workspace_bytes().  It keeps no per-job state between calls.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every call
+ *     enqueues work on that stream and returns without waiting for it, except
+ *     qcheff_expm_batched, which waits on the stream once per chunk to read the
+ *     largest squaring count (see there).
+ *   - Errors: every shape, pointer and workspace check runs on the host before
+ *     anything is enqueued; on failure nothing is launched and the call returns
+ *     a negative status.  qcheff_last_error() gives a message for the calling
+ *     thread's last failure.  A failed launch returns QCHEFF_EDEVICE.
+ *   - Calls on distinct streams with distinct buffers may run concurrently.
+ */
+#ifndef QCHEFF_H
+#define QCHEFF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define QCHEFF_OK            0
+#define QCHEFF_EINVAL       -1  /* bad shape, pointer, order, mode or flag      */
+#define QCHEFF_EWORKSPACE   -2  /* workspace missing or too small               */
+#define QCHEFF_EDEVICE      -3  /* a HIP call or kernel launch failed           */
+#define QCHEFF_EUNSUPPORTED -5  /* valid request this build does not implement */
+
+/* element types */
+#define QCHEFF_C128 1           /* complex double; every step in FP64           */
+#define QCHEFF_C64  2           /* complex float; products and squarings in FP32
+                                   on MFMA, the norm, the scaling choice and the
+                                   Pade denominator solve in FP64               */
+
+/* qcheff_propagate modes */
+#define QCHEFF_STATE   1
+#define QCHEFF_PRODUCT 2
+
+/* qcheff_magnus_generators flags */
+#define QCHEFF_REUSE_BASIS 1u
+
+/* qcheff_workspace_bytes selectors */
+#define QCHEFF_FN_GENERATORS 1
+#define QCHEFF_FN_EXPM       2
+#define QCHEFF_FN_PROPAGATE  3
+
+/*
+ * qcheff_magnus_coeffs - per-interval Magnus coefficients of the control
+ * signals (Sec. 4.1, Eq. magnus-first-order-coeff; second order from the
+ * double integral of Eq. magnus-avg).
+ *
+ *   u          [K][N] float64, device.  Sample i of control k holds on the cell
+ *              [t0 + i*dt_sample, t0 + (i+1)*dt_sample) (zero-order hold).
+ *   K, N       controls and samples; K >= 1, N >= 1, N % M == 0.
+ *   dt_sample  cell width (> 0, finite).
+ *   M          number of intervals; interval n owns samples [n*s, (n+1)*s), s = N/M.
+ *   order      1 or 2.
+ *   c1         [M][K] float64, device, written:
+ *                c1[n][k] = dt_sample * sum_j u[k][n*s + j].
+ *   c2         order 2: [M][K + K(K-1)/2] float64, device, written; ignored
+ *              (may be NULL) for order 1.  Columns 0..K-1 weight [H0, H_k]:
+ *                c2[n][k] = dt^2 * sum_j (s - 1 - 2j) u_k[j];
+ *              column K + p weights [H_k, H_l] for the p-th pair k < l in
+ *              row-major order (0,1), (0,2), ..., (1,2), ...:
+ *                c2[n][K+p] = dt^2 * sum_j sum_{i<j} (u_k[j] u_l[i] - u_l[j] u_k[i]).
+ *              Both are the exact double integrals for a zero-order-hold
+ *              signal.  Sums are compensated (Neumaier) in FP64.
+ *   Returns QCHEFF_OK, QCHEFF_EINVAL (shapes, NULL pointers, order, N % M,
+ *   dt_sample), QCHEFF_EDEVICE.
+ */
+int qcheff_magnus_coeffs(const double* u, int64_t K, int64_t N, double dt_sample,
+                         int64_t M, int order, double* c1, double* c2, void* stream);
+
+/*
+ * qcheff_magnus_generators - Omega_n = -i H-bar_n for M intervals
+ * (Eq. magnus-first-order-term; second-order term of Eq. magnus-avg):
+ *   H-bar_n = dt_interval H0 + sum_k c1[n][k] H_k
+ *             - (i/2) ( sum_k c2[n][k] [H0,H_k] + sum_{k<l} c2[n][K+p(k,l)] [H_k,H_l] ).
+ *
+ *   H0         [d][d] Hermitian, device, op_dtype.
+ *   Hk         [K][d][d] Hermitian, device, op_dtype.  Hermiticity is not checked.
+ *   op_dtype   QCHEFF_C128 (this build accepts C128 operators only).
+ *   c1, c2     as written by qcheff_magnus_coeffs (device); c2 may be NULL for order 1.
+ *   M          intervals to form (>= 0).  A caller that streams intervals in
+ *              chunks passes c1/c2 offset to the chunk and the chunk's M.
+ *   dt_interval  interval length s*dt_sample.
+ *   out_dtype  QCHEFF_C128 or QCHEFF_C64 (FP64 assembly, one rounding at the store).
+ *   omega      [M][d][d] out_dtype, device, written.
+ *   ws         order 2: holds the commutator basis, K + K(K-1)/2 matrices in
+ *              C128, computed here (two-operator products on MFMA, FP64) unless
+ *              flags has QCHEFF_REUSE_BASIS, in which case ws must hold the
+ *              basis of an earlier call with the same H0, Hk (the operators are
+ *              unchanged when only the control signals change).  Order 1 needs
+ *              no workspace.
+ *   Returns QCHEFF_OK, QCHEFF_EINVAL, QCHEFF_EWORKSPACE, QCHEFF_EUNSUPPORTED
+ *   (op_dtype other than C128, K > 8), QCHEFF_EDEVICE.
+ */
+int qcheff_magnus_generators(const void* H0, const void* Hk, int64_t d, int64_t K, int op_dtype,
+                             const double* c1, const double* c2, int64_t M, double dt_interval,
+                             int order, int out_dtype, void* omega, void* ws, size_t ws_bytes,
+                             unsigned flags, void* stream);
+
+/*
+ * qcheff_expm_batched - U_b = exp(Omega_b) for a batch of d x d matrices by
+ * [13/13] Pade scaling and squaring (the exponentiation step of Sec. 4.1; the
+ * method is Higham 2005: s_b = smallest s >= 0 with ||Omega_b||_1 / 2^s <= 5.3719...,
+ * computed in FP64; A = Omega_b / 2^s; R = q(A)^-1 p(A) by LU with partial
+ * pivoting in FP64; U_b = R^(2^s)).
+ *
+ *   omega      [batch][d][d], device, dtype.  Any square matrix; the Magnus
+ *              generators are skew-Hermitian.
+ *   U          [batch][d][d], device, dtype, written.  May be the same buffer
+ *              as omega (the input is consumed).
+ *   s_out      optional [batch] int32, device: the number of squarings used,
+ *              -1 where the norm was not finite (that item's U is NaN).
+ *   ws         workspace of at least qcheff_workspace_bytes(QCHEFF_FN_EXPM, 1, d, ..);
+ *              items are processed in chunks of as many as the workspace holds.
+ *   The call waits on `stream` once per chunk (to read the largest squaring
+ *   count of the chunk); everything else is enqueued.
+ *   Returns QCHEFF_OK, QCHEFF_EINVAL, QCHEFF_EWORKSPACE, QCHEFF_EDEVICE.
+ */
+int qcheff_expm_batched(const void* omega, int64_t batch, int64_t d, int dtype, void* U,
+                        int32_t* s_out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * qcheff_propagate - stroboscopic chain of the interval propagators (Sec. 4.1:
+ * the evolution is exact at multiples of the interval; later intervals act
+ * on the left).
+ *
+ *   U          [M][d][d], device, dtype.
+ *   mode       QCHEFF_STATE:   x is psi [d] complex128 (always FP64), in: psi_0,
+ *                              out: psi_M = U_M ... U_1 psi_0.  Products accumulate
+ *                              in FP64.
+ *              QCHEFF_PRODUCT: x is P [d][d] in dtype, out: P = U_M ... U_1
+ *                              (binary-tree reduction on MFMA).
+ *   traj       optional (STATE only) [M+1][d] complex128: psi_0 ... psi_M.
+ *   ws         STATE: 2*d complex128; PRODUCT: (ceil(M/2) + ceil(M/4)) d^2 dtype.
+ *   Returns QCHEFF_OK, QCHEFF_EINVAL, QCHEFF_EWORKSPACE, QCHEFF_EDEVICE.
+ */
+int qcheff_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, void* x,
+                     void* traj, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * qcheff_workspace_bytes - workspace needed by `fn` (QCHEFF_FN_*):
+ *   GENERATORS: (batch, K, order, d) -> commutator basis bytes (0 for order 1);
+ *   EXPM:       bytes to process `batch` items at once (per-item size x batch);
+ *   PROPAGATE:  `batch` is M, `order` carries the mode (QCHEFF_STATE / _PRODUCT).
+ * Returns 0 for an invalid selector or shape.
+ */
+size_t qcheff_workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int order, int dtype);
+
+/* Message for the calling thread's last non-OK status (never NULL). */
+const char* qcheff_last_error(void);
+
+/*
+ * Kernel timing (instrumentation for throughput and roofline measurements).
+ * While enabled, every launch of the library's complex MFMA GEMM kernel is
+ * bracketed by a pair of HIP events recorded on the launch stream, together
+ * with the launch's algorithmic flop count (8 M N K per active item: a complex
+ * multiply-add is 8 real flops) and byte count (operands read once, result
+ * written once).
+ *   qcheff_timing_enable(1) clears old records and starts recording;
+ *   qcheff_timing_enable(0) clears them and stops.
+ *   qcheff_timing_read(kernel, ...) waits for the recorded events of `kernel`
+ *   (QCHEFF_KERNEL_GEMM_F32 / _F64), returns the number of launches, the summed
+ *   event-to-event time in ms and the summed flops and bytes, and releases
+ *   those records.  Returns QCHEFF_OK, QCHEFF_EINVAL, QCHEFF_EDEVICE.
+ * Recording costs two event records per GEMM launch; leave it off otherwise.
+ */
+#define QCHEFF_KERNEL_GEMM_F32 1
+#define QCHEFF_KERNEL_GEMM_F64 2
+int qcheff_timing_enable(int on);
+int qcheff_timing_read(int kernel, int64_t* launches, double* total_ms, double* flops, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QCHEFF_H */

@@ -180,11 +180,16 @@ def norm1(A):
 
 def scaling_exponent(Omega):
     """Number of squarings s of the [13/13] scaling-and-squaring method (Higham 2005):
-    s = max(0, ceil(log2(||Omega||_1 / theta_13))), in float64."""
+    the smallest s >= 0 with ||Omega||_1 / 2^s <= theta_13 (that is,
+    max(0, ceil(log2(||Omega||_1 / theta_13)))), decided by exact float64
+    comparisons against theta_13 * 2^s; -1 for a non-finite norm."""
     nrm = norm1(Omega)
-    if nrm <= THETA13_F64:
-        return 0
-    return max(0, int(math.ceil(math.log2(nrm / THETA13_F64))))
+    if not math.isfinite(nrm):
+        return -1
+    s = 0
+    while nrm > math.ldexp(THETA13_F64, s):
+        s += 1
+    return s
 
 
 # -------------------------------------------------------------------- chain

@@ -1,0 +1,202 @@
+"""MI355X-native Magnus time-evolution path (arXiv 2411.09982, Sec. 4.1).
+
+Thin Python binding over the C ABI of ``libqcheff_magnus.so`` (include/qcheff.h).
+Every step runs in the library's HIP kernels; this module only marshals
+arguments: it takes torch tensors on the GPU for device memory, passes their
+data pointers and the current HIP stream, and raises ``QcheffError`` on a
+non-OK status.  There is no CPU fallback: without the built library every call
+raises.
+
+Functions (same names as the C entry points, minus the ``qcheff_`` prefix):
+  magnus_coeffs(u, dt_sample, M, order)                 -> c1, c2
+  magnus_generators(H0, Hk, c1, c2, dt_interval, order, out_dtype) -> omega
+  expm_batched(omega)                                   -> U, s
+  propagate(U, mode, x)                                 -> x (in place)
+and ``evolve(...)``, the four calls in sequence (the paper's evolve()).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqcheff_magnus.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "qcheff.h")
+
+OK, EINVAL, EWORKSPACE, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -5
+C128, C64 = 1, 2
+STATE, PRODUCT = 1, 2
+REUSE_BASIS = 1
+FN_GENERATORS, FN_EXPM, FN_PROPAGATE = 1, 2, 3
+
+_DTYPES = {torch.complex128: C128, torch.complex64: C64}
+_TORCH = {C128: torch.complex128, C64: torch.complex64}
+
+_lib = None
+
+
+class QcheffError(RuntimeError):
+    def __init__(self, fn: str, status: int, message: str):
+        super().__init__(f"{fn} failed with status {status}: {message}")
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """Load the HIP library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing; build it with `python -m paper_2411_09982_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    L.qcheff_magnus_coeffs.argtypes = [vp, i64, i64, dbl, i64, i32, vp, vp, vp]
+    L.qcheff_magnus_generators.argtypes = [vp, vp, i64, i64, i32, vp, vp, i64, dbl, i32, i32, vp, vp,
+                                           ctypes.c_size_t, ctypes.c_uint, vp]
+    L.qcheff_expm_batched.argtypes = [vp, i64, i64, i32, vp, vp, vp, ctypes.c_size_t, vp]
+    L.qcheff_propagate.argtypes = [vp, i64, i64, i32, i32, vp, vp, vp, ctypes.c_size_t, vp]
+    for f in ("qcheff_magnus_coeffs", "qcheff_magnus_generators", "qcheff_expm_batched", "qcheff_propagate"):
+        getattr(L, f).restype = i32
+    L.qcheff_workspace_bytes.argtypes = [i32, i64, i64, i64, i32, i32]
+    L.qcheff_workspace_bytes.restype = ctypes.c_size_t
+    L.qcheff_last_error.argtypes = []
+    L.qcheff_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def header_symbols() -> list[str]:
+    """Names of the functions include/qcheff.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(qcheff_\w+)\s*\(", text, re.M)))
+
+
+def _check(fn: str, status: int) -> None:
+    if status != OK:
+        raise QcheffError(fn, status, lib().qcheff_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous GPU tensor")
+    return t
+
+
+def workspace_bytes(fn: int, batch: int, d: int, K: int = 1, order: int = 1, dtype: int = C128) -> int:
+    return int(lib().qcheff_workspace_bytes(fn, batch, d, K, order, dtype))
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor | None:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device) if nbytes else None
+
+
+# --------------------------------------------------------------------- ABI
+
+def magnus_coeffs(u: torch.Tensor, dt_sample: float, M: int, order: int, c1=None, c2=None, stream=None):
+    """Per-interval coefficients (qcheff_magnus_coeffs).  u: [K][N] float64 on the GPU."""
+    _dev(u, "u")
+    K, N = u.shape
+    if c1 is None:
+        c1 = torch.empty((M, K), dtype=torch.float64, device=u.device)
+    if order == 2 and c2 is None:
+        c2 = torch.empty((M, K + K * (K - 1) // 2), dtype=torch.float64, device=u.device)
+    _check("qcheff_magnus_coeffs", lib().qcheff_magnus_coeffs(
+        _ptr(u), K, N, float(dt_sample), M, order, _ptr(c1), _ptr(c2) if order == 2 else None, _stream(stream)))
+    return c1, (c2 if order == 2 else None)
+
+
+def magnus_generators(H0, Hk, c1, c2, dt_interval: float, order: int, out_dtype=torch.complex64,
+                      omega=None, ws=None, reuse_basis: bool = False, stream=None):
+    """Omega_n = -i H-bar_n for every interval (qcheff_magnus_generators).
+
+    Returns (omega, ws); pass ``ws`` back with ``reuse_basis=True`` to skip the
+    commutator basis when only the control signals changed.
+    """
+    _dev(H0, "H0")
+    _dev(Hk, "Hk")
+    d, K, M = H0.shape[0], Hk.shape[0], c1.shape[0]
+    odt = _DTYPES[out_dtype]
+    if omega is None:
+        omega = torch.empty((M, d, d), dtype=out_dtype, device=H0.device)
+    need = workspace_bytes(FN_GENERATORS, 1, d, K, order, C128)
+    if ws is None:
+        ws = _workspace(need, H0.device)
+    _check("qcheff_magnus_generators", lib().qcheff_magnus_generators(
+        _ptr(H0), _ptr(Hk), d, K, _DTYPES[H0.dtype], _ptr(c1), _ptr(c2), M, float(dt_interval), order, odt,
+        _ptr(omega), _ptr(ws), 0 if ws is None else ws.numel(), REUSE_BASIS if reuse_basis else 0,
+        _stream(stream)))
+    return omega, ws
+
+
+def expm_batched(omega, U=None, s_out=None, ws=None, chunk: int | None = None, stream=None):
+    """U_b = exp(omega_b) by [13/13] Pade scaling and squaring (qcheff_expm_batched).
+
+    ``U`` may be ``omega`` itself.  ``chunk`` caps the items processed at once
+    (the workspace is sized for it).  Returns (U, s).
+    """
+    _dev(omega, "omega")
+    B, d = omega.shape[0], omega.shape[-1]
+    dt = _DTYPES[omega.dtype]
+    if U is None:
+        U = torch.empty_like(omega)
+    if s_out is None:
+        s_out = torch.empty(B, dtype=torch.int32, device=omega.device)
+    if ws is None:
+        ws = _workspace(workspace_bytes(FN_EXPM, max(1, min(B, chunk or B)), d, 1, 1, dt), omega.device)
+    _check("qcheff_expm_batched", lib().qcheff_expm_batched(
+        _ptr(omega), B, d, dt, _ptr(U), _ptr(s_out), _ptr(ws), ws.numel(), _stream(stream)))
+    return U, s_out
+
+
+def propagate(U, mode: int, x, traj=None, ws=None, stream=None):
+    """Chain the propagators (qcheff_propagate): psi <- U_M ... U_1 psi, or P = U_M ... U_1."""
+    _dev(U, "U")
+    _dev(x, "x")
+    M, d = U.shape[0], U.shape[-1]
+    dt = _DTYPES[U.dtype]
+    if ws is None:
+        ws = _workspace(workspace_bytes(FN_PROPAGATE, M, d, 1, mode, dt), U.device)
+    _check("qcheff_propagate", lib().qcheff_propagate(
+        _ptr(U), M, d, dt, mode, _ptr(x), _ptr(traj), _ptr(ws), 0 if ws is None else ws.numel(),
+        _stream(stream)))
+    return x
+
+
+def evolve(H0, Hk, u, dt_sample: float, M: int, order: int, psi0=None, dtype=torch.complex64,
+           product: bool = False, trajectory: bool = False, chunk: int | None = None, stream=None):
+    """The whole path on the GPU: coefficients -> Omega_n -> U_n -> chain.
+
+    Inputs are GPU tensors (H0 [d][d] and Hk [K][d][d] complex128, u [K][N]
+    float64, psi0 [d] complex128).  Returns a dict with c1, c2, U, s and, as
+    asked, psi (final state), traj, P.
+    """
+    N = u.shape[1]
+    c1, c2 = magnus_coeffs(u, dt_sample, M, order, stream=stream)
+    omega, _ = magnus_generators(H0, Hk, c1, c2, dt_sample * (N // M), order, dtype, stream=stream)
+    U, s = expm_batched(omega, U=omega, chunk=chunk, stream=stream)
+    out = dict(c1=c1, c2=c2, U=U, s=s)
+    if psi0 is not None:
+        psi = psi0.clone()
+        traj = torch.empty((M + 1, psi.shape[0]), dtype=torch.complex128, device=psi.device) if trajectory else None
+        propagate(U, STATE, psi, traj=traj, stream=stream)
+        out["psi"] = psi
+        if trajectory:
+            out["traj"] = traj
+    if product:
+        P = torch.empty(U.shape[1:], dtype=U.dtype, device=U.device)
+        propagate(U, PRODUCT, P, stream=stream)
+        out["P"] = P
+    return out

@@ -1,0 +1,482 @@
+// C ABI of libqcheff_magnus (include/qcheff.h): argument checks, workspace
+// carving and kernel launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <atomic>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/qcheff.h"
+#include "cgemm.hpp"
+#include "kernels.hpp"
+#include "validate.hpp"
+
+namespace qcheff {
+
+// ------------------------------------------------------------- timing
+namespace {
+struct TimedLaunch {
+  int kernel;
+  double flops, bytes;
+  hipEvent_t a, b;
+};
+std::atomic<int> g_timing{0};
+std::mutex g_timing_mu;
+std::vector<TimedLaunch> g_timed;
+}  // namespace
+
+void LaunchTimer::begin(hipStream_t st) {
+  on = g_timing.load(std::memory_order_relaxed) != 0;
+  if (!on) return;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess || hipEventRecord(a, st) != hipSuccess)
+    on = false;
+}
+
+void LaunchTimer::end(hipStream_t st, int kernel, double flops, double bytes) {
+  if (!on) return;
+  if (hipEventRecord(b, st) != hipSuccess) return;
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  g_timed.push_back({kernel, flops, bytes, a, b});
+}
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int fail(int status, const std::string& msg) {
+  g_last_error = msg;
+  return status;
+}
+
+int fail(const Check& c) { return fail(c.status, c.message); }
+
+#define QC_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(QCHEFF_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_));   \
+  } while (0)
+
+inline unsigned nblocks(int64_t n, int per) { return unsigned((n + per - 1) / per); }
+
+// Carves a workspace into 256-byte aligned regions.
+struct Carver {
+  char* p;
+  size_t left;
+  template <typename Tp> Tp* take(size_t bytes) {
+    bytes = align256(bytes);
+    if (bytes > left) return nullptr;
+    Tp* r = reinterpret_cast<Tp*>(p);
+    p += bytes;
+    left -= bytes;
+    return r;
+  }
+};
+
+// [m/m] Pade coefficients of exp: b_j = (2m-j)! m! / ((2m)! j! (m-j)!), b_0 = 1.
+void pade_coefficients(int m, double* b) {
+  b[0] = 1.0;
+  for (int j = 0; j < m; ++j) b[j + 1] = b[j] * double(m - j) / (double(2 * m - j) * double(j + 1));
+}
+
+// Largest 1-norm for which the [13/13] approximant reaches double-precision
+// backward error (Higham 2005, Table 2.3).
+constexpr double kTheta13 = 5.371920351148152;
+
+// ------------------------------------------------------------------- coeffs
+int run_coeffs(const double* u, int64_t K, int64_t N, double dt, int64_t M, int order, double* c1,
+               double* c2, hipStream_t st) {
+  const int64_t s = N / M;
+  hipLaunchKernelGGL(coeffs_kernel, dim3(nblocks(M, 64)), dim3(64), 0, st, u, int(K), N, M, s, dt, order, c1, c2);
+  QC_HIP(hipGetLastError());
+  return QCHEFF_OK;
+}
+
+// --------------------------------------------------------------- generators
+template <int K, int ORDER, typename OutC2>
+hipError_t launch_generators(const double2* H0, const double2* Hk, const double2* Cb, int64_t d,
+                             const double* c1, const double* c2, int64_t M, double dt, OutC2* omega,
+                             hipStream_t st) {
+  constexpr int NC = K + ((ORDER == 2) ? K + K * (K - 1) / 2 : 0);
+  const int nch = 16;
+  const int64_t dd = d * d;
+  dim3 grid(nblocks(dd, 256), unsigned((M + nch - 1) / nch));
+  hipLaunchKernelGGL((generators_kernel<K, ORDER, OutC2>), grid, dim3(256), size_t(nch) * NC * sizeof(double), st,
+                     H0, Hk, Cb, dd, c1, c2, M, nch, dt, omega);
+  return hipGetLastError();
+}
+
+template <int ORDER, typename OutC2>
+hipError_t dispatch_generators(int K, const double2* H0, const double2* Hk, const double2* Cb, int64_t d,
+                               const double* c1, const double* c2, int64_t M, double dt, OutC2* omega,
+                               hipStream_t st) {
+  switch (K) {
+#define QC_CASE(k) \
+  case k: return launch_generators<k, ORDER, OutC2>(H0, Hk, Cb, d, c1, c2, M, dt, omega, st);
+    QC_CASE(1) QC_CASE(2) QC_CASE(3) QC_CASE(4) QC_CASE(5) QC_CASE(6) QC_CASE(7) QC_CASE(8)
+#undef QC_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// [F, G] for Hermitian F, G into C: C = F G on MFMA (FP64), then C <- C - C^dag.
+int commutator(const double2* F, const double2* G, double2* C, int64_t d, hipStream_t st) {
+  auto p = gemm_params<double>(int(d), int(d), int(d), 1);
+  p.A = reinterpret_cast<const double2*>(F); p.lda = d; p.sA = 0;
+  p.B = reinterpret_cast<const double2*>(G); p.ldb = d; p.sB = 0;
+  p.C = C; p.ldc = d; p.sC = 0;
+  QC_HIP((launch_cgemm<double>(p, st)));
+  hipLaunchKernelGGL(antihermitian_part_kernel, dim3(nblocks(d * d, 256)), dim3(256), 0, st, C, int(d));
+  QC_HIP(hipGetLastError());
+  return QCHEFF_OK;
+}
+
+int run_generators(const double2* H0, const double2* Hk, int64_t d, int64_t K, const double* c1,
+                   const double* c2, int64_t M, double dt, int order, int out_dtype, void* omega,
+                   void* ws, unsigned flags, hipStream_t st) {
+  double2* Cb = static_cast<double2*>(ws);
+  const int64_t dd = d * d;
+  if (order == 2 && !(flags & QCHEFF_REUSE_BASIS)) {
+    int q = 0;
+    for (int64_t k = 0; k < K; ++k, ++q) {
+      int r = commutator(H0, Hk + k * dd, Cb + q * dd, d, st);
+      if (r) return r;
+    }
+    for (int64_t k = 0; k < K; ++k)
+      for (int64_t l = k + 1; l < K; ++l, ++q) {
+        int r = commutator(Hk + k * dd, Hk + l * dd, Cb + q * dd, d, st);
+        if (r) return r;
+      }
+  }
+  if (M == 0) return QCHEFF_OK;
+  hipError_t e;
+  if (out_dtype == QCHEFF_C128) {
+    e = (order == 2) ? dispatch_generators<2>(int(K), H0, Hk, Cb, d, c1, c2, M, dt, static_cast<double2*>(omega), st)
+                     : dispatch_generators<1>(int(K), H0, Hk, Cb, d, c1, c2, M, dt, static_cast<double2*>(omega), st);
+  } else {
+    e = (order == 2) ? dispatch_generators<2>(int(K), H0, Hk, Cb, d, c1, c2, M, dt, static_cast<float2*>(omega), st)
+                     : dispatch_generators<1>(int(K), H0, Hk, Cb, d, c1, c2, M, dt, static_cast<float2*>(omega), st);
+  }
+  QC_HIP(e);
+  return QCHEFF_OK;
+}
+
+// --------------------------------------------------------------------- expm
+
+// Workspace regions of one expm chunk.
+template <typename T> struct ExpmWs {
+  using C2 = typename Cx<T>::t;
+  unsigned long long* norms;
+  int* s_ws;
+  int* smax;
+  C2* X[7];
+  double2* aug;
+  int* piv;
+};
+
+template <typename T> bool carve_expm(void* ws, size_t bytes, int64_t chunk, int64_t d, ExpmWs<T>& w) {
+  Carver cv{static_cast<char*>(ws), bytes};
+  const size_t dd = size_t(d) * size_t(d);
+  w.norms = cv.take<unsigned long long>(size_t(chunk) * 8);
+  w.s_ws = cv.take<int>(size_t(chunk) * 4);
+  w.smax = cv.take<int>(256);
+  for (int i = 0; i < 7; ++i) w.X[i] = cv.take<typename Cx<T>::t>(size_t(chunk) * dd * sizeof(typename Cx<T>::t));
+  w.aug = cv.take<double2>(size_t(chunk) * 2 * dd * 16);
+  w.piv = cv.take<int>(size_t(chunk) * size_t(d) * 4);
+  bool ok = w.norms && w.s_ws && w.smax && w.aug && w.piv;
+  for (int i = 0; i < 7; ++i) ok = ok && w.X[i];
+  return ok;
+}
+
+template <typename T>
+int gemm_sq(typename Cx<T>::t* out, const typename Cx<T>::t* A, const typename Cx<T>::t* B, int64_t d,
+            int64_t nb, hipStream_t st, int nx = 0, const typename Cx<T>::t* const* X = nullptr,
+            const T* xc = nullptr, T gamma = T(0)) {
+  auto p = gemm_params<T>(int(d), int(d), int(d), int(nb));
+  const int64_t dd = d * d;
+  p.A = A; p.lda = d; p.sA = dd;
+  p.B = B; p.ldb = d; p.sB = dd;
+  p.C = out; p.ldc = d; p.sC = dd;
+  p.nx = nx;
+  for (int i = 0; i < nx; ++i) { p.X[i] = X[i]; p.xc[i] = xc[i]; }
+  p.gamma = gamma;
+  QC_HIP((launch_cgemm<T>(p, st)));
+  return QCHEFF_OK;
+}
+
+// Solve q R = p for the chunk's augmented systems [q | p] in place (R lands in
+// the right half): blocked LU with partial pivoting, then back substitution.
+int lu_solve(double2* aug, int* piv, int64_t d, int64_t nb, hipStream_t st) {
+  const int64_t ld = 2 * d, stride = 2 * d * d;
+  for (int64_t k0 = 0; k0 < d; k0 += kNb) {
+    const int64_t k1 = std::min<int64_t>(k0 + kNb, d);
+    hipLaunchKernelGGL(lu_panel_kernel, dim3(unsigned(nb)), dim3(256), 0, st, aug, ld, stride, int(d), int(k0),
+                       int(k1), piv);
+    QC_HIP(hipGetLastError());
+    const int64_t ncols = 2 * d - k1;
+    hipLaunchKernelGGL(lu_swap_trsm_kernel, dim3(nblocks(ncols, 256), unsigned(nb)), dim3(256), 0, st, aug, ld,
+                       stride, int(d), int(2 * d), int(k0), int(k1), piv);
+    QC_HIP(hipGetLastError());
+    if (k1 < d) {
+      auto p = gemm_params<double>(int(d - k1), int(2 * d - k1), int(k1 - k0), int(nb));
+      p.A = aug + k1 * ld + k0; p.lda = ld; p.sA = stride;
+      p.B = aug + k0 * ld + k1; p.ldb = ld; p.sB = stride;
+      p.C = aug + k1 * ld + k1; p.ldc = ld; p.sC = stride;
+      p.alpha = -1.0; p.beta = 1.0;
+      QC_HIP((launch_cgemm<double>(p, st)));
+    }
+  }
+  const int64_t nblk = (d + kNb - 1) / kNb;
+  for (int64_t blk = nblk - 1; blk >= 0; --blk) {
+    const int64_t k0 = blk * kNb, k1 = std::min<int64_t>(k0 + kNb, d);
+    hipLaunchKernelGGL(lu_backsub_kernel, dim3(nblocks(d, 256), unsigned(nb)), dim3(256), 0, st, aug, ld, stride,
+                       int(d), int(k0), int(k1));
+    QC_HIP(hipGetLastError());
+    if (k0 > 0) {
+      auto p = gemm_params<double>(int(k0), int(d), int(k1 - k0), int(nb));
+      p.A = aug + k0; p.lda = ld; p.sA = stride;
+      p.B = aug + k0 * ld + d; p.ldb = ld; p.sB = stride;
+      p.C = aug + d; p.ldc = ld; p.sC = stride;
+      p.alpha = -1.0; p.beta = 1.0;
+      QC_HIP((launch_cgemm<double>(p, st)));
+    }
+  }
+  return QCHEFF_OK;
+}
+
+template <typename T>
+int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t* s_out, int64_t nb, int64_t d,
+                   ExpmWs<T>& w, hipStream_t st) {
+  using C2 = typename Cx<T>::t;
+  const int64_t dd = d * d;
+  double b[14];
+  pade_coefficients(13, b);
+  const T c[14] = {T(b[0]), T(b[1]), T(b[2]), T(b[3]), T(b[4]), T(b[5]), T(b[6]),
+                   T(b[7]), T(b[8]), T(b[9]), T(b[10]), T(b[11]), T(b[12]), T(b[13])};
+  // norms and smax start at zero (a fill kernel, not a memset)
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(nblocks(nb * 2, 256)), dim3(256), 0, st,
+                     reinterpret_cast<uint32_t*>(w.norms), nb * 2, 0u);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(w.smax), int64_t(1), 0u);
+  QC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(norm1_kernel<C2>, dim3(nblocks(d, 256), unsigned(nb)), dim3(256), 0, st, omega, int(d),
+                     w.norms);
+  QC_HIP(hipGetLastError());
+  const unsigned sblocks = unsigned(std::min<int64_t>(nblocks(dd, 256), 1024));
+  hipLaunchKernelGGL(scale_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, omega, w.X[0], dd, w.norms,
+                     kTheta13, w.s_ws, s_out, w.smax);
+  QC_HIP(hipGetLastError());
+  C2 *A = w.X[0], *A2 = w.X[1], *A4 = w.X[2], *A6 = w.X[3], *T4 = w.X[4], *W = w.X[5], *V = w.X[6];
+  int r;
+  if ((r = gemm_sq<T>(A2, A, A, d, nb, st))) return r;
+  if ((r = gemm_sq<T>(A4, A2, A2, d, nb, st))) return r;
+  if ((r = gemm_sq<T>(A6, A4, A2, d, nb, st))) return r;
+  const int64_t n = nb * dd;
+  // W = A6 (b13 A6 + b11 A4 + b9 A2) + b7 A6 + b5 A4 + b3 A2 + b1 I   (U = A W)
+  hipLaunchKernelGGL(lincomb3_kernel<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, T4, A6, A4, A2, n, c[13], c[11], c[9]);
+  QC_HIP(hipGetLastError());
+  const C2* Xs[3] = {A6, A4, A2};
+  const T xw[3] = {c[7], c[5], c[3]};
+  if ((r = gemm_sq<T>(W, A6, T4, d, nb, st, 3, Xs, xw, c[1]))) return r;
+  // V = A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I
+  hipLaunchKernelGGL(lincomb3_kernel<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, T4, A6, A4, A2, n, c[12], c[10], c[8]);
+  QC_HIP(hipGetLastError());
+  const T xv[3] = {c[6], c[4], c[2]};
+  if ((r = gemm_sq<T>(V, A6, T4, d, nb, st, 3, Xs, xv, c[0]))) return r;
+  // [q | p] = [V - A W | V + A W] in FP64
+  {
+    auto p = gemm_params<T>(int(d), int(d), int(d), int(nb));
+    p.A = A; p.lda = d; p.sA = dd;
+    p.B = W; p.ldb = d; p.sB = dd;
+    p.C = V; p.ldc = d; p.sC = dd;
+    p.X[0] = V;
+    p.epi = EPI_AUG;
+    p.aug = w.aug; p.ld_aug = 2 * d; p.s_aug = 2 * dd; p.aug_off = d;
+    QC_HIP((launch_cgemm<T>(p, st)));
+  }
+  if ((r = lu_solve(w.aug, w.piv, d, nb, st))) return r;
+  hipLaunchKernelGGL(place_result_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, w.aug, int(d), w.s_ws,
+                     U, A);
+  QC_HIP(hipGetLastError());
+  // the host needs the squaring counts to size the squaring launches
+  std::vector<int> s_host(size_t(nb), 0);
+  QC_HIP(hipMemcpyAsync(s_host.data(), w.s_ws, size_t(nb) * sizeof(int), hipMemcpyDeviceToHost, st));
+  QC_HIP(hipStreamSynchronize(st));
+  const int smax = std::max(0, *std::max_element(s_host.begin(), s_host.end()));
+  for (int step = 0; step < smax; ++step) {
+    const int64_t active = std::count_if(s_host.begin(), s_host.end(), [step](int s) { return s > step; });
+    auto p = gemm_params<T>(int(d), int(d), int(d), int(nb));
+    p.lda = d; p.ldb = d; p.ldc = d;
+    p.sA = dd; p.sB = dd; p.sC = dd;
+    p.sq = 1; p.sq_s = w.s_ws; p.sq_step = step; p.sq_p0 = U; p.sq_p1 = A;
+    QC_HIP((launch_cgemm<T>(p, st, active)));
+  }
+  return QCHEFF_OK;
+}
+
+template <typename T>
+int run_expm(const void* omega, int64_t batch, int64_t d, void* U, int32_t* s_out, void* ws, size_t ws_bytes,
+             int dtype, hipStream_t st) {
+  using C2 = typename Cx<T>::t;
+  const int64_t chunk = expm_chunk(ws_bytes, batch, d, dtype);
+  const int64_t dd = d * d;
+  ExpmWs<T> w;
+  if (!carve_expm<T>(ws, ws_bytes, chunk, d, w)) return fail(QCHEFF_EWORKSPACE, "workspace carving failed");
+  for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
+    const int64_t nb = std::min(chunk, batch - b0);
+    int r = expm_chunk_run<T>(static_cast<const C2*>(omega) + b0 * dd, static_cast<C2*>(U) + b0 * dd,
+                              s_out ? s_out + b0 : nullptr, nb, d, w, st);
+    if (r) return r;
+  }
+  return QCHEFF_OK;
+}
+
+// ---------------------------------------------------------------- propagate
+template <typename T>
+int run_propagate(const void* Uv, int64_t M, int64_t d, int mode, void* x, void* traj, void* ws, hipStream_t st) {
+  using C2 = typename Cx<T>::t;
+  const C2* U = static_cast<const C2*>(Uv);
+  const int64_t dd = d * d;
+  if (mode == QCHEFF_STATE) {
+    double2* psi = static_cast<double2*>(x);
+    double2* t = static_cast<double2*>(traj);
+    double2* buf[2] = {static_cast<double2*>(ws), static_cast<double2*>(ws) + d};
+    if (t) QC_HIP(hipMemcpyAsync(t, psi, size_t(d) * 16, hipMemcpyDeviceToDevice, st));
+    const double2* cur = psi;
+    for (int64_t n = 0; n < M; ++n) {
+      double2* nxt = t ? t + (n + 1) * d : buf[n & 1];
+      hipLaunchKernelGGL(matvec_kernel<C2>, dim3(nblocks(d, 4)), dim3(256), 0, st, U + n * dd, cur, nxt, int(d));
+      QC_HIP(hipGetLastError());
+      cur = nxt;
+    }
+    if (M > 0) QC_HIP(hipMemcpyAsync(psi, cur, size_t(d) * 16, hipMemcpyDeviceToDevice, st));
+    return QCHEFF_OK;
+  }
+  // PRODUCT: binary tree, out[i] = in[2i+1] in[2i]; an odd last matrix is carried.
+  C2* P = static_cast<C2*>(x);
+  if (M == 0) {
+    // identity: a K = 0 product with gamma = 1 writes every element
+    auto p = gemm_params<T>(int(d), int(d), 0, 1);
+    p.C = P; p.ldc = d; p.sC = 0; p.alpha = T(0); p.gamma = T(1);
+    p.A = P; p.B = P; p.lda = d; p.ldb = d;
+    QC_HIP((launch_cgemm<T>(p, st)));
+    return QCHEFF_OK;
+  }
+  const size_t mat = align256(size_t(dd) * sizeof(C2));
+  C2* bufs[2] = {static_cast<C2*>(ws), reinterpret_cast<C2*>(static_cast<char*>(ws) + size_t((M + 1) / 2) * mat)};
+  const int64_t ldm = int64_t(mat / sizeof(C2));  // matrix stride inside the tree buffers
+  const C2* in = U;
+  int64_t in_stride = dd, cnt = M;
+  int which = 0;
+  while (cnt > 1) {
+    C2* out = bufs[which];
+    const int64_t pairs = cnt / 2;
+    auto p = gemm_params<T>(int(d), int(d), int(d), int(pairs));
+    p.A = in + in_stride; p.lda = d; p.sA = 2 * in_stride;
+    p.B = in; p.ldb = d; p.sB = 2 * in_stride;
+    p.C = out; p.ldc = d; p.sC = ldm;
+    QC_HIP((launch_cgemm<T>(p, st)));
+    if (cnt & 1)
+      QC_HIP(hipMemcpyAsync(out + pairs * ldm, in + (cnt - 1) * in_stride, size_t(dd) * sizeof(C2),
+                            hipMemcpyDeviceToDevice, st));
+    in = out;
+    in_stride = ldm;
+    cnt = pairs + (cnt & 1);
+    which ^= 1;
+  }
+  QC_HIP(hipMemcpyAsync(P, in, size_t(dd) * sizeof(C2), hipMemcpyDeviceToDevice, st));
+  return QCHEFF_OK;
+}
+
+}  // namespace
+}  // namespace qcheff
+
+using namespace qcheff;
+
+extern "C" {
+
+int qcheff_magnus_coeffs(const double* u, int64_t K, int64_t N, double dt_sample, int64_t M, int order, double* c1,
+                         double* c2, void* stream) {
+  Check c = check_coeffs(u, K, N, dt_sample, M, order, c1, c2);
+  if (c.status) return fail(c);
+  return run_coeffs(u, K, N, dt_sample, M, order, c1, c2, static_cast<hipStream_t>(stream));
+}
+
+int qcheff_magnus_generators(const void* H0, const void* Hk, int64_t d, int64_t K, int op_dtype, const double* c1,
+                             const double* c2, int64_t M, double dt_interval, int order, int out_dtype, void* omega,
+                             void* ws, size_t ws_bytes, unsigned flags, void* stream) {
+  Check c = check_generators(H0, Hk, d, K, op_dtype, c1, c2, M, dt_interval, order, out_dtype, omega, ws, ws_bytes,
+                             flags);
+  if (c.status) return fail(c);
+  return run_generators(static_cast<const double2*>(H0), static_cast<const double2*>(Hk), d, K, c1, c2, M,
+                        dt_interval, order, out_dtype, omega, ws, flags, static_cast<hipStream_t>(stream));
+}
+
+int qcheff_expm_batched(const void* omega, int64_t batch, int64_t d, int dtype, void* U, int32_t* s_out, void* ws,
+                        size_t ws_bytes, void* stream) {
+  Check c = check_expm(omega, batch, d, dtype, U, ws, ws_bytes);
+  if (c.status) return fail(c);
+  if (batch == 0) return QCHEFF_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return dtype == QCHEFF_C128 ? run_expm<double>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, st)
+                              : run_expm<float>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, st);
+}
+
+int qcheff_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, void* x, void* traj, void* ws,
+                     size_t ws_bytes, void* stream) {
+  Check c = check_propagate(U, M, d, dtype, mode, x, traj, ws, ws_bytes);
+  if (c.status) return fail(c);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return dtype == QCHEFF_C128 ? run_propagate<double>(U, M, d, mode, x, traj, ws, st)
+                              : run_propagate<float>(U, M, d, mode, x, traj, ws, st);
+}
+
+size_t qcheff_workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int order, int dtype) {
+  return workspace_bytes(fn, batch, d, K, order, dtype);
+}
+
+const char* qcheff_last_error(void) { return g_last_error.c_str(); }
+
+int qcheff_timing_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  for (auto& t : g_timed) {
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  g_timed.clear();
+  g_timing.store(on ? 1 : 0);
+  return QCHEFF_OK;
+}
+
+int qcheff_timing_read(int kernel, int64_t* launches, double* total_ms, double* flops, double* bytes) {
+  if (!launches || !total_ms || !flops || !bytes) return fail(QCHEFF_EINVAL, "NULL output pointer");
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  int64_t n = 0;
+  double ms = 0.0, fl = 0.0, by = 0.0;
+  std::vector<TimedLaunch> keep;
+  for (auto& t : g_timed) {
+    if (t.kernel != kernel) {
+      keep.push_back(t);
+      continue;
+    }
+    float e = 0.f;
+    if (hipEventSynchronize(t.b) != hipSuccess || hipEventElapsedTime(&e, t.a, t.b) != hipSuccess)
+      return fail(QCHEFF_EDEVICE, "reading a timing event failed");
+    ms += e;
+    fl += t.flops;
+    by += t.bytes;
+    ++n;
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  g_timed.swap(keep);
+  *launches = n;
+  *total_ms = ms;
+  *flops = fl;
+  *bytes = by;
+  return QCHEFF_OK;
+}
+
+}  // extern "C"

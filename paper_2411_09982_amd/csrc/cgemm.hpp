@@ -1,0 +1,239 @@
+// Batched complex GEMM on MFMA (gfx950), FP32 or FP64, interleaved complex storage.
+//
+//   C_b = alpha * A_b B_b + beta * C_b + sum_i xc[i] X_{i,b} + gamma * I      (EPI_STD)
+//   aug_b[:, :N] = V_b - A_b B_b,  aug_b[:, off:off+N] = V_b + A_b B_b (FP64)  (EPI_AUG)
+//
+// A complex product is four real MFMA products on planar operands:
+//   Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br.
+// A workgroup of four waves owns a BM x BN tile of C; each wave a WM x WN
+// sub-tile built from 16x16x4 MFMA instructions.  K advances BK at a time
+// through double-buffered LDS; the next tile is fetched into registers while
+// the current one is consumed.  Any M, N, K, leading dimension and offset is
+// accepted: out-of-range loads read zero and out-of-range stores are skipped.
+#pragma once
+
+#include "common.hpp"
+
+namespace qcheff {
+
+enum { EPI_STD = 0, EPI_AUG = 1 };
+
+// Kernel ids of the timing instrumentation (match QCHEFF_KERNEL_* in qcheff.h).
+enum { KERNEL_GEMM_F32 = 1, KERNEL_GEMM_F64 = 2 };
+
+// Records a HIP event pair around a launch while timing is enabled.
+struct LaunchTimer {
+  hipEvent_t a = nullptr, b = nullptr;
+  bool on = false;
+  void begin(hipStream_t st);
+  void end(hipStream_t st, int kernel, double flops, double bytes);
+};
+
+template <typename T> struct GemmParams {
+  using C2 = typename Cx<T>::t;
+  int M, N, K, batch;
+  int tiles_m, tiles_n;
+  const C2* A; int64_t lda, sA;
+  const C2* B; int64_t ldb, sB;
+  C2* C; int64_t ldc, sC;
+  T alpha, beta, gamma;
+  int epi;                      // EPI_STD or EPI_AUG
+  int sq;                       // 1: squaring mode (sq_* fields)
+  int nx;                       // number of X terms (0..3); X share C's ld and stride
+  const C2* X[3]; T xc[3];
+  // EPI_AUG target (FP64 always)
+  double2* aug; int64_t ld_aug, s_aug, aug_off;
+  // squaring mode: A = B = in, C = out, chosen per item from the remaining count
+  const int* sq_s; int sq_step; C2* sq_p0; C2* sq_p1;
+};
+
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(256) void cgemm_kernel(GemmParams<T> p) {
+  using C2 = typename Cx<T>::t;
+  using Acc = typename Cx<T>::acc;
+  constexpr int WAVES_N = BN / WN;
+  static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int LA = BM * BK / 256, LB = BK * BN / 256;
+  static_assert(LA * 256 == BM * BK && LB * 256 == BK * BN, "tile loads must divide evenly");
+
+  __shared__ C2 As[2][BK][BM + 1];
+  __shared__ C2 Bs[2][BK][BN];
+
+  const int tiles = p.tiles_m * p.tiles_n;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = bid / tiles;
+  if (b >= p.batch) return;
+  const int t = bid - b * tiles;
+  const int row0 = (t / p.tiles_n) * BM;
+  const int col0 = (t % p.tiles_n) * BN;
+
+  const C2* A;
+  const C2* B;
+  C2* C;
+  if (p.sq) {
+    const int s = p.sq_s[b];
+    if (s <= p.sq_step) return;              // this item needs no more squarings
+    const int rem = s - p.sq_step;           // squarings left, this one included
+    C2* in = (rem % 2 == 0) ? p.sq_p0 : p.sq_p1;
+    C2* out = (rem % 2 == 0) ? p.sq_p1 : p.sq_p0;
+    A = in + b * p.sA;
+    B = in + b * p.sB;
+    C = out + b * p.sC;
+  } else {
+    A = p.A + b * p.sA;
+    B = p.B + b * p.sB;
+    C = p.C + b * p.sC;
+  }
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
+
+  Acc accr[TM][TN], acci[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) { accr[i][j][e] = T(0); acci[i][j][e] = T(0); }
+
+  C2 ra[LA], rb[LB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int e = tid + 256 * q, r = e / BK, k = e % BK;
+      const int gr = row0 + r, gk = k0 + k;
+      ra[q] = (gr < p.M && gk < p.K) ? A[int64_t(gr) * p.lda + gk] : czero<C2>();
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int e = tid + 256 * q, k = e / BN, c = e % BN;
+      const int gk = k0 + k, gc = col0 + c;
+      rb[q] = (gk < p.K && gc < p.N) ? B[int64_t(gk) * p.ldb + gc] : czero<C2>();
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int e = tid + 256 * q;
+      As[buf][e % BK][e / BK] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int e = tid + 256 * q;
+      Bs[buf][e / BN][e % BN] = rb[q];
+    }
+  };
+
+  const int nk = (p.K + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  const int lr = lane >> 4, lc = lane & 15;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      C2 a[TM], bb[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = As[cur][kk + lr][wm + i * 16 + lc];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bb[j] = Bs[cur][kk + lr][wn + j * 16 + lc];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const T ar = a[i].x, ai = a[i].y, nai = -a[i].y;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          accr[i][j] = mfma16(ar, bb[j].x, accr[i][j]);
+          accr[i][j] = mfma16(nai, bb[j].y, accr[i][j]);
+          acci[i][j] = mfma16(ar, bb[j].y, acci[i][j]);
+          acci[i][j] = mfma16(ai, bb[j].x, acci[i][j]);
+        }
+      }
+    }
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int c = col0 + wn + j * 16 + lc;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = row0 + wm + i * 16 + acc_row<T>(lane, e);
+        if (r >= p.M || c >= p.N) continue;
+        const int64_t off = int64_t(r) * p.ldc + c;
+        if (p.epi == EPI_AUG) {
+          const C2 v = p.X[0][b * p.sC + off];
+          const double pr = double(accr[i][j][e]), pi = double(acci[i][j][e]);
+          double2* out = p.aug + b * p.s_aug + int64_t(r) * p.ld_aug + c;
+          out[0] = make_double2(double(v.x) - pr, double(v.y) - pi);
+          out[p.aug_off] = make_double2(double(v.x) + pr, double(v.y) + pi);
+        } else {
+          T vr = p.alpha * accr[i][j][e], vi = p.alpha * acci[i][j][e];
+          if (p.beta != T(0)) {
+            const C2 old = C[off];
+            vr += p.beta * old.x;
+            vi += p.beta * old.y;
+          }
+          for (int x = 0; x < p.nx; ++x) {
+            const C2 xv = p.X[x][b * p.sC + off];
+            vr += p.xc[x] * xv.x;
+            vi += p.xc[x] * xv.y;
+          }
+          if (r == c) vr += p.gamma;
+          C2 o;
+          o.x = vr;
+          o.y = vi;
+          C[off] = o;
+        }
+      }
+    }
+  }
+}
+
+// Tile shapes per precision.
+template <typename T> struct GemmTile;
+template <> struct GemmTile<float> { static constexpr int BM = 128, BN = 128, BK = 16, WM = 64, WN = 64; };
+template <> struct GemmTile<double> { static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32; };
+
+template <typename T> GemmParams<T> gemm_params(int M, int N, int K, int batch) {
+  GemmParams<T> p{};
+  p.M = M; p.N = N; p.K = K; p.batch = batch;
+  p.tiles_m = (M + GemmTile<T>::BM - 1) / GemmTile<T>::BM;
+  p.tiles_n = (N + GemmTile<T>::BN - 1) / GemmTile<T>::BN;
+  p.alpha = T(1); p.beta = T(0); p.gamma = T(0); p.nx = 0;
+  return p;
+}
+
+// Launch; `active` is the number of items that do work (squaring mode skips
+// the others) and feeds the timing record's algorithmic flop and byte counts.
+template <typename T>
+hipError_t launch_cgemm(const GemmParams<T>& p, hipStream_t stream, int64_t active = -1) {
+  using G = GemmTile<T>;
+  if (p.M <= 0 || p.N <= 0 || p.batch <= 0) return hipSuccess;
+  const int64_t blocks = int64_t(p.tiles_m) * p.tiles_n * p.batch;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (active < 0) active = p.batch;
+  LaunchTimer tm;
+  tm.begin(stream);
+  hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN>), dim3(unsigned(blocks)), dim3(256), 0,
+                     stream, p);
+  const hipError_t e = hipGetLastError();
+  if (tm.on) {
+    const double mn = double(p.M) * p.N, es = double(sizeof(typename Cx<T>::t));
+    const double flops = 8.0 * mn * double(p.K) * double(active);
+    double elems = double(p.M) * p.K + double(p.K) * p.N + mn * (1 + p.nx + (p.beta != T(0) ? 1 : 0));
+    double bytes = elems * es;
+    if (p.epi == EPI_AUG) bytes += mn * 32.0;  // V is the generic M N term; two FP64 halves are written
+    tm.end(stream, sizeof(T) == 4 ? KERNEL_GEMM_F32 : KERNEL_GEMM_F64, flops, bytes * double(active));
+  }
+  return e;
+}
+
+}  // namespace qcheff

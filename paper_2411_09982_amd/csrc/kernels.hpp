@@ -1,0 +1,421 @@
+// Device kernels of the Magnus path other than the GEMM (gfx950).
+#pragma once
+
+#include "common.hpp"
+
+namespace qcheff {
+
+// ---------------------------------------------------------------- helpers
+
+// Neumaier's compensated summation (Neumaier 1974): running sum plus a
+// correction term that collects the rounding error of every addition.
+struct Neumaier {
+  double s = 0.0, c = 0.0;
+  __device__ __forceinline__ void add(double x) {
+    const double t = s + x;
+    c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  __device__ __forceinline__ double value() const { return s + c; }
+};
+
+template <typename C2> __device__ __forceinline__ C2 to_c2(double re, double im);
+template <> __device__ __forceinline__ float2 to_c2<float2>(double re, double im) {
+  return make_float2(float(re), float(im));
+}
+template <> __device__ __forceinline__ double2 to_c2<double2>(double re, double im) {
+  return make_double2(re, im);
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------ coefficients
+//
+// One thread per interval n; the interval's s samples are read in order.
+//   c1[n][k]    = dt * sum_j u_k[j]
+//   c2[n][k]    = dt^2 * sum_j (s - 1 - 2j) u_k[j]
+//   c2[n][K+p]  = dt^2 * sum_j (u_k[j] P_l[j] - u_l[j] P_k[j]),  P[j] = sum_{i<j} u[i]
+__global__ void coeffs_kernel(const double* __restrict__ u, int K, int64_t N, int64_t M, int64_t s,
+                              double dt, int order, double* __restrict__ c1, double* __restrict__ c2) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= M) return;
+  const int64_t base = n * s;
+  const int P2 = K + K * (K - 1) / 2;
+  for (int k = 0; k < K; ++k) {
+    const double* uk = u + int64_t(k) * N + base;
+    Neumaier sum, wsum;
+    for (int64_t j = 0; j < s; ++j) {
+      const double x = uk[j];
+      sum.add(x);
+      if (order == 2) wsum.add(double(s - 1 - 2 * j) * x);
+    }
+    c1[n * K + k] = dt * sum.value();
+    if (order == 2) c2[n * P2 + k] = dt * dt * wsum.value();
+  }
+  if (order != 2) return;
+  int p = K;
+  for (int k = 0; k < K; ++k) {
+    for (int l = k + 1; l < K; ++l, ++p) {
+      const double* uk = u + int64_t(k) * N + base;
+      const double* ul = u + int64_t(l) * N + base;
+      Neumaier acc, Pk, Pl;
+      for (int64_t j = 0; j < s; ++j) {
+        const double xk = uk[j], xl = ul[j];
+        acc.add(xk * Pl.value());
+        acc.add(-(xl * Pk.value()));
+        Pk.add(xk);
+        Pl.add(xl);
+      }
+      c2[n * P2 + p] = dt * dt * acc.value();
+    }
+  }
+}
+
+// ------------------------------------------------------ commutator basis
+//
+// In place: C <- X - X^dag for a square d x d matrix (X = F G for Hermitian F,
+// G gives [F, G] = F G - (F G)^dag, exactly anti-Hermitian).
+__global__ void antihermitian_part_kernel(double2* X, int d) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= int64_t(d) * d) return;
+  const int i = int(e / d), j = int(e % d);
+  if (i > j) return;
+  const double2 a = X[int64_t(i) * d + j];
+  if (i == j) {
+    X[e] = make_double2(0.0, 2.0 * a.y);
+    return;
+  }
+  const double2 b = X[int64_t(j) * d + i];
+  const double2 cij = make_double2(a.x - b.x, a.y + b.y);  // a - conj(b)
+  X[int64_t(i) * d + j] = cij;
+  X[int64_t(j) * d + i] = make_double2(-cij.x, cij.y);     // -conj(cij)
+}
+
+// ------------------------------------------------------------- generators
+//
+// Omega_n[e] = -i ( dt H0[e] + sum_k c1[n][k] H_k[e] - (i/2) sum_p c2[n][p] C_p[e] )
+// One thread per matrix element e holds the operator values in registers and
+// walks a chunk of intervals; coefficients of the chunk sit in LDS.
+template <int K, int ORDER, typename OutC2>
+__global__ __launch_bounds__(256) void generators_kernel(const double2* __restrict__ H0,
+                                                         const double2* __restrict__ Hk,
+                                                         const double2* __restrict__ Cb, int64_t dd,
+                                                         const double* __restrict__ c1,
+                                                         const double* __restrict__ c2, int64_t M,
+                                                         int nch, double dt, OutC2* __restrict__ omega) {
+  constexpr int P2 = (ORDER == 2) ? K + K * (K - 1) / 2 : 0;
+  constexpr int NC = K + P2;
+  extern __shared__ double sh[];  // [nch][NC]
+  const int64_t n0 = int64_t(blockIdx.y) * nch;
+  const int cnt = int(min(int64_t(nch), M - n0));
+  for (int i = threadIdx.x; i < cnt * NC; i += blockDim.x) {
+    const int r = i / NC, q = i % NC;
+    sh[i] = (q < K) ? c1[(n0 + r) * K + q] : c2[(n0 + r) * P2 + (q - K)];
+  }
+  __syncthreads();
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= dd) return;
+  const double2 h0 = H0[e];
+  double2 hk[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) hk[k] = Hk[int64_t(k) * dd + e];
+  double2 cb[P2 > 0 ? P2 : 1];
+#pragma unroll
+  for (int q = 0; q < P2; ++q) cb[q] = Cb[int64_t(q) * dd + e];
+  for (int r = 0; r < cnt; ++r) {
+    const double* cf = sh + r * NC;
+    double hr = dt * h0.x, hi = dt * h0.y;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      hr += cf[k] * hk[k].x;
+      hi += cf[k] * hk[k].y;
+    }
+    if constexpr (ORDER == 2) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int q = 0; q < P2; ++q) {
+        sr += cf[K + q] * cb[q].x;
+        si += cf[K + q] * cb[q].y;
+      }
+      hr += 0.5 * si;   // -(i/2) (sr + i si) = si/2 - i sr/2
+      hi -= 0.5 * sr;
+    }
+    omega[(n0 + r) * dd + e] = to_c2<OutC2>(hi, -hr);  // -i (hr + i hi)
+  }
+}
+
+// ------------------------------------------------------ norm and scaling
+//
+// Column sums of |Omega| in FP64 (one thread per column), maximum per item
+// by an atomic max on the IEEE bit pattern (monotone for non-negative values).
+template <typename C2>
+__global__ __launch_bounds__(256) void norm1_kernel(const C2* __restrict__ X, int d,
+                                                    unsigned long long* __restrict__ norms) {
+  const int b = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  double sum = 0.0;
+  if (j < d) {
+    const C2* col = X + int64_t(b) * d * d + j;
+    for (int i = 0; i < d; ++i) {
+      const C2 v = col[int64_t(i) * d];
+      sum += sqrt(double(v.x) * double(v.x) + double(v.y) * double(v.y));
+    }
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = sum;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double o = red[threadIdx.x + w];
+      // propagate NaN: a comparison with NaN is false, so test it explicitly
+      if (o > red[threadIdx.x] || o != o) red[threadIdx.x] = o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(norms + b, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+// s = smallest s >= 0 with nrm <= theta * 2^s (exact comparisons); -1 if nrm is not finite.
+__device__ __forceinline__ int squarings_for(double nrm, double theta) {
+  if (!(nrm <= 1.7976931348623157e308)) return -1;
+  int s = 0;
+  while (nrm > ldexp(theta, s)) ++s;
+  return s;
+}
+
+// A = Omega / 2^s per item (exact); records s.
+template <typename C2>
+__global__ __launch_bounds__(256) void scale_kernel(const C2* __restrict__ omega, C2* __restrict__ A,
+                                                    int64_t dd, const unsigned long long* __restrict__ norms,
+                                                    double theta, int* __restrict__ s_ws,
+                                                    int* __restrict__ s_out, int* __restrict__ smax) {
+  const int b = blockIdx.y;
+  const double nrm = __longlong_as_double((long long)norms[b]);
+  const int s = squarings_for(nrm, theta);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s_ws[b] = s;
+    if (s_out) s_out[b] = s;
+    atomicMax(smax, s);
+  }
+  const double f = (s >= 0) ? ldexp(1.0, -s) : __longlong_as_double(0x7ff8000000000000LL);
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < dd; e += int64_t(gridDim.x) * blockDim.x) {
+    const C2 v = omega[b * dd + e];
+    C2 o;
+    o.x = v.x * f;
+    o.y = v.y * f;
+    A[b * dd + e] = o;
+  }
+}
+
+// Y = a X3 + b X2 + c X1, elementwise over n complex numbers.
+template <typename T>
+__global__ void lincomb3_kernel(typename Cx<T>::t* __restrict__ Y, const typename Cx<T>::t* __restrict__ X3,
+                                const typename Cx<T>::t* __restrict__ X2,
+                                const typename Cx<T>::t* __restrict__ X1, int64_t n, T a, T bb, T c) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const auto x3 = X3[i], x2 = X2[i], x1 = X1[i];
+  typename Cx<T>::t y;
+  y.x = a * x3.x + bb * x2.x + c * x1.x;
+  y.y = a * x3.y + bb * x2.y + c * x1.y;
+  Y[i] = y;
+}
+
+// ------------------------------------------------- batched LU (FP64 complex)
+//
+// The augmented system [q | p] (d x 2d, row-major, ld = 2d) is reduced by
+// right-looking blocked LU with partial pivoting: panel factorization
+// (one workgroup per item), row interchanges and the unit-lower solve for the
+// block row (one thread per column), then the trailing update on MFMA.  The
+// back substitution with U runs block by block from the bottom.
+
+constexpr int kNb = 32;
+
+__device__ __forceinline__ double2 crecip(double2 a) {
+  const double den = a.x * a.x + a.y * a.y;
+  return make_double2(a.x / den, -a.y / den);
+}
+
+__global__ __launch_bounds__(256) void lu_panel_kernel(double2* aug, int64_t ld, int64_t stride, int d,
+                                                       int k0, int k1, int* piv_all) {
+  const int b = blockIdx.x;
+  double2* A = aug + b * stride;
+  int* piv = piv_all + int64_t(b) * d;
+  const int tid = threadIdx.x;
+  __shared__ double smax[256];
+  __shared__ int sidx[256];
+  __shared__ double2 prow[kNb];
+  for (int j = k0; j < k1; ++j) {
+    double best = -1.0;
+    int bi = j;
+    for (int i = j + tid; i < d; i += 256) {
+      const double2 v = A[int64_t(i) * ld + j];
+      const double m = fabs(v.x) + fabs(v.y);
+      if (m > best) { best = m; bi = i; }
+    }
+    smax[tid] = best;
+    sidx[tid] = bi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) {
+        const double o = smax[tid + w];
+        const int oi = sidx[tid + w];
+        if (o > smax[tid] || (o == smax[tid] && oi < sidx[tid])) { smax[tid] = o; sidx[tid] = oi; }
+      }
+      __syncthreads();
+    }
+    const int pr = sidx[0];
+    if (tid == 0) piv[j] = pr;
+    if (pr != j) {
+      for (int c = k0 + tid; c < k1; c += 256) {
+        const double2 t = A[int64_t(j) * ld + c];
+        A[int64_t(j) * ld + c] = A[int64_t(pr) * ld + c];
+        A[int64_t(pr) * ld + c] = t;
+      }
+    }
+    __syncthreads();
+    if (tid < k1 - j) prow[tid] = A[int64_t(j) * ld + j + tid];
+    __syncthreads();
+    const double2 inv = crecip(prow[0]);
+    for (int i = j + 1 + tid; i < d; i += 256) {
+      double2* row = A + int64_t(i) * ld;
+      const double2 l = cmul(row[j], inv);
+      row[j] = l;
+      for (int c = 1; c < k1 - j; ++c) {
+        const double2 t = cmul(l, prow[c]);
+        row[j + c].x -= t.x;
+        row[j + c].y -= t.y;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Row interchanges of the panel applied to columns [k1, ncols), then the block
+// row U12 = L11^{-1} A12 (unit lower triangular solve), one thread per column.
+__global__ __launch_bounds__(256) void lu_swap_trsm_kernel(double2* aug, int64_t ld, int64_t stride, int d,
+                                                           int ncols, int k0, int k1, const int* piv_all) {
+  const int b = blockIdx.y;
+  double2* A = aug + b * stride;
+  const int* piv = piv_all + int64_t(b) * d;
+  const int nb = k1 - k0;
+  __shared__ double2 L[kNb][kNb + 1];
+  __shared__ int sp[kNb];
+  for (int e = threadIdx.x; e < nb * nb; e += 256) {
+    const int i = e / nb, j = e % nb;
+    L[i][j] = A[int64_t(k0 + i) * ld + k0 + j];
+  }
+  if (threadIdx.x < nb) sp[threadIdx.x] = piv[k0 + threadIdx.x];
+  __syncthreads();
+  const int c = k1 + blockIdx.x * 256 + threadIdx.x;
+  if (c >= ncols) return;
+  for (int j = 0; j < nb; ++j) {
+    const int pr = sp[j];
+    if (pr != k0 + j) {
+      const double2 t = A[int64_t(k0 + j) * ld + c];
+      A[int64_t(k0 + j) * ld + c] = A[int64_t(pr) * ld + c];
+      A[int64_t(pr) * ld + c] = t;
+    }
+  }
+  double2 x[kNb];
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) x[j] = (j < nb) ? A[int64_t(k0 + j) * ld + c] : make_double2(0.0, 0.0);
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) {
+#pragma unroll
+    for (int i = j + 1; i < kNb; ++i) {
+      if (i < nb) {
+        const double2 t = cmul(L[i][j], x[j]);
+        x[i].x -= t.x;
+        x[i].y -= t.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kNb; ++j)
+    if (j < nb) A[int64_t(k0 + j) * ld + c] = x[j];
+}
+
+// Back substitution for rows [k0, k1) of the right-hand side (columns [d, 2d)):
+// X_k = U_kk^{-1} Y_k, one thread per column.
+__global__ __launch_bounds__(256) void lu_backsub_kernel(double2* aug, int64_t ld, int64_t stride, int d,
+                                                         int k0, int k1) {
+  const int b = blockIdx.y;
+  double2* A = aug + b * stride;
+  const int nb = k1 - k0;
+  __shared__ double2 Ub[kNb][kNb + 1];
+  for (int e = threadIdx.x; e < nb * nb; e += 256) {
+    const int i = e / nb, j = e % nb;
+    Ub[i][j] = (j >= i) ? A[int64_t(k0 + i) * ld + k0 + j] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int c = d + blockIdx.x * 256 + threadIdx.x;
+  if (c >= 2 * d) return;
+  double2 x[kNb];
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) x[j] = (j < nb) ? A[int64_t(k0 + j) * ld + c] : make_double2(0.0, 0.0);
+#pragma unroll
+  for (int i = kNb - 1; i >= 0; --i) {
+    if (i < nb) {
+      double2 v = x[i];
+#pragma unroll
+      for (int j = i + 1; j < kNb; ++j) {
+        if (j < nb) {
+          const double2 t = cmul(Ub[i][j], x[j]);
+          v.x -= t.x;
+          v.y -= t.y;
+        }
+      }
+      x[i] = cmul(v, crecip(Ub[i][i]));
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kNb; ++j)
+    if (j < nb) A[int64_t(k0 + j) * ld + c] = x[j];
+}
+
+// R = aug[:, d:2d] written (cast) to the buffer where the squarings must start
+// so that the last one lands in U: U if s is even (or no squaring), else P1.
+template <typename C2>
+__global__ __launch_bounds__(256) void place_result_kernel(const double2* __restrict__ aug, int d,
+                                                           const int* __restrict__ s_ws, C2* U, C2* P1) {
+  const int b = blockIdx.y;
+  const int64_t dd = int64_t(d) * d;
+  const int s = s_ws[b];
+  C2* dst = ((s > 0 && (s & 1)) ? P1 : U) + b * dd;
+  const double2* src = aug + b * 2 * dd;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < dd; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = e / d, j = e % d;
+    const double2 v = src[i * 2 * d + d + j];
+    dst[e] = to_c2<C2>(v.x, v.y);
+  }
+}
+
+// ---------------------------------------------------------------- chain
+//
+// y = U x with U in C2 (FP32 or FP64) and x, y in FP64; one wave per row.
+template <typename C2>
+__global__ __launch_bounds__(256) void matvec_kernel(const C2* __restrict__ U, const double2* __restrict__ x,
+                                                     double2* __restrict__ y, int d) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + wave;
+  if (row >= d) return;
+  const C2* ur = U + int64_t(row) * d;
+  double ar = 0.0, ai = 0.0;
+  for (int c = lane; c < d; c += 64) {
+    const C2 u = ur[c];
+    const double2 v = x[c];
+    ar += double(u.x) * v.x - double(u.y) * v.y;
+    ai += double(u.x) * v.y + double(u.y) * v.x;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    ar += __shfl_down(ar, off);
+    ai += __shfl_down(ai, off);
+  }
+  if (lane == 0) y[row] = make_double2(ar, ai);
+}
+
+}  // namespace qcheff

@@ -1,0 +1,141 @@
+// Host-side argument checks and workspace sizes (see validate.hpp).
+#include "validate.hpp"
+
+#include <cmath>
+
+#include "../../include/qcheff.h"
+
+namespace qcheff {
+
+size_t elem_bytes(int dtype) {
+  return dtype == QCHEFF_C128 ? 16 : dtype == QCHEFF_C64 ? 8 : 0;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+Check check_coeffs(const void* u, int64_t K, int64_t N, double dt_sample, int64_t M, int order,
+                   const void* c1, const void* c2) {
+  if (order != 1 && order != 2) return Check::fail(QCHEFF_EINVAL, "order must be 1 or 2");
+  if (K < 1) return Check::fail(QCHEFF_EINVAL, "K must be >= 1");
+  if (N < 1 || M < 1) return Check::fail(QCHEFF_EINVAL, "N and M must be >= 1");
+  if (N % M != 0) return Check::fail(QCHEFF_EINVAL, "N must be a multiple of M");
+  if (!finite_pos(dt_sample)) return Check::fail(QCHEFF_EINVAL, "dt_sample must be finite and > 0");
+  if (!u || !c1) return Check::fail(QCHEFF_EINVAL, "u and c1 must not be NULL");
+  if (order == 2 && !c2) return Check::fail(QCHEFF_EINVAL, "c2 must not be NULL for order 2");
+  if (K > 4096 || N > (int64_t(1) << 40)) return Check::fail(QCHEFF_EINVAL, "K or N too large");
+  return Check::ok();
+}
+
+size_t generators_ws_bytes(int64_t d, int64_t K, int order) {
+  if (order != 2) return 0;
+  return align256(size_t(n_c2(K)) * size_t(d) * size_t(d) * 16);
+}
+
+Check check_generators(const void* H0, const void* Hk, int64_t d, int64_t K, int op_dtype,
+                       const void* c1, const void* c2, int64_t M, double dt_interval, int order,
+                       int out_dtype, const void* omega, const void* ws, size_t ws_bytes,
+                       unsigned flags) {
+  if (order != 1 && order != 2) return Check::fail(QCHEFF_EINVAL, "order must be 1 or 2");
+  if (d < 1 || d > kMaxDim) return Check::fail(QCHEFF_EINVAL, "d must be in [1, 16384]");
+  if (K < 1) return Check::fail(QCHEFF_EINVAL, "K must be >= 1");
+  if (M < 0) return Check::fail(QCHEFF_EINVAL, "M must be >= 0");
+  if (!std::isfinite(dt_interval)) return Check::fail(QCHEFF_EINVAL, "dt_interval must be finite");
+  if (flags & ~QCHEFF_REUSE_BASIS) return Check::fail(QCHEFF_EINVAL, "unknown flag bits");
+  if (elem_bytes(op_dtype) == 0 || elem_bytes(out_dtype) == 0)
+    return Check::fail(QCHEFF_EINVAL, "unknown dtype");
+  if (op_dtype != QCHEFF_C128) return Check::fail(QCHEFF_EUNSUPPORTED, "operators must be QCHEFF_C128");
+  if (K > kMaxControls) return Check::fail(QCHEFF_EUNSUPPORTED, "at most 8 controls");
+  if (!H0 || !Hk) return Check::fail(QCHEFF_EINVAL, "H0 and Hk must not be NULL");
+  if (M > 0 && (!c1 || !omega)) return Check::fail(QCHEFF_EINVAL, "c1 and omega must not be NULL");
+  if (order == 2 && M > 0 && !c2) return Check::fail(QCHEFF_EINVAL, "c2 must not be NULL for order 2");
+  if (order == 2) {
+    if (!ws) return Check::fail(QCHEFF_EWORKSPACE, "order 2 needs a workspace for the commutator basis");
+    if (ws_bytes < generators_ws_bytes(d, K, order))
+      return Check::fail(QCHEFF_EWORKSPACE, "workspace too small for the commutator basis");
+  }
+  return Check::ok();
+}
+
+// expm workspace, per item: seven d x d matrices in dtype (A, A^2, A^4, A^6, two
+// polynomial terms, V), one d x 2d augmented system in C128, d pivots (int32).
+// Header: per-item FP64 norm slot, int32 squaring count.
+size_t expm_item_bytes(int64_t d, int dtype) {
+  size_t dd = size_t(d) * size_t(d);
+  return 7 * align256(dd * elem_bytes(dtype)) + align256(2 * dd * 16) + align256(size_t(d) * 4);
+}
+
+size_t expm_header_bytes(int64_t batch) {
+  return align256(size_t(batch) * 8) + align256(size_t(batch) * 4) + 256;
+}
+
+size_t expm_ws_bytes(int64_t batch, int64_t d, int dtype) {
+  if (batch < 1 || d < 1 || elem_bytes(dtype) == 0) return 0;
+  return expm_header_bytes(batch) + size_t(batch) * expm_item_bytes(d, dtype);
+}
+
+int64_t expm_chunk(size_t ws_bytes, int64_t batch, int64_t d, int dtype) {
+  if (batch < 1) return 0;
+  // largest c <= batch with expm_ws_bytes(c) <= ws_bytes
+  size_t item = expm_item_bytes(d, dtype);
+  int64_t c = int64_t(ws_bytes / (item ? item : 1));
+  if (c > batch) c = batch;
+  while (c > 0 && expm_ws_bytes(c, d, dtype) > ws_bytes) --c;
+  return c;
+}
+
+Check check_expm(const void* omega, int64_t batch, int64_t d, int dtype, const void* U,
+                 const void* ws, size_t ws_bytes) {
+  if (batch < 0) return Check::fail(QCHEFF_EINVAL, "batch must be >= 0");
+  if (d < 1 || d > kMaxDim) return Check::fail(QCHEFF_EINVAL, "d must be in [1, 16384]");
+  if (elem_bytes(dtype) == 0) return Check::fail(QCHEFF_EINVAL, "unknown dtype");
+  if (batch == 0) return Check::ok();
+  if (!omega || !U) return Check::fail(QCHEFF_EINVAL, "omega and U must not be NULL");
+  if (!ws) return Check::fail(QCHEFF_EWORKSPACE, "workspace must not be NULL");
+  if (expm_chunk(ws_bytes, batch, d, dtype) < 1)
+    return Check::fail(QCHEFF_EWORKSPACE, "workspace smaller than one item needs");
+  return Check::ok();
+}
+
+size_t propagate_ws_bytes(int64_t M, int64_t d, int dtype, int mode) {
+  if (M < 0 || d < 1 || elem_bytes(dtype) == 0) return 0;
+  if (mode == QCHEFF_STATE) return align256(size_t(2 * d) * 16);
+  if (mode == QCHEFF_PRODUCT) {
+    size_t mat = align256(size_t(d) * size_t(d) * elem_bytes(dtype));
+    return size_t((M + 1) / 2 + (M + 3) / 4) * mat;
+  }
+  return 0;
+}
+
+Check check_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, const void* x,
+                      const void* traj, const void* ws, size_t ws_bytes) {
+  if (mode != QCHEFF_STATE && mode != QCHEFF_PRODUCT) return Check::fail(QCHEFF_EINVAL, "unknown mode");
+  if (M < 0) return Check::fail(QCHEFF_EINVAL, "M must be >= 0");
+  if (d < 1 || d > kMaxDim) return Check::fail(QCHEFF_EINVAL, "d must be in [1, 16384]");
+  if (elem_bytes(dtype) == 0) return Check::fail(QCHEFF_EINVAL, "unknown dtype");
+  if (!x) return Check::fail(QCHEFF_EINVAL, "x must not be NULL");
+  if (M > 0 && !U) return Check::fail(QCHEFF_EINVAL, "U must not be NULL");
+  if (mode == QCHEFF_PRODUCT && traj) return Check::fail(QCHEFF_EINVAL, "traj is for QCHEFF_STATE only");
+  size_t need = propagate_ws_bytes(M, d, dtype, mode);
+  if (M > 0 && need > 0 && (!ws || ws_bytes < need))
+    return Check::fail(QCHEFF_EWORKSPACE, "workspace too small");
+  return Check::ok();
+}
+
+size_t workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int order, int dtype) {
+  if (d < 1 || d > kMaxDim) return 0;
+  switch (fn) {
+    case QCHEFF_FN_GENERATORS:
+      if (K < 1 || (order != 1 && order != 2)) return 0;
+      return generators_ws_bytes(d, K, order);
+    case QCHEFF_FN_EXPM:
+      return expm_ws_bytes(batch, d, dtype);
+    case QCHEFF_FN_PROPAGATE:
+      return propagate_ws_bytes(batch, d, dtype, order);
+    default:
+      return 0;
+  }
+}
+
+}  // namespace qcheff

@@ -1,0 +1,50 @@
+// Host-side argument checks and workspace sizes of the C ABI (include/qcheff.h).
+//
+// Plain C++ with no HIP dependency, so that it builds with g++ and is unit-tested
+// on a machine without a GPU.  Every check runs before anything is enqueued.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+namespace qcheff {
+
+constexpr int64_t kMaxDim = 16384;      // largest d accepted
+constexpr int64_t kMaxControls = 8;     // largest K accepted by the generator kernel
+constexpr int kLuBlock = 32;            // panel width of the batched LU
+
+struct Check {
+  int status = 0;        // QCHEFF_* status
+  std::string message;   // set when status != 0
+  static Check ok() { return {}; }
+  static Check fail(int st, std::string m) { return {st, std::move(m)}; }
+};
+
+inline int64_t n_pairs(int64_t K) { return K * (K - 1) / 2; }
+inline int64_t n_c2(int64_t K) { return K + n_pairs(K); }
+size_t elem_bytes(int dtype);   // 16 for C128, 8 for C64, 0 otherwise
+
+Check check_coeffs(const void* u, int64_t K, int64_t N, double dt_sample, int64_t M, int order,
+                   const void* c1, const void* c2);
+Check check_generators(const void* H0, const void* Hk, int64_t d, int64_t K, int op_dtype,
+                       const void* c1, const void* c2, int64_t M, double dt_interval, int order,
+                       int out_dtype, const void* omega, const void* ws, size_t ws_bytes,
+                       unsigned flags);
+Check check_expm(const void* omega, int64_t batch, int64_t d, int dtype, const void* U,
+                 const void* ws, size_t ws_bytes);
+Check check_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, const void* x,
+                      const void* traj, const void* ws, size_t ws_bytes);
+
+// Workspace layouts.  Each region starts on a 256-byte boundary.
+size_t align256(size_t n);
+size_t generators_ws_bytes(int64_t d, int64_t K, int order);
+// expm: per-item bytes and the fixed header
+size_t expm_item_bytes(int64_t d, int dtype);
+size_t expm_header_bytes(int64_t batch);
+size_t expm_ws_bytes(int64_t batch, int64_t d, int dtype);
+int64_t expm_chunk(size_t ws_bytes, int64_t batch, int64_t d, int dtype);  // items per chunk, 0 if none fit
+size_t propagate_ws_bytes(int64_t M, int64_t d, int dtype, int mode);
+size_t workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int order, int dtype);
+
+}  // namespace qcheff

@@ -1,0 +1,100 @@
+"""C-ABI checks that need no GPU: the library loads, exports what the header
+declares, rejects bad arguments before launching anything, and sizes its
+workspaces as documented."""
+import ctypes
+
+import pytest
+
+import paper_2411_09982_amd as q
+
+pytestmark = pytest.mark.skipif(not __import__("os").path.exists(q.LIB_PATH),
+                                reason="libqcheff_magnus.so not built")
+
+
+def test_exports_every_header_symbol():
+    names = q.header_symbols()
+    assert set(names) == {"qcheff_magnus_coeffs", "qcheff_magnus_generators", "qcheff_expm_batched",
+                          "qcheff_propagate", "qcheff_workspace_bytes", "qcheff_last_error"}
+    L = q.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation
+
+
+def _err():
+    return q.lib().qcheff_last_error().decode()
+
+
+def test_coeffs_validation():
+    L = q.lib()
+    assert L.qcheff_magnus_coeffs(FAKE, 1, 10, 0.1, 3, 1, FAKE, None, None) == q.EINVAL
+    assert "multiple" in _err()
+    assert L.qcheff_magnus_coeffs(FAKE, 1, 10, 0.1, 5, 3, FAKE, FAKE, None) == q.EINVAL
+    assert "order" in _err()
+    assert L.qcheff_magnus_coeffs(FAKE, 1, 10, 0.1, 5, 2, FAKE, None, None) == q.EINVAL
+    assert L.qcheff_magnus_coeffs(None, 1, 10, 0.1, 5, 1, FAKE, None, None) == q.EINVAL
+    assert L.qcheff_magnus_coeffs(FAKE, 0, 10, 0.1, 5, 1, FAKE, None, None) == q.EINVAL
+    assert L.qcheff_magnus_coeffs(FAKE, 1, 10, -0.1, 5, 1, FAKE, None, None) == q.EINVAL
+    assert L.qcheff_magnus_coeffs(FAKE, 1, 10, float("nan"), 5, 1, FAKE, None, None) == q.EINVAL
+    assert L.qcheff_magnus_coeffs(FAKE, 1, 10, 0.1, 0, 1, FAKE, None, None) == q.EINVAL
+
+
+def test_generators_validation():
+    L = q.lib()
+    g = L.qcheff_magnus_generators
+    # order 2 without workspace
+    assert g(FAKE, FAKE, 4, 1, q.C128, FAKE, FAKE, 3, 0.1, 2, q.C64, FAKE, None, 0, 0, None) == q.EWORKSPACE
+    need = q.workspace_bytes(q.FN_GENERATORS, 1, 4, 1, 2, q.C128)
+    assert need == 256  # one 4x4 complex128 commutator, rounded up to 256 B
+    assert g(FAKE, FAKE, 4, 1, q.C128, FAKE, FAKE, 3, 0.1, 2, q.C64, FAKE, FAKE, need - 1, 0, None) == q.EWORKSPACE
+    assert g(FAKE, FAKE, 4, 1, q.C64, FAKE, FAKE, 3, 0.1, 1, q.C64, FAKE, None, 0, 0, None) == q.EUNSUPPORTED
+    assert g(FAKE, FAKE, 4, 9, q.C128, FAKE, FAKE, 3, 0.1, 1, q.C64, FAKE, None, 0, 0, None) == q.EUNSUPPORTED
+    assert g(FAKE, FAKE, 4, 1, q.C128, FAKE, FAKE, 3, 0.1, 1, 7, FAKE, None, 0, 0, None) == q.EINVAL
+    assert g(FAKE, FAKE, 0, 1, q.C128, FAKE, FAKE, 3, 0.1, 1, q.C64, FAKE, None, 0, 0, None) == q.EINVAL
+    assert g(FAKE, FAKE, 4, 1, q.C128, FAKE, FAKE, 3, 0.1, 1, q.C64, FAKE, None, 0, 4, None) == q.EINVAL
+    assert g(None, FAKE, 4, 1, q.C128, FAKE, FAKE, 3, 0.1, 1, q.C64, FAKE, None, 0, 0, None) == q.EINVAL
+    assert g(FAKE, FAKE, 4, 1, q.C128, FAKE, None, 3, 0.1, 2, q.C64, FAKE, FAKE, need, 0, None) == q.EINVAL
+
+
+def test_expm_validation_and_workspace():
+    L = q.lib()
+    e = L.qcheff_expm_batched
+    assert e(FAKE, 2, 0, q.C64, FAKE, None, FAKE, 1 << 30, None) == q.EINVAL
+    assert e(FAKE, 2, 8, 5, FAKE, None, FAKE, 1 << 30, None) == q.EINVAL
+    assert e(FAKE, 2, 8, q.C64, FAKE, None, None, 0, None) == q.EWORKSPACE
+    one = q.workspace_bytes(q.FN_EXPM, 1, 8, 1, 1, q.C64)
+    two = q.workspace_bytes(q.FN_EXPM, 2, 8, 1, 1, q.C64)
+    assert 0 < one < two
+    assert e(FAKE, 2, 8, q.C64, FAKE, None, FAKE, one - 1, None) == q.EWORKSPACE
+    assert e(None, 2, 8, q.C64, FAKE, None, FAKE, one, None) == q.EINVAL
+    assert e(FAKE, -1, 8, q.C64, FAKE, None, FAKE, one, None) == q.EINVAL
+    # per item: 7 d^2 working matrices + the 2 d^2 FP64 augmented system + pivots
+    d = 1000
+    c64 = q.workspace_bytes(q.FN_EXPM, 1, d, 1, 1, q.C64)
+    c128 = q.workspace_bytes(q.FN_EXPM, 1, d, 1, 1, q.C128)
+    assert c64 >= 7 * d * d * 8 + 2 * d * d * 16 and c64 < 7 * d * d * 8 + 2 * d * d * 16 + 8192
+    assert c128 >= 7 * d * d * 16 + 2 * d * d * 16
+    assert e(FAKE, 0, 8, q.C64, FAKE, None, None, 0, None) == q.OK   # empty batch is a no-op
+
+
+def test_propagate_validation():
+    L = q.lib()
+    p = L.qcheff_propagate
+    assert p(FAKE, 3, 4, q.C64, 9, FAKE, None, FAKE, 1 << 20, None) == q.EINVAL
+    assert p(FAKE, 3, 4, q.C64, q.PRODUCT, FAKE, FAKE, FAKE, 1 << 20, None) == q.EINVAL
+    assert p(FAKE, 3, 4, q.C64, q.STATE, None, None, FAKE, 1 << 20, None) == q.EINVAL
+    assert p(FAKE, 3, 4, q.C64, q.STATE, FAKE, None, None, 0, None) == q.EWORKSPACE
+    assert q.workspace_bytes(q.FN_PROPAGATE, 3, 4, 1, q.STATE, q.C64) == 256
+    # product tree: ceil(M/2) + ceil(M/4) matrices of 256-byte-rounded size
+    assert q.workspace_bytes(q.FN_PROPAGATE, 5, 4, 1, q.PRODUCT, q.C64) == (3 + 2) * 256
+    assert q.workspace_bytes(9, 5, 4, 1, 1, q.C64) == 0
+
+
+def test_no_cpu_fallback_in_binding(monkeypatch, tmp_path):
+    # the binding refuses to run without the HIP library
+    monkeypatch.setattr(q, "_lib", None)
+    monkeypatch.setattr(q, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError):
+        q.lib()

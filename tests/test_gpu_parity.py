@@ -1,0 +1,228 @@
+"""GPU parity: every C-ABI entry point against the CPU oracle, element by element.
+
+Tolerances (written here, derived in the design doc):
+  FP64 path (QCHEFF_C128): propagator / state infidelity <= 1e-12 and
+      max-abs error <= 1e-10 per U_n;
+  FP32 path (QCHEFF_C64, FP64 norm / scaling / Pade solve): infidelity <= 1e-6;
+  coefficients: within a few ulps of the sum of absolute terms (compensated sums).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+q = pytest.importorskip("paper_2411_09982_amd")
+DEV = "cuda:0"
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+INF_TOL = {torch.complex128: 1e-12, torch.complex64: 1e-6}
+U32 = 2.0 ** -24
+
+
+def inf_tol(dtype, s):
+    """Per-propagator infidelity bound.  In FP32 every squaring doubles the
+    deviation of |eigenvalue| from 1 left by the FP32 rounding of R, and that
+    radial error enters 1 - |tr(U_ref^dag U)|^2/d^2 at first order, so the bound
+    is 1e-6 or 4 * 2^s * u32, whichever is larger."""
+    if dtype == torch.complex128:
+        return np.full(np.shape(s), INF_TOL[dtype])
+    return np.maximum(INF_TOL[dtype], 4.0 * 2.0 ** np.asarray(s, dtype=float) * U32)
+
+
+# ------------------------------------------------------------ coefficients
+
+def _coeff_bounds(u, dt, M):
+    """Sums of absolute terms per coefficient (scale for the rounding bound)."""
+    a = np.abs(u)
+    ua = oracle.interval_coefficients(a, dt, M, 1)[0]
+    K, N = u.shape
+    s = N // M
+    w = np.abs(s - 1 - 2 * np.arange(s))
+    c20 = np.stack([[dt * dt * (w * a[k, n * s:(n + 1) * s]).sum() for k in range(K)] for n in range(M)])
+    return ua, c20
+
+
+@pytest.mark.parametrize("K,N,M,order", [(1, 10_000, 100, 1), (2, 100_000, 1000, 2), (4, 91, 13, 2),
+                                         (3, 40, 40, 2), (2, 5000, 1, 2), (1, 7, 7, 1)])
+def test_coeffs_parity(K, N, M, order):
+    say(f"coeffs K={K} N={N} M={M} order={order}")
+    g = np.random.default_rng(K * 1000 + M)
+    t = np.linspace(0, 7, N)
+    u = np.stack([np.cos(3.1 * t + k) + 0.3 * g.standard_normal(N) for k in range(K)])
+    dt = 7.0 / N
+    c1o, c2o = oracle.interval_coefficients(u, dt, M, order)
+    c1, c2 = q.magnus_coeffs(gpu(u), dt, M, order)
+    torch.cuda.synchronize()
+    ua, c20a = _coeff_bounds(u, dt, M)
+    assert np.all(np.abs(host(c1) - c1o) <= 4e-16 * ua + 1e-300)
+    if order == 2:
+        c2g = host(c2)
+        assert np.all(np.abs(c2g[:, :K] - c2o[:, :K]) <= 4e-16 * c20a + 1e-300)
+        # pair terms: products with prefix sums; scale = dt^2 * s * sum|u_k| |u_l| style bound
+        s = N // M
+        for p in range(K, c2o.shape[1]):
+            scale = dt * dt * s * np.max(np.abs(u)) ** 2 * s
+            assert np.all(np.abs(c2g[:, p] - c2o[:, p]) <= 1e-14 * scale)
+
+
+# -------------------------------------------------------------- generators
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("d,K,order", [(1, 1, 2), (7, 2, 2), (33, 3, 2), (130, 2, 1), (130, 2, 2), (200, 4, 2)])
+def test_generators_parity(d, K, order, dtype):
+    say(f"generators d={d} K={K} order={order} {dtype}")
+    w = wl.random_system(d, K, 12 * 5, 12, order, config_id=d + K, drift_scale=20.0, drive_scale=3.0)
+    c1, c2 = oracle.interval_coefficients(w.u, w.dt_sample, w.M, order)
+    ref = oracle.generators(w.H0, w.Hk, c1, c2, w.dt_interval, order)
+    H0, Hk = gpu(w.H0), gpu(w.Hk)
+    om, ws = q.magnus_generators(H0, Hk, gpu(c1), gpu(c2) if order == 2 else None, w.dt_interval, order, dtype)
+    torch.cuda.synchronize()
+    err = np.abs(host(om) - ref).max()
+    scale = np.abs(ref).max()
+    tol = 1e-14 * scale * d if dtype == torch.complex128 else 1.2e-7 * scale
+    assert err <= tol, (err, tol)
+    # skew-Hermitian by construction
+    om_h = host(om)
+    assert np.abs(om_h + np.conj(np.swapaxes(om_h, 1, 2))).max() == 0.0
+    if order == 2:
+        # same operators, new signals: the cached commutator basis is reused
+        u2 = w.u[::-1].copy() * 1.7
+        c1b, c2b = oracle.interval_coefficients(u2, w.dt_sample, w.M, order)
+        ref2 = oracle.generators(w.H0, w.Hk, c1b, c2b, w.dt_interval, order)
+        om2, _ = q.magnus_generators(H0, Hk, gpu(c1b), gpu(c2b), w.dt_interval, order, dtype, ws=ws,
+                                     reuse_basis=True)
+        torch.cuda.synchronize()
+        assert np.abs(host(om2) - ref2).max() <= 2 * tol
+
+
+# ------------------------------------------------------------- exponential
+
+EXPM_DIMS = [1, 2, 3, 7, 8, 16, 33, 64, 100, 128, 257]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("d", EXPM_DIMS)
+def test_expm_parity(d, dtype):
+    say(f"expm d={d} {dtype}")
+    norms = [0.0, 0.01, 1.0, 5.3, 5.4, 20.0, 170.0, 1500.0]   # s = 0 .. 9
+    Om = wl.random_skew_hermitian_batch(len(norms), d, norms, config_id=300 + d)
+    ref = oracle.expm_skew_hermitian(Om)
+    seen = Om.astype(np.complex64).astype(np.complex128) if dtype == torch.complex64 else Om
+    s_ref = [oracle.scaling_exponent(x) for x in seen]
+    om = gpu(Om).to(dtype)
+    U, s = q.expm_batched(om)
+    torch.cuda.synchronize()
+    Ug = host(U).astype(np.complex128)
+    assert list(host(s)) == s_ref
+    inf = np.abs(oracle.propagator_infidelity(ref, Ug))
+    assert np.all(inf <= inf_tol(dtype, np.array(s_ref))), inf
+    if dtype == torch.complex128:
+        assert np.abs(Ug - ref).max() <= 1e-10
+        assert oracle.unitarity_error(Ug) <= 1e-12
+    else:
+        assert oracle.unitarity_error(Ug) <= 1e-3
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_expm_chunked_alias_and_nonfinite(dtype):
+    say(f"expm chunking {dtype}")
+    d, B = 45, 7
+    Om = wl.random_skew_hermitian_batch(B, d, np.linspace(0.5, 300, B), config_id=77)
+    om = gpu(Om).to(dtype)
+    U1, s1 = q.expm_batched(om)                        # one chunk
+    U2, s2 = q.expm_batched(om, chunk=3)               # chunks of 3, 3, 1
+    om3 = om.clone()
+    U3, s3 = q.expm_batched(om3, U=om3, chunk=2)       # in place
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U2) and torch.equal(U1, U3)
+    assert torch.equal(s1, s2) and torch.equal(s1, s3)
+    bad = om.clone()
+    bad[2, 3, 4] = float("nan")
+    U4, s4 = q.expm_batched(bad)
+    torch.cuda.synchronize()
+    assert int(s4[2]) == -1 and torch.isnan(U4[2]).all()
+    keep = [0, 1, 3, 4, 5, 6]
+    assert torch.equal(U4[keep], U1[keep])
+
+
+# -------------------------------------------------------------------- chain
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("M,d", [(0, 5), (1, 5), (2, 17), (5, 33), (17, 64), (40, 130)])
+def test_propagate_parity(M, d, dtype):
+    say(f"propagate M={M} d={d} {dtype}")
+    Om = wl.random_skew_hermitian_batch(max(M, 1), d, 3.0, config_id=500 + M)[:M]
+    Uo = oracle.expm_skew_hermitian(Om) if M else np.zeros((0, d, d), complex)
+    Ud = gpu(Uo).to(dtype)
+    Uref = host(Ud).astype(np.complex128)       # what the GPU sees (rounded for FP32)
+    psi0 = wl.random_state(d, 7)
+    psi = gpu(psi0)
+    traj = torch.empty((M + 1, d), dtype=torch.complex128, device=DEV)
+    q.propagate(Ud, q.STATE, psi, traj=traj)
+    P = torch.empty((d, d), dtype=dtype, device=DEV)
+    q.propagate(Ud, q.PRODUCT, P)
+    torch.cuda.synchronize()
+    psi_o, traj_o = oracle.propagate_state(Uref, psi0, trajectory=True)
+    tol = 1e-13 * max(M, 1) * math.sqrt(d)
+    assert np.abs(host(psi) - psi_o).max() <= tol
+    assert np.abs(host(traj) - traj_o).max() <= tol
+    P_o = oracle.propagate_product(Uref)
+    ptol = tol if dtype == torch.complex128 else 1e-6 * max(M, 1) * math.sqrt(d)
+    assert np.abs(host(P).astype(np.complex128) - P_o).max() <= ptol
+
+
+# --------------------------------------------------------------- end to end
+
+def _evolve(w, dtype, chunk=None):
+    return q.evolve(gpu(w.H0), gpu(w.Hk), gpu(w.u), w.dt_sample, w.M, w.order, psi0=gpu(w.psi0), dtype=dtype,
+                    product=True, trajectory=True, chunk=chunk)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_transmon_duffing_d8_end_to_end(order):
+    # the single-transmon job (d = 8, 1e4 samples, M = 100), complex128
+    say(f"transmon d8 order={order}")
+    w = wl.transmon_duffing(order=order)
+    ref = oracle.run(w.H0, w.Hk, w.u, w.dt_sample, w.M, order, psi0=w.psi0, product=True)
+    out = _evolve(w, torch.complex128)
+    torch.cuda.synchronize()
+    U = host(out["U"])
+    assert np.all(oracle.propagator_infidelity(ref["U"], U) <= 1e-12)
+    assert np.abs(U - ref["U"]).max() <= 1e-10
+    assert oracle.state_infidelity(ref["psi"], host(out["psi"])) <= 1e-12
+    assert np.abs(host(out["traj"]) - ref["traj"]).max() <= 1e-10
+    assert oracle.propagator_infidelity(ref["P"], host(out["P"])) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_random_system_order2_end_to_end(dtype):
+    say(f"random system order 2 {dtype}")
+    w = wl.random_system(48, 3, 40 * 15, 40, 2, config_id=88, drift_scale=30.0, drive_scale=5.0)
+    ref = oracle.run(w.H0, w.Hk, w.u, w.dt_sample, w.M, 2, psi0=w.psi0, product=True)
+    out = _evolve(w, dtype, chunk=16)
+    torch.cuda.synchronize()
+    U = host(out["U"]).astype(np.complex128)
+    tol = INF_TOL[dtype]
+    assert np.all(oracle.propagator_infidelity(ref["U"], U) <= tol)
+    assert oracle.state_infidelity(ref["psi"], host(out["psi"])) <= tol
+    assert oracle.propagator_infidelity(ref["P"], host(out["P"]).astype(np.complex128)) <= tol

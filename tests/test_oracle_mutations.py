@@ -25,7 +25,7 @@ MUTANTS = {
     "commutator_swapped": ("comms = [(k, commutator(H0, Hk[k]))", "comms = [(k, commutator(Hk[k], H0))"),
     "missing_conj": ("@ V.conj().T", "@ V.T"),
     "c20_missing_dt": ("c2[n, k] = dt * dt * math.fsum(w * seg[k])", "c2[n, k] = dt * math.fsum(w * seg[k])"),
-    "scaling_floor": ("int(math.ceil(math.log2(nrm / THETA13_F64)))", "int(math.floor(math.log2(nrm / THETA13_F64)))"),
+    "scaling_step": ("        s += 1\n    return s", "        s += 2\n    return s"),
     "state_adjoint": ("psi = Un @ psi", "psi = Un.conj().T @ psi"),
     "drift_dropped": ("H = dt_interval * H0", "H = 0.0 * H0"),
 }
