@@ -1,0 +1,226 @@
+"""Throughput of the Magnus time-evolution path on one MI355X.
+
+One step = one pass of the whole path over one job, inputs resident in HBM:
+  per-interval coefficients -> commutator basis + generators Omega_n ->
+  U_n = exp(Omega_n) for all M intervals (Pade scaling and squaring) ->
+  state chain psi_M = U_M ... U_1 psi_0.
+Metric: interval propagators per second (M / step time).
+
+Prints ONE JSON line.  Default workload: transmon (10 levels) x resonator
+(100 levels), d = 1000, two drives, 1e5 samples, M = 1000 intervals, second
+order, complex64 products on MFMA with FP64 norm / scaling / Pade solve.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--dtype c64|c128]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}   # MI355X dense FP32 / FP64 matrix peaks
+HBM_PEAK_GBS = 8000.0
+DEFAULT_CHUNK = {"c64": 256, "c128": 128}          # intervals per expm chunk
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="transmon10x_resonator100_d1000")
+    ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--no-fp64-compare", action="store_true", help="skip the plain FP64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-intervals", type=int, default=96, help="intervals in the CPU-oracle sample")
+    return ap.parse_args()
+
+
+def build_workload(name):
+    import workloads as wl
+    if name == "transmon10x_resonator100_d1000":
+        return wl.transmon_resonator()
+    if name == "spin_chain_10_d1024":
+        return wl.spin_chain()
+    if name == "transmon_duffing_d8":
+        return wl.transmon_duffing()
+    raise SystemExit(f"unknown workload {name}")
+
+
+class Job:
+    """Device-resident inputs and preallocated buffers for one workload."""
+
+    def __init__(self, w, dtype_name, chunk):
+        import torch
+        import paper_2411_09982_amd as q
+        self.q, self.torch, self.w = q, torch, w
+        dev = "cuda:0"
+        self.dtype = torch.complex64 if dtype_name == "c64" else torch.complex128
+        code = q.C64 if dtype_name == "c64" else q.C128
+        d, K, M = w.d, w.K, w.M
+        self.H0 = torch.from_numpy(w.H0).to(dev)
+        self.Hk = torch.from_numpy(w.Hk).to(dev)
+        self.u = torch.from_numpy(np.ascontiguousarray(w.u)).to(dev)
+        self.psi0 = torch.from_numpy(w.psi0).to(dev)
+        self.psi = torch.empty_like(self.psi0)
+        self.c1 = torch.empty((M, K), dtype=torch.float64, device=dev)
+        self.c2 = torch.empty((M, K + K * (K - 1) // 2), dtype=torch.float64, device=dev) if w.order == 2 else None
+        self.omega = torch.empty((M, d, d), dtype=self.dtype, device=dev)
+        self.s = torch.empty(M, dtype=torch.int32, device=dev)
+        gen_ws = q.workspace_bytes(q.FN_GENERATORS, 1, d, K, w.order, q.C128)
+        self.gen_ws = torch.empty(max(gen_ws, 1), dtype=torch.uint8, device=dev) if gen_ws else None
+        self.chunk = min(chunk, M)
+        self.exp_ws = torch.empty(q.workspace_bytes(q.FN_EXPM, self.chunk, d, 1, 1, code), dtype=torch.uint8,
+                                  device=dev)
+        self.prop_ws = torch.empty(q.workspace_bytes(q.FN_PROPAGATE, M, d, 1, q.STATE, code), dtype=torch.uint8,
+                                   device=dev)
+
+    def step(self):
+        q, w = self.q, self.w
+        q.magnus_coeffs(self.u, w.dt_sample, w.M, w.order, c1=self.c1, c2=self.c2)
+        q.magnus_generators(self.H0, self.Hk, self.c1, self.c2, w.dt_interval, w.order, self.dtype,
+                            omega=self.omega, ws=self.gen_ws)
+        q.expm_batched(self.omega, U=self.omega, s_out=self.s, ws=self.exp_ws)
+        self.psi.copy_(self.psi0)
+        q.propagate(self.omega, q.STATE, self.psi, ws=self.prop_ws)
+
+
+def timed(job, steps, warmup, roofline=True):
+    torch, q = job.torch, job.q
+    for _ in range(warmup):
+        job.step()
+    torch.cuda.synchronize()
+    if roofline:
+        q.timing_enable(True)
+    times = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        job.step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern = {}
+    if roofline:
+        kern["f32"] = q.timing_read(q.KERNEL_GEMM_F32)
+        kern["f64"] = q.timing_read(q.KERNEL_GEMM_F64)
+        q.timing_enable(False)
+    return elapsed, times, kern
+
+
+def flop_count(w, s_hist):
+    """Algorithmic flops of one step: (8 (6 + s_n) + 32/3) d^3 per interval for the
+    [13/13] Pade products, solve and squarings, plus 16 d^3 per commutator."""
+    d = float(w.d)
+    n_comm = (w.K + w.K * (w.K - 1) // 2) if w.order == 2 else 0
+    return sum((8.0 * (6 + s) + 32.0 / 3.0) * d ** 3 for s in s_hist) + 16.0 * d ** 3 * n_comm
+
+
+def cpu_baseline(w, n_int):
+    """The oracle on the host cores over the first n_int intervals of the same job."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    s = w.N // w.M
+    u = np.ascontiguousarray(w.u[:, : n_int * s])
+    t0 = time.perf_counter()
+    c1, c2 = oracle.interval_coefficients(u, w.dt_sample, n_int, w.order)
+    Hbar = oracle.effective_hamiltonians(w.H0, w.Hk, c1, c2, w.dt_interval, w.order)
+    U = oracle.propagator_from_hamiltonian(Hbar)
+    psi = oracle.propagate_state(U, w.psi0)
+    el = time.perf_counter() - t0
+    return dict(value=n_int / el, unit="interval propagators/s", cores=int(cores), kind="oracle",
+                sample=f"first {n_int} of {w.M} intervals of the same job (d={w.d}), coefficients + "
+                       f"commutator basis + eigh propagators + state chain, {el:.1f} s"), U, psi
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this path has no multi-GPU mode",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2411_09982_amd as q
+    q.lib()
+    w = build_workload(a.workload)
+    chunk = a.chunk or DEFAULT_CHUNK[a.dtype]
+    job = Job(w, a.dtype, chunk)
+    elapsed, times, kern = timed(job, a.steps, a.warmup)
+    s_hist = job.s.cpu().numpy().tolist()
+    value = w.M * a.steps / elapsed
+    ms = 1000.0 * elapsed / a.steps
+    fl_step = flop_count(w, s_hist)
+
+    k = kern["f32"] if a.dtype == "c64" else kern["f64"]
+    achieved = k["flops"] / (k["ms"] * 1e-3) / 1e12 if k["ms"] > 0 else 0.0
+    peak = MFMA_PEAK_TFLOPS[a.dtype]
+    roof = dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
+                frac=round(achieved / peak, 4), traffic=None,
+                kernel=("cgemm_kernel<float,128,128,16,64,64>" if a.dtype == "c64"
+                        else "cgemm_kernel<double,64,64,16,32,32>"),
+                launches=k["launches"], avg_launch_ms=round(k["ms"] / max(k["launches"], 1), 4),
+                flops_per_launch=k["flops"] / max(k["launches"], 1))
+    extra = dict(
+        whole_step_tflops=round(fl_step / (ms * 1e-3) / 1e12, 2),
+        step_ms_p50=round(1000 * float(np.percentile(times, 50)), 2),
+        step_ms_p99=round(1000 * float(np.percentile(times, 99)), 2),
+        s_hist={str(v): s_hist.count(v) for v in sorted(set(s_hist))},
+        fp64_gemm=dict(launches=kern["f64"]["launches"], ms_per_step=round(kern["f64"]["ms"] / a.steps, 2),
+                       tflops=round(kern["f64"]["flops"] / max(kern["f64"]["ms"], 1e-9) * 1e-9, 2)),
+        fp32_gemm=dict(launches=kern["f32"]["launches"], ms_per_step=round(kern["f32"]["ms"] / a.steps, 2)),
+        chunk=job.chunk,
+    )
+    psi_mixed = job.psi.cpu().numpy()
+    U_samples = {n: job.omega[n].cpu().numpy().astype(np.complex128) for n in (0, w.M // 2, w.M - 1)}
+    del job
+    torch.cuda.empty_cache()
+
+    if a.dtype == "c64" and not a.no_fp64_compare:
+        job64 = Job(w, "c128", DEFAULT_CHUNK["c128"])
+        el64, _, _ = timed(job64, 1, 1, roofline=False)
+        v64 = w.M / el64
+        psi64 = job64.psi.cpu().numpy()
+        extra["fp64_plain"] = dict(value=round(v64, 2), ms_per_step=round(1000 * el64, 1),
+                                   mixed_speedup=round(value / v64, 3),
+                                   state_infidelity_fp32_vs_fp64=float(
+                                       1 - abs(np.vdot(psi64, psi_mixed)) ** 2))
+        del job64
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        import oracle
+        cpu, U_or, _ = cpu_baseline(w, a.cpu_intervals)
+        # sampled parity of the benchmarked run: interval 0 from the oracle sample
+        extra["infidelity_U0_vs_oracle"] = float(oracle.propagator_infidelity(U_or[0], U_samples[0]))
+
+    out = dict(
+        metric="Magnus interval propagators/s at d=1024 (MFMA %) vs FP64 plain; p50/p99 latency",
+        value=round(value, 3), unit="interval propagators/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+        ms_per_step=round(ms, 2), higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="c64+f64" if a.dtype == "c64" else "c128",
+        data="synthetic",
+        config=dict(workload=w.name, d=w.d, K=w.K, N=w.N, M=w.M, order=w.order,
+                    precision=("complex64 MFMA products and squarings, FP64 norm/scaling/Pade solve"
+                               if a.dtype == "c64" else "complex128 throughout")),
+        roofline=roof, cpu_baseline=cpu, extra=extra,
+    )
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

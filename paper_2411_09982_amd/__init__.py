@@ -31,6 +31,7 @@ C128, C64 = 1, 2
 STATE, PRODUCT = 1, 2
 REUSE_BASIS = 1
 FN_GENERATORS, FN_EXPM, FN_PROPAGATE = 1, 2, 3
+KERNEL_GEMM_F32, KERNEL_GEMM_F64 = 1, 2
 
 _DTYPES = {torch.complex128: C128, torch.complex64: C64}
 _TORCH = {C128: torch.complex128, C64: torch.complex64}
@@ -62,6 +63,10 @@ def lib() -> ctypes.CDLL:
         getattr(L, f).restype = i32
     L.qcheff_workspace_bytes.argtypes = [i32, i64, i64, i64, i32, i32]
     L.qcheff_workspace_bytes.restype = ctypes.c_size_t
+    L.qcheff_timing_enable.argtypes = [i32]
+    L.qcheff_timing_enable.restype = i32
+    L.qcheff_timing_read.argtypes = [i32, vp, vp, vp, vp]
+    L.qcheff_timing_read.restype = i32
     L.qcheff_last_error.argtypes = []
     L.qcheff_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -173,6 +178,19 @@ def propagate(U, mode: int, x, traj=None, ws=None, stream=None):
         _ptr(U), M, d, dt, mode, _ptr(x), _ptr(traj), _ptr(ws), 0 if ws is None else ws.numel(),
         _stream(stream)))
     return x
+
+
+def timing_enable(on: bool) -> None:
+    """Start (clearing old records) or stop HIP-event timing of the GEMM kernel launches."""
+    _check("qcheff_timing_enable", lib().qcheff_timing_enable(1 if on else 0))
+
+
+def timing_read(kernel: int) -> dict:
+    """Launch count, summed event time (ms), algorithmic flops and bytes of `kernel`'s timed launches."""
+    n, ms, fl, by = ctypes.c_int64(0), ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+    _check("qcheff_timing_read", lib().qcheff_timing_read(kernel, ctypes.byref(n), ctypes.byref(ms),
+                                                          ctypes.byref(fl), ctypes.byref(by)))
+    return dict(launches=n.value, ms=ms.value, flops=fl.value, bytes=by.value)
 
 
 def evolve(H0, Hk, u, dt_sample: float, M: int, order: int, psi0=None, dtype=torch.complex64,

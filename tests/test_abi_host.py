@@ -14,7 +14,8 @@ pytestmark = pytest.mark.skipif(not __import__("os").path.exists(q.LIB_PATH),
 def test_exports_every_header_symbol():
     names = q.header_symbols()
     assert set(names) == {"qcheff_magnus_coeffs", "qcheff_magnus_generators", "qcheff_expm_batched",
-                          "qcheff_propagate", "qcheff_workspace_bytes", "qcheff_last_error"}
+                          "qcheff_propagate", "qcheff_workspace_bytes", "qcheff_last_error",
+                          "qcheff_timing_enable", "qcheff_timing_read"}
     L = q.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -90,6 +91,15 @@ def test_propagate_validation():
     # product tree: ceil(M/2) + ceil(M/4) matrices of 256-byte-rounded size
     assert q.workspace_bytes(q.FN_PROPAGATE, 5, 4, 1, q.PRODUCT, q.C64) == (3 + 2) * 256
     assert q.workspace_bytes(9, 5, 4, 1, 1, q.C64) == 0
+
+
+def test_timing_api_without_gpu():
+    L = q.lib()
+    assert L.qcheff_timing_read(1, None, None, None, None) == q.EINVAL
+    n, ms, fl, by = ctypes.c_int64(7), ctypes.c_double(1), ctypes.c_double(1), ctypes.c_double(1)
+    assert L.qcheff_timing_enable(0) == q.OK
+    assert L.qcheff_timing_read(1, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by)) == q.OK
+    assert n.value == 0 and ms.value == 0.0
 
 
 def test_no_cpu_fallback_in_binding(monkeypatch, tmp_path):
