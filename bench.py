@@ -170,8 +170,8 @@ def main():
     peak = MFMA_PEAK_TFLOPS[a.dtype]
     roof = dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
                 frac=round(achieved / peak, 4), traffic=None,
-                kernel=("cgemm_kernel<float,128,128,16,64,64>" if a.dtype == "c64"
-                        else "cgemm_kernel<double,64,64,16,32,32>"),
+                kernel=("cgemm_kernel<float,...> (Pade products, squarings)" if a.dtype == "c64"
+                        else "cgemm_kernel<double,...> (Pade products, squarings, LU updates)"),
                 launches=k["launches"], avg_launch_ms=round(k["ms"] / max(k["launches"], 1), 4),
                 flops_per_launch=k["flops"] / max(k["launches"], 1))
     extra = dict(

@@ -126,9 +126,12 @@ int qcheff_magnus_generators(const void* H0, const void* Hk, int64_t d, int64_t 
 /*
  * qcheff_expm_batched - U_b = exp(Omega_b) for a batch of d x d matrices by
  * [13/13] Pade scaling and squaring (the exponentiation step of Sec. 4.1; the
- * method is Higham 2005: s_b = smallest s >= 0 with ||Omega_b||_1 / 2^s <= 5.3719...,
+ * method is Higham 2005: s_b = smallest s >= 0 with ||Omega_b||_1 / 2^s <= theta13,
  * computed in FP64; A = Omega_b / 2^s; R = q(A)^-1 p(A) by LU with partial
- * pivoting in FP64; U_b = R^(2^s)).
+ * pivoting in FP64; U_b = R^(2^s)).  theta13 = 5.371920351148152 is the largest
+ * norm at which the [13/13] approximant's backward error stays below 2^-53; both
+ * dtypes use it (in FP32 the rounding of the polynomial evaluation, which grows
+ * with the norm, outweighs the squaring a larger theta would save).
  *
  *   omega      [batch][d][d], device, dtype.  Any square matrix; the Magnus
  *              generators are skew-Hermitian.

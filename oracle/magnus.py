@@ -37,8 +37,9 @@ import numpy as np
 
 # Higham (2005), "The scaling and squaring method for the matrix exponential
 # revisited", Table 2.3: largest 1-norm for which the [13/13] Pade approximant
-# reaches double-precision backward error.
+# reaches double-precision backward error (u = 2^-53).
 THETA13_F64 = 5.371920351148152
+
 
 
 # ------------------------------------------------------------------ checks
@@ -178,7 +179,7 @@ def norm1(A):
     return float(np.abs(np.asarray(A)).sum(axis=-2).max())
 
 
-def scaling_exponent(Omega):
+def scaling_exponent(Omega, theta=THETA13_F64):
     """Number of squarings s of the [13/13] scaling-and-squaring method (Higham 2005):
     the smallest s >= 0 with ||Omega||_1 / 2^s <= theta_13 (that is,
     max(0, ceil(log2(||Omega||_1 / theta_13)))), decided by exact float64
@@ -187,7 +188,7 @@ def scaling_exponent(Omega):
     if not math.isfinite(nrm):
         return -1
     s = 0
-    while nrm > math.ldexp(THETA13_F64, s):
+    while nrm > math.ldexp(theta, s):
         s += 1
     return s
 

@@ -12,6 +12,7 @@
 #include "../../include/qcheff.h"
 #include "cgemm.hpp"
 #include "kernels.hpp"
+#include "lu.hpp"
 #include "validate.hpp"
 
 namespace qcheff {
@@ -83,7 +84,11 @@ void pade_coefficients(int m, double* b) {
 }
 
 // Largest 1-norm for which the [13/13] approximant reaches double-precision
-// backward error (Higham 2005, Table 2.3).
+// backward error (Higham 2005, Table 2.3).  The FP32 path uses it too: its
+// truncation error would allow about twice the norm, but the rounding error of
+// evaluating the degree-13 polynomials in FP32 grows with sum_j b_j ||A||^j
+// (about 15 at this norm, 270 at twice it), which costs more accuracy than the
+// squaring it saves.
 constexpr double kTheta13 = 5.371920351148152;
 
 // ------------------------------------------------------------------- coeffs
@@ -207,44 +212,108 @@ int gemm_sq(typename Cx<T>::t* out, const typename Cx<T>::t* A, const typename C
   return QCHEFF_OK;
 }
 
+// ------------------------------------------------------- recursive LU solve
+//
 // Solve q R = p for the chunk's augmented systems [q | p] in place (R lands in
-// the right half): blocked LU with partial pivoting, then back substitution.
-int lu_solve(double2* aug, int* piv, int64_t d, int64_t nb, hipStream_t st) {
-  const int64_t ld = 2 * d, stride = 2 * d * d;
-  for (int64_t k0 = 0; k0 < d; k0 += kNb) {
-    const int64_t k1 = std::min<int64_t>(k0 + kNb, d);
-    hipLaunchKernelGGL(lu_panel_kernel, dim3(unsigned(nb)), dim3(256), 0, st, aug, ld, stride, int(d), int(k0),
-                       int(k1), piv);
-    QC_HIP(hipGetLastError());
-    const int64_t ncols = 2 * d - k1;
-    hipLaunchKernelGGL(lu_swap_trsm_kernel, dim3(nblocks(ncols, 256), unsigned(nb)), dim3(256), 0, st, aug, ld,
-                       stride, int(d), int(2 * d), int(k0), int(k1), piv);
-    QC_HIP(hipGetLastError());
-    if (k1 < d) {
-      auto p = gemm_params<double>(int(d - k1), int(2 * d - k1), int(k1 - k0), int(nb));
-      p.A = aug + k1 * ld + k0; p.lda = ld; p.sA = stride;
-      p.B = aug + k0 * ld + k1; p.ldb = ld; p.sB = stride;
-      p.C = aug + k1 * ld + k1; p.ldc = ld; p.sC = stride;
-      p.alpha = -1.0; p.beta = 1.0;
-      QC_HIP((launch_cgemm<double>(p, st)));
-    }
-  }
-  const int64_t nblk = (d + kNb - 1) / kNb;
-  for (int64_t blk = nblk - 1; blk >= 0; --blk) {
-    const int64_t k0 = blk * kNb, k1 = std::min<int64_t>(k0 + kNb, d);
-    hipLaunchKernelGGL(lu_backsub_kernel, dim3(nblocks(d, 256), unsigned(nb)), dim3(256), 0, st, aug, ld, stride,
-                       int(d), int(k0), int(k1));
-    QC_HIP(hipGetLastError());
-    if (k0 > 0) {
-      auto p = gemm_params<double>(int(k0), int(d), int(k1 - k0), int(nb));
-      p.A = aug + k0; p.lda = ld; p.sA = stride;
-      p.B = aug + k0 * ld + d; p.ldb = ld; p.sB = stride;
-      p.C = aug + d; p.ldc = ld; p.sC = stride;
-      p.alpha = -1.0; p.beta = 1.0;
-      QC_HIP((launch_cgemm<double>(p, st)));
-    }
-  }
+// the right half).  factor(k0, k1) factors columns [k0, k1) over rows [k0, d)
+// after every update from the columns left of k0 has been applied to them.
+struct LuCtx {
+  double2* aug;
+  int* piv;
+  int64_t d, ld, stride, nb;
+  hipStream_t st;
+  int panel_nb;     // leaf width of the factorization
+  int panel_rows;   // register panel: rows per item it can hold (0: global-memory panel)
+};
+
+int lu_gemm_update(const LuCtx& c, int64_t r0, int64_t r1, int64_t c0, int64_t c1, int64_t k0, int64_t k1) {
+  // A[r0:r1, c0:c1] -= A[r0:r1, k0:k1] * A[k0:k1, c0:c1]
+  if (r1 <= r0 || c1 <= c0 || k1 <= k0) return QCHEFF_OK;
+  auto p = gemm_params<double>(int(r1 - r0), int(c1 - c0), int(k1 - k0), int(c.nb));
+  p.A = c.aug + r0 * c.ld + k0; p.lda = c.ld; p.sA = c.stride;
+  p.B = c.aug + k0 * c.ld + c0; p.ldb = c.ld; p.sB = c.stride;
+  p.C = c.aug + r0 * c.ld + c0; p.ldc = c.ld; p.sC = c.stride;
+  p.alpha = -1.0; p.beta = 1.0;
+  QC_HIP((launch_cgemm<double>(p, c.st)));
   return QCHEFF_OK;
+}
+
+int lu_pivots(const LuCtx& c, int64_t k0, int64_t k1, int64_t c0, int64_t c1) {
+  if (c1 <= c0 || k1 <= k0) return QCHEFF_OK;
+  hipLaunchKernelGGL(lu_pivots_kernel, dim3(nblocks(c1 - c0, 256), unsigned(c.nb)), dim3(256), 0, c.st, c.aug, c.ld,
+                     c.stride, int(c.d), int(k0), int(k1), int(c0), int(c1), c.piv);
+  QC_HIP(hipGetLastError());
+  return QCHEFF_OK;
+}
+
+int64_t split_point(int64_t r0, int64_t r1, int64_t unit) {
+  const int64_t half = (r1 - r0) / 2;
+  return r0 + std::max<int64_t>(unit, (half + unit - 1) / unit * unit);
+}
+
+// X <- L^{-1} X, L unit lower on rows/cols [r0, r1), X = A[r0:r1, c0:c1]
+int trsm_lower(const LuCtx& c, int64_t r0, int64_t r1, int64_t c0, int64_t c1) {
+  if (r1 - r0 <= kTrsmNb) {
+    hipLaunchKernelGGL(trsm_lower_unit_kernel, dim3(nblocks(c1 - c0, 256), unsigned(c.nb)), dim3(256), 0, c.st,
+                       c.aug, c.ld, c.stride, int(r0), int(r1), int(c0), int(c1));
+    QC_HIP(hipGetLastError());
+    return QCHEFF_OK;
+  }
+  const int64_t h = split_point(r0, r1, kTrsmNb);
+  int r;
+  if ((r = trsm_lower(c, r0, h, c0, c1))) return r;
+  if ((r = lu_gemm_update(c, h, r1, c0, c1, r0, h))) return r;
+  return trsm_lower(c, h, r1, c0, c1);
+}
+
+// X <- U^{-1} X, U upper on rows/cols [r0, r1), X = A[r0:r1, c0:c1]
+int trsm_upper(const LuCtx& c, int64_t r0, int64_t r1, int64_t c0, int64_t c1) {
+  if (r1 - r0 <= kTrsmNb) {
+    hipLaunchKernelGGL(trsm_upper_kernel, dim3(nblocks(c1 - c0, 256), unsigned(c.nb)), dim3(256), 0, c.st, c.aug,
+                       c.ld, c.stride, int(r0), int(r1), int(c0), int(c1));
+    QC_HIP(hipGetLastError());
+    return QCHEFF_OK;
+  }
+  const int64_t h = split_point(r0, r1, kTrsmNb);
+  int r;
+  if ((r = trsm_upper(c, h, r1, c0, c1))) return r;
+  if ((r = lu_gemm_update(c, r0, h, c0, c1, h, r1))) return r;
+  return trsm_upper(c, r0, h, c0, c1);
+}
+
+int lu_panel(const LuCtx& c, int64_t k0, int64_t k1) {
+  const unsigned g = unsigned(c.nb);
+  const int d = int(c.d);
+  if (c.panel_rows == 1024)
+    hipLaunchKernelGGL((lu_panel_reg_kernel<16>), dim3(g), dim3(1024), 0, c.st, c.aug, c.ld, c.stride, d, int(k0),
+                       int(k1), c.piv);
+  else
+    hipLaunchKernelGGL(lu_panel_kernel, dim3(g), dim3(256), 0, c.st, c.aug, c.ld, c.stride, d, int(k0), int(k1),
+                       c.piv);
+  QC_HIP(hipGetLastError());
+  return QCHEFF_OK;
+}
+
+int lu_factor(const LuCtx& c, int64_t k0, int64_t k1) {
+  if (k1 - k0 <= c.panel_nb) return lu_panel(c, k0, k1);
+  const int64_t km = split_point(k0, k1, c.panel_nb);
+  int r;
+  if ((r = lu_factor(c, k0, km))) return r;
+  if ((r = lu_pivots(c, k0, km, km, k1))) return r;          // left pivots on the right half
+  if ((r = trsm_lower(c, k0, km, km, k1))) return r;         // U12 = L11^{-1} A12
+  if ((r = lu_gemm_update(c, km, c.d, km, k1, k0, km))) return r;  // A22 -= L21 U12
+  if ((r = lu_factor(c, km, k1))) return r;
+  return lu_pivots(c, km, k1, k0, km);                       // right pivots on the left half's L
+}
+
+int lu_solve(double2* aug, int* piv, int64_t d, int64_t nb, hipStream_t st) {
+  LuCtx c{aug, piv, d, 2 * d, 2 * d * d, nb, st, 32, 0};
+  if (d <= 1024) { c.panel_nb = 16; c.panel_rows = 1024; }
+  int r;
+  if ((r = lu_factor(c, 0, d))) return r;
+  if ((r = lu_pivots(c, 0, d, d, 2 * d))) return r;          // P p
+  if ((r = trsm_lower(c, 0, d, d, 2 * d))) return r;         // Y = L^{-1} P p
+  return trsm_upper(c, 0, d, d, 2 * d);                      // R = U^{-1} Y
 }
 
 template <typename T>

@@ -5,7 +5,7 @@
 //
 // A complex product is four real MFMA products on planar operands:
 //   Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br.
-// A workgroup of four waves owns a BM x BN tile of C; each wave a WM x WN
+// A workgroup of NT / 64 waves owns a BM x BN tile of C; each wave a WM x WN
 // sub-tile built from 16x16x4 MFMA instructions.  K advances BK at a time
 // through double-buffered LDS; the next tile is fetched into registers while
 // the current one is consumed.  Any M, N, K, leading dimension and offset is
@@ -47,15 +47,15 @@ template <typename T> struct GemmParams {
   const int* sq_s; int sq_step; C2* sq_p0; C2* sq_p1;
 };
 
-template <typename T, int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(256) void cgemm_kernel(GemmParams<T> p) {
+template <typename T, int BM, int BN, int BK, int WM, int WN, int NT>
+__global__ __launch_bounds__(NT) void cgemm_kernel(GemmParams<T> p) {
   using C2 = typename Cx<T>::t;
   using Acc = typename Cx<T>::acc;
   constexpr int WAVES_N = BN / WN;
-  static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
+  static_assert((BM / WM) * (BN / WN) * 64 == NT, "one wave per WM x WN sub-tile");
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int LA = BM * BK / 256, LB = BK * BN / 256;
-  static_assert(LA * 256 == BM * BK && LB * 256 == BK * BN, "tile loads must divide evenly");
+  constexpr int LA = BM * BK / NT, LB = BK * BN / NT;
+  static_assert(LA * NT == BM * BK && LB * NT == BK * BN, "tile loads must divide evenly");
 
   __shared__ C2 As[2][BK][BM + 1];
   __shared__ C2 Bs[2][BK][BN];
@@ -98,37 +98,45 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmParams<T> p) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) { accr[i][j][e] = T(0); acci[i][j][e] = T(0); }
 
+  // Loads are unconditional: an out-of-range element reads a clamped, valid
+  // address and is replaced by zero, so no load sits behind a branch.
   C2 ra[LA], rb[LB];
   auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < LA; ++q) {
-      const int e = tid + 256 * q, r = e / BK, k = e % BK;
+      const int e = tid + NT * q, r = e / BK, k = e % BK;
       const int gr = row0 + r, gk = k0 + k;
-      ra[q] = (gr < p.M && gk < p.K) ? A[int64_t(gr) * p.lda + gk] : czero<C2>();
+      const bool in = gr < p.M && gk < p.K;
+      const C2 v = A[int64_t(min(gr, p.M - 1)) * p.lda + max(0, min(gk, p.K - 1))];
+      ra[q] = in ? v : czero<C2>();
     }
 #pragma unroll
     for (int q = 0; q < LB; ++q) {
-      const int e = tid + 256 * q, k = e / BN, c = e % BN;
+      const int e = tid + NT * q, k = e / BN, c = e % BN;
       const int gk = k0 + k, gc = col0 + c;
-      rb[q] = (gk < p.K && gc < p.N) ? B[int64_t(gk) * p.ldb + gc] : czero<C2>();
+      const bool in = gk < p.K && gc < p.N;
+      const C2 v = B[int64_t(max(0, min(gk, p.K - 1))) * p.ldb + min(gc, p.N - 1)];
+      rb[q] = in ? v : czero<C2>();
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < LA; ++q) {
-      const int e = tid + 256 * q;
+      const int e = tid + NT * q;
       As[buf][e % BK][e / BK] = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < LB; ++q) {
-      const int e = tid + 256 * q;
+      const int e = tid + NT * q;
       Bs[buf][e / BN][e % BN] = rb[q];
     }
   };
 
   const int nk = (p.K + BK - 1) / BK;
-  load(0);
-  store(0);
+  if (nk > 0) {   // K = 0 (C = beta C + terms) reads no operand
+    load(0);
+    store(0);
+  }
   __syncthreads();
   const int lr = lane >> 4, lc = lane & 15;
   for (int kt = 0; kt < nk; ++kt) {
@@ -199,8 +207,12 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmParams<T> p) {
 
 // Tile shapes per precision.
 template <typename T> struct GemmTile;
-template <> struct GemmTile<float> { static constexpr int BM = 128, BN = 128, BK = 16, WM = 64, WN = 64; };
-template <> struct GemmTile<double> { static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32; };
+template <> struct GemmTile<float> {
+  static constexpr int BM = 128, BN = 128, BK = 16, WM = 64, WN = 32, NT = 512;
+};
+template <> struct GemmTile<double> {
+  static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, NT = 256;
+};
 
 template <typename T> GemmParams<T> gemm_params(int M, int N, int K, int batch) {
   GemmParams<T> p{};
@@ -222,8 +234,8 @@ hipError_t launch_cgemm(const GemmParams<T>& p, hipStream_t stream, int64_t acti
   if (active < 0) active = p.batch;
   LaunchTimer tm;
   tm.begin(stream);
-  hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN>), dim3(unsigned(blocks)), dim3(256), 0,
-                     stream, p);
+  hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT>), dim3(unsigned(blocks)), dim3(G::NT),
+                     0, stream, p);
   const hipError_t e = hipGetLastError();
   if (tm.on) {
     const double mn = double(p.M) * p.N, es = double(sizeof(typename Cx<T>::t));

@@ -224,159 +224,6 @@ __global__ void lincomb3_kernel(typename Cx<T>::t* __restrict__ Y, const typenam
   Y[i] = y;
 }
 
-// ------------------------------------------------- batched LU (FP64 complex)
-//
-// The augmented system [q | p] (d x 2d, row-major, ld = 2d) is reduced by
-// right-looking blocked LU with partial pivoting: panel factorization
-// (one workgroup per item), row interchanges and the unit-lower solve for the
-// block row (one thread per column), then the trailing update on MFMA.  The
-// back substitution with U runs block by block from the bottom.
-
-constexpr int kNb = 32;
-
-__device__ __forceinline__ double2 crecip(double2 a) {
-  const double den = a.x * a.x + a.y * a.y;
-  return make_double2(a.x / den, -a.y / den);
-}
-
-__global__ __launch_bounds__(256) void lu_panel_kernel(double2* aug, int64_t ld, int64_t stride, int d,
-                                                       int k0, int k1, int* piv_all) {
-  const int b = blockIdx.x;
-  double2* A = aug + b * stride;
-  int* piv = piv_all + int64_t(b) * d;
-  const int tid = threadIdx.x;
-  __shared__ double smax[256];
-  __shared__ int sidx[256];
-  __shared__ double2 prow[kNb];
-  for (int j = k0; j < k1; ++j) {
-    double best = -1.0;
-    int bi = j;
-    for (int i = j + tid; i < d; i += 256) {
-      const double2 v = A[int64_t(i) * ld + j];
-      const double m = fabs(v.x) + fabs(v.y);
-      if (m > best) { best = m; bi = i; }
-    }
-    smax[tid] = best;
-    sidx[tid] = bi;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) {
-        const double o = smax[tid + w];
-        const int oi = sidx[tid + w];
-        if (o > smax[tid] || (o == smax[tid] && oi < sidx[tid])) { smax[tid] = o; sidx[tid] = oi; }
-      }
-      __syncthreads();
-    }
-    const int pr = sidx[0];
-    if (tid == 0) piv[j] = pr;
-    if (pr != j) {
-      for (int c = k0 + tid; c < k1; c += 256) {
-        const double2 t = A[int64_t(j) * ld + c];
-        A[int64_t(j) * ld + c] = A[int64_t(pr) * ld + c];
-        A[int64_t(pr) * ld + c] = t;
-      }
-    }
-    __syncthreads();
-    if (tid < k1 - j) prow[tid] = A[int64_t(j) * ld + j + tid];
-    __syncthreads();
-    const double2 inv = crecip(prow[0]);
-    for (int i = j + 1 + tid; i < d; i += 256) {
-      double2* row = A + int64_t(i) * ld;
-      const double2 l = cmul(row[j], inv);
-      row[j] = l;
-      for (int c = 1; c < k1 - j; ++c) {
-        const double2 t = cmul(l, prow[c]);
-        row[j + c].x -= t.x;
-        row[j + c].y -= t.y;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Row interchanges of the panel applied to columns [k1, ncols), then the block
-// row U12 = L11^{-1} A12 (unit lower triangular solve), one thread per column.
-__global__ __launch_bounds__(256) void lu_swap_trsm_kernel(double2* aug, int64_t ld, int64_t stride, int d,
-                                                           int ncols, int k0, int k1, const int* piv_all) {
-  const int b = blockIdx.y;
-  double2* A = aug + b * stride;
-  const int* piv = piv_all + int64_t(b) * d;
-  const int nb = k1 - k0;
-  __shared__ double2 L[kNb][kNb + 1];
-  __shared__ int sp[kNb];
-  for (int e = threadIdx.x; e < nb * nb; e += 256) {
-    const int i = e / nb, j = e % nb;
-    L[i][j] = A[int64_t(k0 + i) * ld + k0 + j];
-  }
-  if (threadIdx.x < nb) sp[threadIdx.x] = piv[k0 + threadIdx.x];
-  __syncthreads();
-  const int c = k1 + blockIdx.x * 256 + threadIdx.x;
-  if (c >= ncols) return;
-  for (int j = 0; j < nb; ++j) {
-    const int pr = sp[j];
-    if (pr != k0 + j) {
-      const double2 t = A[int64_t(k0 + j) * ld + c];
-      A[int64_t(k0 + j) * ld + c] = A[int64_t(pr) * ld + c];
-      A[int64_t(pr) * ld + c] = t;
-    }
-  }
-  double2 x[kNb];
-#pragma unroll
-  for (int j = 0; j < kNb; ++j) x[j] = (j < nb) ? A[int64_t(k0 + j) * ld + c] : make_double2(0.0, 0.0);
-#pragma unroll
-  for (int j = 0; j < kNb; ++j) {
-#pragma unroll
-    for (int i = j + 1; i < kNb; ++i) {
-      if (i < nb) {
-        const double2 t = cmul(L[i][j], x[j]);
-        x[i].x -= t.x;
-        x[i].y -= t.y;
-      }
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < kNb; ++j)
-    if (j < nb) A[int64_t(k0 + j) * ld + c] = x[j];
-}
-
-// Back substitution for rows [k0, k1) of the right-hand side (columns [d, 2d)):
-// X_k = U_kk^{-1} Y_k, one thread per column.
-__global__ __launch_bounds__(256) void lu_backsub_kernel(double2* aug, int64_t ld, int64_t stride, int d,
-                                                         int k0, int k1) {
-  const int b = blockIdx.y;
-  double2* A = aug + b * stride;
-  const int nb = k1 - k0;
-  __shared__ double2 Ub[kNb][kNb + 1];
-  for (int e = threadIdx.x; e < nb * nb; e += 256) {
-    const int i = e / nb, j = e % nb;
-    Ub[i][j] = (j >= i) ? A[int64_t(k0 + i) * ld + k0 + j] : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  const int c = d + blockIdx.x * 256 + threadIdx.x;
-  if (c >= 2 * d) return;
-  double2 x[kNb];
-#pragma unroll
-  for (int j = 0; j < kNb; ++j) x[j] = (j < nb) ? A[int64_t(k0 + j) * ld + c] : make_double2(0.0, 0.0);
-#pragma unroll
-  for (int i = kNb - 1; i >= 0; --i) {
-    if (i < nb) {
-      double2 v = x[i];
-#pragma unroll
-      for (int j = i + 1; j < kNb; ++j) {
-        if (j < nb) {
-          const double2 t = cmul(Ub[i][j], x[j]);
-          v.x -= t.x;
-          v.y -= t.y;
-        }
-      }
-      x[i] = cmul(v, crecip(Ub[i][i]));
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < kNb; ++j)
-    if (j < nb) A[int64_t(k0 + j) * ld + c] = x[j];
-}
-
 // R = aug[:, d:2d] written (cast) to the buffer where the squarings must start
 // so that the last one lands in U: U if s is even (or no squaring), else P1.
 template <typename C2>

@@ -50,7 +50,7 @@ def test_transmon_resonator_d1000_full_size(job_and_ref, dt_name):
         assert inf <= inf_tol(job.dtype, s[n])
         if dt_name == "c128":
             assert np.abs(Ug - Uo[j]).max() <= 1e-10
-        assert s[n] == oracle.scaling_exponent(-1j * Hb[j]) or dt_name == "c64"
+        assert s[n] == oracle.scaling_exponent(-1j * Hb[j])
     # generators of the sampled intervals, formed again into a scratch buffer
     idx = torch.tensor(SAMPLED, device="cuda:0")
     om, _ = job.q.magnus_generators(job.H0, job.Hk, job.c1[idx].contiguous(), job.c2[idx].contiguous(),

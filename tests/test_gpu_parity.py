@@ -124,7 +124,7 @@ EXPM_DIMS = [1, 2, 3, 7, 8, 16, 33, 64, 100, 128, 257]
 @pytest.mark.parametrize("d", EXPM_DIMS)
 def test_expm_parity(d, dtype):
     say(f"expm d={d} {dtype}")
-    norms = [0.0, 0.01, 1.0, 5.3, 5.4, 20.0, 170.0, 1500.0]   # s = 0 .. 9
+    norms = [0.0, 0.01, 1.0, 5.3, 5.4, 11.0, 11.5, 20.0, 170.0, 1500.0]   # s = 0 .. 9
     Om = wl.random_skew_hermitian_batch(len(norms), d, norms, config_id=300 + d)
     ref = oracle.expm_skew_hermitian(Om)
     seen = Om.astype(np.complex64).astype(np.complex128) if dtype == torch.complex64 else Om
@@ -141,6 +141,27 @@ def test_expm_parity(d, dtype):
         assert oracle.unitarity_error(Ug) <= 1e-12
     else:
         assert oracle.unitarity_error(Ug) <= 1e-3
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("d", [1024, 1030])
+def test_expm_parity_large(d, dtype):
+    # d <= 1024 factors with register-resident panels, d > 1024 through the
+    # global-memory panel kernel
+    say(f"expm large d={d} {dtype}")
+    norms = [3.0, 60.0, 900.0]
+    Om = wl.random_skew_hermitian_batch(len(norms), d, norms, config_id=400 + d)
+    ref = oracle.expm_skew_hermitian(Om)
+    seen = Om.astype(np.complex64).astype(np.complex128) if dtype == torch.complex64 else Om
+    s_ref = [oracle.scaling_exponent(x) for x in seen]
+    U, s = q.expm_batched(gpu(Om).to(dtype))
+    torch.cuda.synchronize()
+    Ug = host(U).astype(np.complex128)
+    assert list(host(s)) == s_ref
+    inf = np.abs(oracle.propagator_infidelity(ref, Ug))
+    assert np.all(inf <= inf_tol(dtype, np.array(s_ref))), inf
+    if dtype == torch.complex128:
+        assert np.abs(Ug - ref).max() <= 1e-10
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])

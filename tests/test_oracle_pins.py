@@ -259,3 +259,13 @@ def test_input_checks():
     with pytest.raises(ValueError):
         oracle.check_inputs(H, H[None], np.full((1, 10), np.nan), 5)
     oracle.check_inputs(H, H[None], np.zeros((1, 10)), 5)
+
+
+def test_pade_theta_reproduces_higham_table():
+    # Higham (2005), Table 2.3 (u = 2^-53): theta_3 .. theta_13 of the [m/m] approximant
+    import oracle.pade_theta as pt
+    table = {3: 1.495585217958292e-2, 5: 2.539398330063230e-1, 7: 9.504178996162932e-1,
+             9: 2.097847961257068e0, 13: 5.371920351148152e0}
+    for m, val in table.items():
+        assert pt.theta(m, 2.0 ** -53, n=120) == pytest.approx(val, rel=1e-14)
+    assert oracle.THETA13_F64 == table[13]
