@@ -2,8 +2,9 @@
 
 One step = one pass of the whole path over one job, inputs resident in HBM:
   per-interval coefficients -> commutator basis + generators Omega_n ->
-  U_n = exp(Omega_n) for all M intervals (Pade scaling and squaring) ->
-  state chain psi_M = U_M ... U_1 psi_0.
+  U_n = exp(Omega_n) for all M intervals (Pade scaling and squaring, in chunks) ->
+  state chain psi_M = U_M ... U_1 psi_0 (each chunk's chain overlaps the next
+  chunk's exponentials on a second stream).
 Metric: interval propagators per second (M / step time).
 
 Prints ONE JSON line.  Default workload: transmon (10 levels) x resonator
@@ -41,7 +42,21 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-intervals", type=int, default=96, help="intervals in the CPU-oracle sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 1 GiB, three times: under rocprofv3 --pmc its
+    FETCH_SIZE and WRITE_SIZE per dispatch are the counters' reading for 1 GiB moved."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_bytes=src.numel() * 4, repeats=3)), flush=True)
 
 
 def build_workload(name):
@@ -82,15 +97,26 @@ class Job:
                                   device=dev)
         self.prop_ws = torch.empty(q.workspace_bytes(q.FN_PROPAGATE, M, d, 1, q.STATE, code), dtype=torch.uint8,
                                    device=dev)
+        self.side = torch.cuda.Stream()   # default priority
 
     def step(self):
-        q, w = self.q, self.w
+        """The whole path; the state chain of chunk c runs on a side stream while the
+        exponentials of chunk c + 1 run on the main one."""
+        q, w, torch = self.q, self.w, self.torch
+        main = torch.cuda.current_stream()
         q.magnus_coeffs(self.u, w.dt_sample, w.M, w.order, c1=self.c1, c2=self.c2)
         q.magnus_generators(self.H0, self.Hk, self.c1, self.c2, w.dt_interval, w.order, self.dtype,
                             omega=self.omega, ws=self.gen_ws)
-        q.expm_batched(self.omega, U=self.omega, s_out=self.s, ws=self.exp_ws)
         self.psi.copy_(self.psi0)
-        q.propagate(self.omega, q.STATE, self.psi, ws=self.prop_ws)
+        for c0 in range(0, w.M, self.chunk):
+            c1 = min(w.M, c0 + self.chunk)
+            U = self.omega[c0:c1]
+            q.expm_batched(U, U=U, s_out=self.s[c0:c1], ws=self.exp_ws)
+            ev = torch.cuda.Event()
+            ev.record(main)
+            self.side.wait_event(ev)
+            q.propagate(U, q.STATE, self.psi, ws=self.prop_ws, stream=self.side)
+        main.wait_stream(self.side)
 
 
 def timed(job, steps, warmup, roofline=True):
@@ -149,6 +175,9 @@ def cpu_baseline(w, n_int):
 
 def main():
     a = parse()
+    if a.copy_calibration:
+        copy_calibration()
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this path has no multi-GPU mode",
               file=sys.stderr)

@@ -177,7 +177,7 @@ template <typename T> struct ExpmWs {
   unsigned long long* norms;
   int* s_ws;
   int* smax;
-  C2* X[7];
+  C2* X[6];
   double2* aug;
   int* piv;
 };
@@ -188,18 +188,20 @@ template <typename T> bool carve_expm(void* ws, size_t bytes, int64_t chunk, int
   w.norms = cv.take<unsigned long long>(size_t(chunk) * 8);
   w.s_ws = cv.take<int>(size_t(chunk) * 4);
   w.smax = cv.take<int>(256);
-  for (int i = 0; i < 7; ++i) w.X[i] = cv.take<typename Cx<T>::t>(size_t(chunk) * dd * sizeof(typename Cx<T>::t));
+  for (int i = 0; i < 6; ++i) w.X[i] = cv.take<typename Cx<T>::t>(size_t(chunk) * dd * sizeof(typename Cx<T>::t));
   w.aug = cv.take<double2>(size_t(chunk) * 2 * dd * 16);
   w.piv = cv.take<int>(size_t(chunk) * size_t(d) * 4);
   bool ok = w.norms && w.s_ws && w.smax && w.aug && w.piv;
-  for (int i = 0; i < 7; ++i) ok = ok && w.X[i];
+  for (int i = 0; i < 6; ++i) ok = ok && w.X[i];
   return ok;
 }
 
+// out = A B (+ sum_i xc[i] X_i + gamma I) over a batch of d x d items; with bc,
+// the right operand is bc[0] X_0 + bc[1] X_1 + bc[2] X_2 instead of B.
 template <typename T>
 int gemm_sq(typename Cx<T>::t* out, const typename Cx<T>::t* A, const typename Cx<T>::t* B, int64_t d,
             int64_t nb, hipStream_t st, int nx = 0, const typename Cx<T>::t* const* X = nullptr,
-            const T* xc = nullptr, T gamma = T(0)) {
+            const T* xc = nullptr, T gamma = T(0), const T* bc = nullptr) {
   auto p = gemm_params<T>(int(d), int(d), int(d), int(nb));
   const int64_t dd = d * d;
   p.A = A; p.lda = d; p.sA = dd;
@@ -208,6 +210,13 @@ int gemm_sq(typename Cx<T>::t* out, const typename Cx<T>::t* A, const typename C
   p.nx = nx;
   for (int i = 0; i < nx; ++i) { p.X[i] = X[i]; p.xc[i] = xc[i]; }
   p.gamma = gamma;
+  if (bc) {
+    p.B = X[0];
+    p.nbx = 2;
+    p.BX[0] = X[1];
+    p.BX[1] = X[2];
+    for (int i = 0; i < 3; ++i) p.bxc[i] = bc[i];
+  }
   QC_HIP((launch_cgemm<T>(p, st)));
   return QCHEFF_OK;
 }
@@ -337,23 +346,19 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
   hipLaunchKernelGGL(scale_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, omega, w.X[0], dd, w.norms,
                      kTheta13, w.s_ws, s_out, w.smax);
   QC_HIP(hipGetLastError());
-  C2 *A = w.X[0], *A2 = w.X[1], *A4 = w.X[2], *A6 = w.X[3], *T4 = w.X[4], *W = w.X[5], *V = w.X[6];
+  C2 *A = w.X[0], *A2 = w.X[1], *A4 = w.X[2], *A6 = w.X[3], *W = w.X[4], *V = w.X[5];
   int r;
   if ((r = gemm_sq<T>(A2, A, A, d, nb, st))) return r;
   if ((r = gemm_sq<T>(A4, A2, A2, d, nb, st))) return r;
   if ((r = gemm_sq<T>(A6, A4, A2, d, nb, st))) return r;
-  const int64_t n = nb * dd;
   // W = A6 (b13 A6 + b11 A4 + b9 A2) + b7 A6 + b5 A4 + b3 A2 + b1 I   (U = A W)
-  hipLaunchKernelGGL(lincomb3_kernel<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, T4, A6, A4, A2, n, c[13], c[11], c[9]);
-  QC_HIP(hipGetLastError());
-  const C2* Xs[3] = {A6, A4, A2};
-  const T xw[3] = {c[7], c[5], c[3]};
-  if ((r = gemm_sq<T>(W, A6, T4, d, nb, st, 3, Xs, xw, c[1]))) return r;
   // V = A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I
-  hipLaunchKernelGGL(lincomb3_kernel<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, T4, A6, A4, A2, n, c[12], c[10], c[8]);
-  QC_HIP(hipGetLastError());
-  const T xv[3] = {c[6], c[4], c[2]};
-  if ((r = gemm_sq<T>(V, A6, T4, d, nb, st, 3, Xs, xv, c[0]))) return r;
+  // The right operand's linear combination is formed as the GEMM loads it.
+  const C2* Xs[3] = {A6, A4, A2};
+  const T xw[3] = {c[7], c[5], c[3]}, bw[3] = {c[13], c[11], c[9]};
+  if ((r = gemm_sq<T>(W, A6, A6, d, nb, st, 3, Xs, xw, c[1], bw))) return r;
+  const T xv[3] = {c[6], c[4], c[2]}, bv[3] = {c[12], c[10], c[8]};
+  if ((r = gemm_sq<T>(V, A6, A6, d, nb, st, 3, Xs, xv, c[0], bv))) return r;
   // [q | p] = [V - A W | V + A W] in FP64
   {
     auto p = gemm_params<T>(int(d), int(d), int(d), int(nb));

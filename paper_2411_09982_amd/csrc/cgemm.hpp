@@ -1,6 +1,7 @@
 // Batched complex GEMM on MFMA (gfx950), FP32 or FP64, interleaved complex storage.
 //
 //   C_b = alpha * A_b B_b + beta * C_b + sum_i xc[i] X_{i,b} + gamma * I      (EPI_STD)
+//   (B_b may be a linear combination of up to three matrices, formed as it loads)
 //   aug_b[:, :N] = V_b - A_b B_b,  aug_b[:, off:off+N] = V_b + A_b B_b (FP64)  (EPI_AUG)
 //
 // A complex product is four real MFMA products on planar operands:
@@ -41,14 +42,19 @@ template <typename T> struct GemmParams {
   int sq;                       // 1: squaring mode (sq_* fields)
   int nx;                       // number of X terms (0..3); X share C's ld and stride
   const C2* X[3]; T xc[3];
+  // B operand as a linear combination: B_eff = bxc[0] B + sum_{i < nbx} bxc[i+1] BX[i]
+  // (BX share B's ld and stride); nbx = 0 uses B as it is
+  int nbx;
+  const C2* BX[2]; T bxc[3];
   // EPI_AUG target (FP64 always)
   double2* aug; int64_t ld_aug, s_aug, aug_off;
   // squaring mode: A = B = in, C = out, chosen per item from the remaining count
   const int* sq_s; int sq_step; C2* sq_p0; C2* sq_p1;
 };
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, int NT>
-__global__ __launch_bounds__(NT) void cgemm_kernel(GemmParams<T> p) {
+template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int WAVES_PER_EU>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU))) void cgemm_kernel(
+    GemmParams<T> p) {
   using C2 = typename Cx<T>::t;
   using Acc = typename Cx<T>::acc;
   constexpr int WAVES_N = BN / WN;
@@ -85,6 +91,8 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmParams<T> p) {
     B = p.B + b * p.sB;
     C = p.C + b * p.sC;
   }
+  const C2* BX0 = p.nbx > 0 ? p.BX[0] + b * p.sB : B;
+  const C2* BX1 = p.nbx > 1 ? p.BX[1] + b * p.sB : B;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -115,7 +123,14 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmParams<T> p) {
       const int e = tid + NT * q, k = e / BN, c = e % BN;
       const int gk = k0 + k, gc = col0 + c;
       const bool in = gk < p.K && gc < p.N;
-      const C2 v = B[int64_t(max(0, min(gk, p.K - 1))) * p.ldb + min(gc, p.N - 1)];
+      const int64_t off = int64_t(max(0, min(gk, p.K - 1))) * p.ldb + min(gc, p.N - 1);
+      C2 v = B[off];
+      if (p.nbx > 0) {
+        const C2 x0 = BX0[off];
+        const C2 x1 = (p.nbx > 1) ? BX1[off] : czero<C2>();
+        v.x = p.bxc[0] * v.x + p.bxc[1] * x0.x + p.bxc[2] * x1.x;
+        v.y = p.bxc[0] * v.y + p.bxc[1] * x0.y + p.bxc[2] * x1.y;
+      }
       rb[q] = in ? v : czero<C2>();
     }
   };
@@ -205,13 +220,15 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmParams<T> p) {
   }
 }
 
-// Tile shapes per precision.
 template <typename T> struct GemmTile;
+// Tile shapes per precision.  FP32: 128x128 tile, eight waves of 64x32, and a
+// register budget of 128 per lane so that two workgroups share a CU (four
+// waves per SIMD hide the LDS and global latency of each other).
 template <> struct GemmTile<float> {
-  static constexpr int BM = 128, BN = 128, BK = 16, WM = 64, WN = 32, NT = 512;
+  static constexpr int BM = 128, BN = 128, BK = 16, WM = 64, WN = 32, NT = 512, WPE = 4;
 };
 template <> struct GemmTile<double> {
-  static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, NT = 256;
+  static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, NT = 256, WPE = 2;
 };
 
 template <typename T> GemmParams<T> gemm_params(int M, int N, int K, int batch) {
@@ -234,8 +251,8 @@ hipError_t launch_cgemm(const GemmParams<T>& p, hipStream_t stream, int64_t acti
   if (active < 0) active = p.batch;
   LaunchTimer tm;
   tm.begin(stream);
-  hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT>), dim3(unsigned(blocks)), dim3(G::NT),
-                     0, stream, p);
+  hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT, G::WPE>), dim3(unsigned(blocks)),
+                     dim3(G::NT), 0, stream, p);
   const hipError_t e = hipGetLastError();
   if (tm.on) {
     const double mn = double(p.M) * p.N, es = double(sizeof(typename Cx<T>::t));

@@ -210,20 +210,6 @@ __global__ __launch_bounds__(256) void scale_kernel(const C2* __restrict__ omega
   }
 }
 
-// Y = a X3 + b X2 + c X1, elementwise over n complex numbers.
-template <typename T>
-__global__ void lincomb3_kernel(typename Cx<T>::t* __restrict__ Y, const typename Cx<T>::t* __restrict__ X3,
-                                const typename Cx<T>::t* __restrict__ X2,
-                                const typename Cx<T>::t* __restrict__ X1, int64_t n, T a, T bb, T c) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const auto x3 = X3[i], x2 = X2[i], x1 = X1[i];
-  typename Cx<T>::t y;
-  y.x = a * x3.x + bb * x2.x + c * x1.x;
-  y.y = a * x3.y + bb * x2.y + c * x1.y;
-  Y[i] = y;
-}
-
 // R = aug[:, d:2d] written (cast) to the buffer where the squarings must start
 // so that the last one lands in U: U if s is even (or no squaring), else P1.
 template <typename C2>

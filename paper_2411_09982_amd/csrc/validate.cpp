@@ -58,12 +58,12 @@ Check check_generators(const void* H0, const void* Hk, int64_t d, int64_t K, int
   return Check::ok();
 }
 
-// expm workspace, per item: seven d x d matrices in dtype (A, A^2, A^4, A^6, two
-// polynomial terms, V), one d x 2d augmented system in C128, d pivots (int32).
+// expm workspace, per item: six d x d matrices in dtype (A, A^2, A^4, A^6, W, V),
+// one d x 2d augmented system in C128, d pivots (int32).
 // Header: per-item FP64 norm slot, int32 squaring count.
 size_t expm_item_bytes(int64_t d, int dtype) {
   size_t dd = size_t(d) * size_t(d);
-  return 7 * align256(dd * elem_bytes(dtype)) + align256(2 * dd * 16) + align256(size_t(d) * 4);
+  return 6 * align256(dd * elem_bytes(dtype)) + align256(2 * dd * 16) + align256(size_t(d) * 4);
 }
 
 size_t expm_header_bytes(int64_t batch) {

@@ -1,0 +1,51 @@
+"""Continuous batching on the GPU: every job's result is the same alone and in the mix."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+from tests.test_gpu_parity import say
+
+pytestmark = pytest.mark.gpu
+
+q = pytest.importorskip("paper_2411_09982_amd")
+from paper_2411_09982_amd.serve import Request, Server, max_overlap, poisson_requests  # noqa: E402
+
+CHUNK = 8
+
+
+def _make(i, g):
+    d = int(g.choice([8, 33, 64, 100]))
+    K = int(g.integers(1, 3))
+    M = int(g.choice([12, 30]))
+    order = int(g.integers(1, 3))
+    prec = "c64" if g.random() < 0.5 else "c128"
+    w = wl.random_system(d, K, M * 5, M, order, config_id=700 + i, drift_scale=15.0, drive_scale=3.0)
+    return Request(i, w.H0, w.Hk, w.u, w.dt_sample, M, order, prec, w.psi0)
+
+
+def test_mix_equals_alone_and_oracle():
+    reqs = poisson_requests(12, 300.0, 11, _make)
+    srv = Server(budget_bytes=1, max_slots=3, chunk=CHUNK)
+    sizes = sorted(srv.bytes_for(r) for r in reqs)
+    srv.adm.budget = int(2.5 * sizes[len(sizes) // 2])      # some jobs must wait for memory
+    srv.adm.budget = max(srv.adm.budget, sizes[-1])
+    say(f"serving {len(reqs)} jobs, budget {srv.adm.budget} B, sizes {sizes[0]}..{sizes[-1]}")
+    res = srv.run(reqs)
+    assert sorted(res) == [r.rid for r in reqs]
+    say(f"  max jobs in flight {max_overlap(res)}")
+    dev = "cuda:0"
+    for r in reqs:
+        dtype = torch.complex64 if r.precision == "c64" else torch.complex128
+        alone = q.evolve(torch.from_numpy(r.H0).to(dev), torch.from_numpy(r.Hk).to(dev),
+                         torch.from_numpy(r.u).to(dev), r.dt_sample, r.M, r.order,
+                         psi0=torch.from_numpy(r.psi0).to(dev), dtype=dtype, chunk=CHUNK)
+        psi_alone = alone["psi"].cpu().numpy()
+        assert np.array_equal(psi_alone, res[r.rid].psi), r.rid        # bit-identical
+        ref = oracle.run(r.H0, r.Hk, r.u, r.dt_sample, r.M, r.order, psi0=r.psi0)
+        inf = abs(oracle.state_infidelity(ref["psi"], res[r.rid].psi))
+        # FP32: every interval may leave a radial error up to 2^s u (see the parity
+        # tests); over M intervals they add at worst linearly
+        tol = 1e-12 if r.precision == "c128" else max(1e-6, r.M * 2.0 ** res[r.rid].s_max * 2.0 ** -24)
+        assert inf <= tol, (r.rid, inf, tol)
