@@ -27,6 +27,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}   # MI355X dense FP32 / FP64 matrix peaks
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cgemm_f32_traffic_transmon_resonator_d1000.md")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2411_09982_amd", "csrc", "cgemm.hpp")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32 GEMM kernel from the committed rocprofv3 --pmc
+    summary, or None when the kernel source has changed since it was measured."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    sha = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
+    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("kernel_source_sha256:",
+                                                                                         "hbm_bytes_per_launch:")))
+    if fields.get("kernel_source_sha256", "").strip() != sha:
+        return None
+    return float(fields["hbm_bytes_per_launch"])
 HBM_PEAK_GBS = 8000.0
 DEFAULT_CHUNK = {"c64": 256, "c128": 128}          # intervals per expm chunk
 
@@ -42,6 +60,17 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-intervals", type=int, default=96, help="intervals in the CPU-oracle sample")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving mode: Poisson request streams through the continuous-batching server; "
+                         "prints one JSON line of latency percentiles per rate")
+    ap.add_argument("--serve-rates", default="10,100,1000")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-dmax", type=int, default=2048)
+    ap.add_argument("--serve-mmax", type=int, default=1024)
+    ap.add_argument("--sweep", action="store_true",
+                    help="batched-sweep mode: 512 transmon-chain instances, d in {16..512}, M = 256, order 2; "
+                         "prints one JSON line")
+    ap.add_argument("--sweep-jobs", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
@@ -173,10 +202,77 @@ def cpu_baseline(w, n_int):
                        f"commutator basis + eigh propagators + state chain, {el:.1f} s"), U, psi
 
 
+def serve(a):
+    """Latency under Poisson arrivals: d ~ U{64..dmax}, M ~ U{64..mmax}, order 1 or 2,
+    FP32 or FP64 per request, admitted by an HBM budget of 200 GB, up to 8 in flight."""
+    import torch
+    import workloads as wl
+    from paper_2411_09982_amd.serve import Request, Server, latency_percentiles, max_overlap, poisson_requests
+
+    def make(i, g):
+        d = int(g.integers(64, a.serve_dmax + 1))
+        M = int(g.integers(64, a.serve_mmax + 1))
+        order = int(g.integers(1, 3))
+        prec = "c64" if g.random() < 0.5 else "c128"
+        w = wl.serving_request_system(d, M, order, g)
+        return Request(i, w.H0, w.Hk, w.u, w.dt_sample, M, order, prec, w.psi0)
+
+    for rate in [float(x) for x in a.serve_rates.split(",")]:
+        reqs = poisson_requests(a.serve_requests, rate, 2411 + int(rate), make)
+        srv = Server(budget_bytes=200 << 30, max_slots=8, chunk=64)
+        t0 = time.perf_counter()
+        res = srv.run(reqs)
+        wall = time.perf_counter() - t0
+        lat = latency_percentiles(res)
+        print(json.dumps(dict(metric="serving latency (Magnus propagation requests)", rate_req_s=rate,
+                              requests=len(reqs), p50_ms=round(lat["p50_ms"], 1), p99_ms=round(lat["p99_ms"], 1),
+                              wall_s=round(wall, 2), completed_req_s=round(len(reqs) / wall, 2),
+                              max_in_flight=max_overlap(res), d_range=[64, a.serve_dmax],
+                              M_range=[64, a.serve_mmax], data="synthetic")), flush=True)
+        del srv
+        torch.cuda.empty_cache()
+
+
+def sweep(a):
+    """Interval propagators/s over a sweep of uneven-dimension jobs (grouped by d)."""
+    import torch
+    import workloads as wl
+    from paper_2411_09982_amd.sweep import Sweep
+    jobs = wl.sweep_instances(a.sweep_jobs)
+    dtype = torch.complex64 if a.dtype == "c64" else torch.complex128
+    sw = Sweep(jobs, dtype)
+    for _ in range(max(a.warmup, 0)):
+        sw.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per = {}
+    for _ in range(a.steps):
+        for d, t in sw.run().items():
+            per[d] = per.get(d, 0.0) + t
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / a.steps
+    n_int = sum(j.M for j in jobs)
+    counts = {}
+    for j in jobs:
+        counts[j.d] = counts.get(j.d, 0) + 1
+    print(json.dumps(dict(metric="batched sweep: interval propagators/s", value=round(n_int / el, 1),
+                          unit="interval propagators/s", ms_per_step=round(1000 * el, 1), steps=a.steps,
+                          jobs=len(jobs), intervals=n_int, dtype=a.dtype, data="synthetic",
+                          jobs_per_d={str(k): v for k, v in sorted(counts.items())},
+                          ms_per_d={str(k): round(1000 * v / a.steps, 1) for k, v in sorted(per.items())})),
+          flush=True)
+
+
 def main():
     a = parse()
+    if a.sweep:
+        sweep(a)
+        return
     if a.copy_calibration:
         copy_calibration()
+        return
+    if a.serve:
+        serve(a)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this path has no multi-GPU mode",
@@ -198,7 +294,7 @@ def main():
     achieved = k["flops"] / (k["ms"] * 1e-3) / 1e12 if k["ms"] > 0 else 0.0
     peak = MFMA_PEAK_TFLOPS[a.dtype]
     roof = dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
-                frac=round(achieved / peak, 4), traffic=None,
+                frac=round(achieved / peak, 4), traffic=measured_traffic() if a.dtype == "c64" else None,
                 kernel=("cgemm_kernel<float,...> (Pade products, squarings)" if a.dtype == "c64"
                         else "cgemm_kernel<double,...> (Pade products, squarings, LU updates)"),
                 launches=k["launches"], avg_launch_ms=round(k["ms"] / max(k["launches"], 1), 4),

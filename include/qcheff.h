@@ -167,6 +167,19 @@ int qcheff_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, v
                      void* traj, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * qcheff_propagate_batched - B independent state chains of equal dimension
+ * (parameter sweeps, batches of jobs): chain b computes
+ * x[b] <- U[b][M-1] ... U[b][0] x[b], the stroboscopic evolution of Sec. 4.1.
+ *
+ *   U          [B][M][d][d], device, dtype.
+ *   x          [B][d] complex128 (FP64 states, products accumulate in FP64), in/out.
+ *   d          1 .. 2048 (each chain's two state vectors are held in LDS).
+ *   One workgroup per chain walks all M intervals; no workspace.
+ *   Returns QCHEFF_OK, QCHEFF_EINVAL, QCHEFF_EDEVICE.
+ */
+int qcheff_propagate_batched(const void* U, int64_t B, int64_t M, int64_t d, int dtype, void* x, void* stream);
+
+/*
  * qcheff_workspace_bytes - workspace needed by `fn` (QCHEFF_FN_*):
  *   GENERATORS: (batch, K, order, d) -> commutator basis bytes (0 for order 1);
  *   EXPM:       bytes to process `batch` items at once (per-item size x batch);

@@ -59,7 +59,9 @@ def lib() -> ctypes.CDLL:
                                            ctypes.c_size_t, ctypes.c_uint, vp]
     L.qcheff_expm_batched.argtypes = [vp, i64, i64, i32, vp, vp, vp, ctypes.c_size_t, vp]
     L.qcheff_propagate.argtypes = [vp, i64, i64, i32, i32, vp, vp, vp, ctypes.c_size_t, vp]
-    for f in ("qcheff_magnus_coeffs", "qcheff_magnus_generators", "qcheff_expm_batched", "qcheff_propagate"):
+    L.qcheff_propagate_batched.argtypes = [vp, i64, i64, i64, i32, vp, vp]
+    for f in ("qcheff_magnus_coeffs", "qcheff_magnus_generators", "qcheff_expm_batched", "qcheff_propagate",
+              "qcheff_propagate_batched"):
         getattr(L, f).restype = i32
     L.qcheff_workspace_bytes.argtypes = [i32, i64, i64, i64, i32, i32]
     L.qcheff_workspace_bytes.restype = ctypes.c_size_t
@@ -177,6 +179,16 @@ def propagate(U, mode: int, x, traj=None, ws=None, stream=None):
     _check("qcheff_propagate", lib().qcheff_propagate(
         _ptr(U), M, d, dt, mode, _ptr(x), _ptr(traj), _ptr(ws), 0 if ws is None else ws.numel(),
         _stream(stream)))
+    return x
+
+
+def propagate_batched(U, x, stream=None):
+    """B chains at once (qcheff_propagate_batched): U [B][M][d][d], x [B][d] complex128, in place."""
+    _dev(U, "U")
+    _dev(x, "x")
+    B, M, d = U.shape[0], U.shape[1], U.shape[-1]
+    _check("qcheff_propagate_batched", lib().qcheff_propagate_batched(
+        _ptr(U), B, M, d, _DTYPES[U.dtype], _ptr(x), _stream(stream)))
     return x
 
 

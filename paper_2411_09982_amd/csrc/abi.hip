@@ -5,6 +5,9 @@
 #include <algorithm>
 #include <cmath>
 #include <atomic>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -13,6 +16,7 @@
 #include "cgemm.hpp"
 #include "kernels.hpp"
 #include "lu.hpp"
+#include "expm_small.hpp"
 #include "validate.hpp"
 
 namespace qcheff {
@@ -90,6 +94,90 @@ void pade_coefficients(int m, double* b) {
 // (about 15 at this norm, 270 at twice it), which costs more accuracy than the
 // squaring it saves.
 constexpr double kTheta13 = 5.371920351148152;
+
+// -------------------------------------------------------------- tile tuner
+//
+// The square batched products of one exponential call all share a shape.  The
+// first call for a (precision, d) pair times every tile configuration on the
+// chunk's own A*A product (two launches each, the second one timed with HIP
+// events) and keeps the fastest for the rest of the process.  Every
+// configuration accumulates each output element over k in the same order, so
+// the choice changes speed only, never a bit of the result.
+// QCHEFF_AUTOTUNE=0 replaces the timing with a size rule; QCHEFF_TUNE_FILE
+// names a text file of "precision d cfg" lines read at first use and appended
+// to after each new decision.
+std::mutex g_tune_mu;
+std::map<std::pair<int, int64_t>, int> g_tune;
+bool g_tune_loaded = false;
+
+int rule_cfg(int64_t d) { return d <= 96 ? 1 : 0; }
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* f = std::getenv("QCHEFF_TUNE_FILE");
+  if (!f) return;
+  if (FILE* fp = std::fopen(f, "r")) {
+    int prec, cfg;
+    long long d;
+    while (std::fscanf(fp, "%d %lld %d", &prec, &d, &cfg) == 3)
+      if (cfg == 0 || cfg == 1) g_tune[{prec, int64_t(d)}] = cfg;
+    std::fclose(fp);
+  }
+}
+
+void tune_store_locked(int prec, int64_t d, int cfg) {
+  g_tune[{prec, d}] = cfg;
+  const char* f = std::getenv("QCHEFF_TUNE_FILE");
+  if (!f) return;
+  if (FILE* fp = std::fopen(f, "a")) {
+    std::fprintf(fp, "%d %lld %d\n", prec, (long long)d, cfg);
+    std::fclose(fp);
+  }
+}
+
+template <typename T>
+int square_cfg(int64_t d, int64_t nb, const typename Cx<T>::t* A, typename Cx<T>::t* scratch, hipStream_t st,
+               int* cfg_out) {
+  const int prec = sizeof(T) == 8 ? QCHEFF_C128 : QCHEFF_C64;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find({prec, d});
+    if (it != g_tune.end()) {
+      *cfg_out = it->second;
+      return QCHEFF_OK;
+    }
+  }
+  const char* env = std::getenv("QCHEFF_AUTOTUNE");
+  int best = rule_cfg(d);
+  if (!(env && env[0] == '0')) {
+    float best_ms = 3.4e38f;
+    hipEvent_t e0, e1;
+    QC_HIP(hipEventCreate(&e0));
+    QC_HIP(hipEventCreate(&e1));
+    for (int cfg = 0; cfg < 2; ++cfg) {
+      auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
+      p.A = A; p.lda = d; p.sA = d * d;
+      p.B = A; p.ldb = d; p.sB = d * d;
+      p.C = scratch; p.ldc = d; p.sC = d * d;
+      QC_HIP((launch_cgemm<T>(p, st, 0)));
+      QC_HIP(hipEventRecord(e0, st));
+      QC_HIP((launch_cgemm<T>(p, st, 0)));
+      QC_HIP(hipEventRecord(e1, st));
+      QC_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      QC_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) { best_ms = ms; best = cfg; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_store_locked(prec, d, best);
+  *cfg_out = best;
+  return QCHEFF_OK;
+}
 
 // ------------------------------------------------------------------- coeffs
 int run_coeffs(const double* u, int64_t K, int64_t N, double dt, int64_t M, int order, double* c1,
@@ -199,10 +287,10 @@ template <typename T> bool carve_expm(void* ws, size_t bytes, int64_t chunk, int
 // out = A B (+ sum_i xc[i] X_i + gamma I) over a batch of d x d items; with bc,
 // the right operand is bc[0] X_0 + bc[1] X_1 + bc[2] X_2 instead of B.
 template <typename T>
-int gemm_sq(typename Cx<T>::t* out, const typename Cx<T>::t* A, const typename Cx<T>::t* B, int64_t d,
+int gemm_sq(int cfg, typename Cx<T>::t* out, const typename Cx<T>::t* A, const typename Cx<T>::t* B, int64_t d,
             int64_t nb, hipStream_t st, int nx = 0, const typename Cx<T>::t* const* X = nullptr,
             const T* xc = nullptr, T gamma = T(0), const T* bc = nullptr) {
-  auto p = gemm_params<T>(int(d), int(d), int(d), int(nb));
+  auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
   const int64_t dd = d * d;
   p.A = A; p.lda = d; p.sA = dd;
   p.B = B; p.ldb = d; p.sB = dd;
@@ -238,7 +326,7 @@ struct LuCtx {
 int lu_gemm_update(const LuCtx& c, int64_t r0, int64_t r1, int64_t c0, int64_t c1, int64_t k0, int64_t k1) {
   // A[r0:r1, c0:c1] -= A[r0:r1, k0:k1] * A[k0:k1, c0:c1]
   if (r1 <= r0 || c1 <= c0 || k1 <= k0) return QCHEFF_OK;
-  auto p = gemm_params<double>(int(r1 - r0), int(c1 - c0), int(k1 - k0), int(c.nb));
+  auto p = gemm_params<double>(int(r1 - r0), int(c1 - c0), int(k1 - k0), int(c.nb), rule_cfg(c.d));
   p.A = c.aug + r0 * c.ld + k0; p.lda = c.ld; p.sA = c.stride;
   p.B = c.aug + k0 * c.ld + c0; p.ldb = c.ld; p.sB = c.stride;
   p.C = c.aug + r0 * c.ld + c0; p.ldc = c.ld; p.sC = c.stride;
@@ -347,21 +435,22 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
                      kTheta13, w.s_ws, s_out, w.smax);
   QC_HIP(hipGetLastError());
   C2 *A = w.X[0], *A2 = w.X[1], *A4 = w.X[2], *A6 = w.X[3], *W = w.X[4], *V = w.X[5];
-  int r;
-  if ((r = gemm_sq<T>(A2, A, A, d, nb, st))) return r;
-  if ((r = gemm_sq<T>(A4, A2, A2, d, nb, st))) return r;
-  if ((r = gemm_sq<T>(A6, A4, A2, d, nb, st))) return r;
+  int r, cfg = 0;
+  if ((r = square_cfg<T>(d, nb, A, W, st, &cfg))) return r;
+  if ((r = gemm_sq<T>(cfg, A2, A, A, d, nb, st))) return r;
+  if ((r = gemm_sq<T>(cfg, A4, A2, A2, d, nb, st))) return r;
+  if ((r = gemm_sq<T>(cfg, A6, A4, A2, d, nb, st))) return r;
   // W = A6 (b13 A6 + b11 A4 + b9 A2) + b7 A6 + b5 A4 + b3 A2 + b1 I   (U = A W)
   // V = A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I
   // The right operand's linear combination is formed as the GEMM loads it.
   const C2* Xs[3] = {A6, A4, A2};
   const T xw[3] = {c[7], c[5], c[3]}, bw[3] = {c[13], c[11], c[9]};
-  if ((r = gemm_sq<T>(W, A6, A6, d, nb, st, 3, Xs, xw, c[1], bw))) return r;
+  if ((r = gemm_sq<T>(cfg, W, A6, A6, d, nb, st, 3, Xs, xw, c[1], bw))) return r;
   const T xv[3] = {c[6], c[4], c[2]}, bv[3] = {c[12], c[10], c[8]};
-  if ((r = gemm_sq<T>(V, A6, A6, d, nb, st, 3, Xs, xv, c[0], bv))) return r;
+  if ((r = gemm_sq<T>(cfg, V, A6, A6, d, nb, st, 3, Xs, xv, c[0], bv))) return r;
   // [q | p] = [V - A W | V + A W] in FP64
   {
-    auto p = gemm_params<T>(int(d), int(d), int(d), int(nb));
+    auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
     p.A = A; p.lda = d; p.sA = dd;
     p.B = W; p.ldb = d; p.sB = dd;
     p.C = V; p.ldc = d; p.sC = dd;
@@ -381,7 +470,7 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
   const int smax = std::max(0, *std::max_element(s_host.begin(), s_host.end()));
   for (int step = 0; step < smax; ++step) {
     const int64_t active = std::count_if(s_host.begin(), s_host.end(), [step](int s) { return s > step; });
-    auto p = gemm_params<T>(int(d), int(d), int(d), int(nb));
+    auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
     p.lda = d; p.ldb = d; p.ldc = d;
     p.sA = dd; p.sB = dd; p.sC = dd;
     p.sq = 1; p.sq_s = w.s_ws; p.sq_step = step; p.sq_p0 = U; p.sq_p1 = A;
@@ -394,6 +483,14 @@ template <typename T>
 int run_expm(const void* omega, int64_t batch, int64_t d, void* U, int32_t* s_out, void* ws, size_t ws_bytes,
              int dtype, hipStream_t st) {
   using C2 = typename Cx<T>::t;
+  if (d <= kSmallD) {
+    // one workgroup per item, everything in LDS; no workspace and no host sync
+    const unsigned grid = unsigned(std::min<int64_t>(batch, 256 * 8));
+    hipLaunchKernelGGL(expm_small_kernel<T>, dim3(grid), dim3(256), 0, st, static_cast<const C2*>(omega),
+                       static_cast<C2*>(U), s_out, int(d), int(batch), kTheta13);
+    QC_HIP(hipGetLastError());
+    return QCHEFF_OK;
+  }
   const int64_t chunk = expm_chunk(ws_bytes, batch, d, dtype);
   const int64_t dd = d * d;
   ExpmWs<T> w;
@@ -505,6 +602,22 @@ int qcheff_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, v
   hipStream_t st = static_cast<hipStream_t>(stream);
   return dtype == QCHEFF_C128 ? run_propagate<double>(U, M, d, mode, x, traj, ws, st)
                               : run_propagate<float>(U, M, d, mode, x, traj, ws, st);
+}
+
+int qcheff_propagate_batched(const void* U, int64_t B, int64_t M, int64_t d, int dtype, void* x, void* stream) {
+  Check c = check_propagate_batched(U, B, M, d, dtype, x);
+  if (c.status) return fail(c);
+  if (B == 0 || M == 0) return QCHEFF_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t lds = size_t(2 * d) * sizeof(double2);
+  if (dtype == QCHEFF_C128)
+    hipLaunchKernelGGL(chain_batched_kernel<double2>, dim3(unsigned(B)), dim3(256), lds, st,
+                       static_cast<const double2*>(U), static_cast<double2*>(x), int(M), int(d));
+  else
+    hipLaunchKernelGGL(chain_batched_kernel<float2>, dim3(unsigned(B)), dim3(256), lds, st,
+                       static_cast<const float2*>(U), static_cast<double2*>(x), int(M), int(d));
+  QC_HIP(hipGetLastError());
+  return QCHEFF_OK;
 }
 
 size_t qcheff_workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int order, int dtype) {

@@ -38,12 +38,13 @@ template <typename T> struct GemmParams {
   const C2* B; int64_t ldb, sB;
   C2* C; int64_t ldc, sC;
   T alpha, beta, gamma;
+  int cfg;                      // tile configuration (GemmTile<T, cfg>)
   int epi;                      // EPI_STD or EPI_AUG
   int sq;                       // 1: squaring mode (sq_* fields)
   int nx;                       // number of X terms (0..3); X share C's ld and stride
   const C2* X[3]; T xc[3];
-  // B operand as a linear combination: B_eff = bxc[0] B + sum_{i < nbx} bxc[i+1] BX[i]
-  // (BX share B's ld and stride); nbx = 0 uses B as it is
+  // B operand as a linear combination: B_eff = bxc[0] B + bxc[1] BX[0] + bxc[2] BX[1]
+  // (BX share B's ld and stride) when nbx = 2; nbx = 0 uses B as it is
   int nbx;
   const C2* BX[2]; T bxc[3];
   // EPI_AUG target (FP64 always)
@@ -52,7 +53,7 @@ template <typename T> struct GemmParams {
   const int* sq_s; int sq_step; C2* sq_p0; C2* sq_p1;
 };
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int WAVES_PER_EU>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int WAVES_PER_EU, bool BCOMB>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU))) void cgemm_kernel(
     GemmParams<T> p) {
   using C2 = typename Cx<T>::t;
@@ -91,8 +92,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
     B = p.B + b * p.sB;
     C = p.C + b * p.sC;
   }
-  const C2* BX0 = p.nbx > 0 ? p.BX[0] + b * p.sB : B;
-  const C2* BX1 = p.nbx > 1 ? p.BX[1] + b * p.sB : B;
+  const C2* BX0 = BCOMB ? p.BX[0] + b * p.sB : B;
+  const C2* BX1 = BCOMB ? p.BX[1] + b * p.sB : B;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -107,7 +108,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
       for (int e = 0; e < 4; ++e) { accr[i][j][e] = T(0); acci[i][j][e] = T(0); }
 
   // Loads are unconditional: an out-of-range element reads a clamped, valid
-  // address and is replaced by zero, so no load sits behind a branch.
+  // address and is replaced by zero, so no load sits behind a branch.  Offsets
+  // inside one item fit 32 bits (the host keeps ld * rows below 2^31).
+  const int lda = int(p.lda), ldb = int(p.ldb);
   C2 ra[LA], rb[LB];
   auto load = [&](int k0) {
 #pragma unroll
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
       const int e = tid + NT * q, r = e / BK, k = e % BK;
       const int gr = row0 + r, gk = k0 + k;
       const bool in = gr < p.M && gk < p.K;
-      const C2 v = A[int64_t(min(gr, p.M - 1)) * p.lda + max(0, min(gk, p.K - 1))];
+      const C2 v = A[min(gr, p.M - 1) * lda + max(0, min(gk, p.K - 1))];
       ra[q] = in ? v : czero<C2>();
     }
 #pragma unroll
@@ -123,11 +126,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
       const int e = tid + NT * q, k = e / BN, c = e % BN;
       const int gk = k0 + k, gc = col0 + c;
       const bool in = gk < p.K && gc < p.N;
-      const int64_t off = int64_t(max(0, min(gk, p.K - 1))) * p.ldb + min(gc, p.N - 1);
+      const int off = max(0, min(gk, p.K - 1)) * ldb + min(gc, p.N - 1);
       C2 v = B[off];
-      if (p.nbx > 0) {
-        const C2 x0 = BX0[off];
-        const C2 x1 = (p.nbx > 1) ? BX1[off] : czero<C2>();
+      if constexpr (BCOMB) {
+        const C2 x0 = BX0[off], x1 = BX1[off];
         v.x = p.bxc[0] * v.x + p.bxc[1] * x0.x + p.bxc[2] * x1.x;
         v.y = p.bxc[0] * v.y + p.bxc[1] * x0.y + p.bxc[2] * x1.y;
       }
@@ -164,13 +166,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
       for (int i = 0; i < TM; ++i) a[i] = As[cur][kk + lr][wm + i * 16 + lc];
 #pragma unroll
       for (int j = 0; j < TN; ++j) bb[j] = Bs[cur][kk + lr][wn + j * 16 + lc];
+      // the minus sign of Ai Bi rides on the operand with fewer fragments
+      T nbi[TN];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) nbi[j] = -bb[j].y;
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        const T ar = a[i].x, ai = a[i].y, nai = -a[i].y;
+        const T ar = a[i].x, ai = a[i].y;
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
           accr[i][j] = mfma16(ar, bb[j].x, accr[i][j]);
-          accr[i][j] = mfma16(nai, bb[j].y, accr[i][j]);
+          accr[i][j] = mfma16(ai, nbi[j], accr[i][j]);
           acci[i][j] = mfma16(ar, bb[j].y, acci[i][j]);
           acci[i][j] = mfma16(ai, bb[j].x, acci[i][j]);
         }
@@ -220,39 +226,64 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
   }
 }
 
-template <typename T> struct GemmTile;
-// Tile shapes per precision.  FP32: 128x128 tile, eight waves of 64x32, and a
-// register budget of 128 per lane so that two workgroups share a CU (four
-// waves per SIMD hide the LDS and global latency of each other).
-template <> struct GemmTile<float> {
+// Tile configurations per precision: cfg 0 is the large tile, cfg 1 the small
+// one (for small matrices, where the large tile would be mostly padding).
+// FP32 cfg 0: 128x128 tile, eight waves of 64x32, at most 128 registers per lane
+// so that two workgroups share a CU (four waves per SIMD hide each other's LDS
+// and global latency).
+template <typename T, int CFG> struct GemmTile;
+template <> struct GemmTile<float, 0> {
   static constexpr int BM = 128, BN = 128, BK = 16, WM = 64, WN = 32, NT = 512, WPE = 4;
 };
-template <> struct GemmTile<double> {
+template <> struct GemmTile<float, 1> {
+  static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, NT = 256, WPE = 4;
+};
+template <> struct GemmTile<double, 0> {
   static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, NT = 256, WPE = 2;
 };
+template <> struct GemmTile<double, 1> {
+  static constexpr int BM = 32, BN = 32, BK = 16, WM = 16, WN = 16, NT = 256, WPE = 4;
+};
 
-template <typename T> GemmParams<T> gemm_params(int M, int N, int K, int batch) {
+template <typename T> GemmParams<T> gemm_params(int M, int N, int K, int batch, int cfg = 0) {
   GemmParams<T> p{};
   p.M = M; p.N = N; p.K = K; p.batch = batch;
-  p.tiles_m = (M + GemmTile<T>::BM - 1) / GemmTile<T>::BM;
-  p.tiles_n = (N + GemmTile<T>::BN - 1) / GemmTile<T>::BN;
+  p.cfg = cfg;
+  const int bm = cfg ? GemmTile<T, 1>::BM : GemmTile<T, 0>::BM;
+  const int bn = cfg ? GemmTile<T, 1>::BN : GemmTile<T, 0>::BN;
+  p.tiles_m = (M + bm - 1) / bm;
+  p.tiles_n = (N + bn - 1) / bn;
   p.alpha = T(1); p.beta = T(0); p.gamma = T(0); p.nx = 0;
   return p;
+}
+
+template <typename T, int CFG> void launch_tile(const GemmParams<T>& p, unsigned blocks, hipStream_t stream) {
+  using G = GemmTile<T, CFG>;
+  if (p.nbx > 0)
+    hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT, G::WPE, true>), dim3(blocks),
+                       dim3(G::NT), 0, stream, p);
+  else
+    hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT, G::WPE, false>), dim3(blocks),
+                       dim3(G::NT), 0, stream, p);
 }
 
 // Launch; `active` is the number of items that do work (squaring mode skips
 // the others) and feeds the timing record's algorithmic flop and byte counts.
 template <typename T>
 hipError_t launch_cgemm(const GemmParams<T>& p, hipStream_t stream, int64_t active = -1) {
-  using G = GemmTile<T>;
   if (p.M <= 0 || p.N <= 0 || p.batch <= 0) return hipSuccess;
+  if (p.lda * int64_t(p.M) >= (int64_t(1) << 31) || p.ldb * int64_t(p.K) >= (int64_t(1) << 31) ||
+      p.ldc * int64_t(p.M) >= (int64_t(1) << 31))
+    return hipErrorInvalidValue;
   const int64_t blocks = int64_t(p.tiles_m) * p.tiles_n * p.batch;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   if (active < 0) active = p.batch;
   LaunchTimer tm;
   tm.begin(stream);
-  hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT, G::WPE>), dim3(unsigned(blocks)),
-                     dim3(G::NT), 0, stream, p);
+  if (p.cfg == 1)
+    launch_tile<T, 1>(p, unsigned(blocks), stream);
+  else
+    launch_tile<T, 0>(p, unsigned(blocks), stream);
   const hipError_t e = hipGetLastError();
   if (tm.on) {
     const double mn = double(p.M) * p.N, es = double(sizeof(typename Cx<T>::t));

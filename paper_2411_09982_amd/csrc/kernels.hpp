@@ -251,4 +251,45 @@ __global__ __launch_bounds__(256) void matvec_kernel(const C2* __restrict__ U, c
   if (lane == 0) y[row] = make_double2(ar, ai);
 }
 
+// B independent state chains at once: chain b runs psi <- U[b][n] psi for
+// n = 0..M-1 inside one workgroup (one wave per row at a time, the state in
+// LDS in FP64), so a single launch covers every chain and every interval.
+template <typename C2>
+__global__ __launch_bounds__(256) void chain_batched_kernel(const C2* __restrict__ U, double2* __restrict__ x,
+                                                            int M, int d) {
+  extern __shared__ double2 sv[];   // [2][d]
+  const int b = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t dd = int64_t(d) * d;
+  double2* xb = x + int64_t(b) * d;
+  double2* cur = sv;
+  double2* nxt = sv + d;
+  for (int i = threadIdx.x; i < d; i += 256) cur[i] = xb[i];
+  __syncthreads();
+  const C2* Ub = U + int64_t(b) * M * dd;
+  for (int n = 0; n < M; ++n) {
+    const C2* Un = Ub + n * dd;
+    for (int row = wave; row < d; row += 4) {
+      const C2* ur = Un + int64_t(row) * d;
+      double ar = 0.0, ai = 0.0;
+      for (int c = lane; c < d; c += 64) {
+        const C2 u = ur[c];
+        const double2 v = cur[c];
+        ar += double(u.x) * v.x - double(u.y) * v.y;
+        ai += double(u.x) * v.y + double(u.y) * v.x;
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        ar += __shfl_down(ar, off);
+        ai += __shfl_down(ai, off);
+      }
+      if (lane == 0) nxt[row] = make_double2(ar, ai);
+    }
+    __syncthreads();
+    double2* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  for (int i = threadIdx.x; i < d; i += 256) xb[i] = cur[i];
+}
+
 }  // namespace qcheff

@@ -123,6 +123,16 @@ Check check_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, 
   return Check::ok();
 }
 
+Check check_propagate_batched(const void* U, int64_t B, int64_t M, int64_t d, int dtype, const void* x) {
+  if (B < 0 || M < 0) return Check::fail(QCHEFF_EINVAL, "B and M must be >= 0");
+  if (d < 1 || d > 2048) return Check::fail(QCHEFF_EINVAL, "d must be in [1, 2048] (the state sits in LDS)");
+  if (elem_bytes(dtype) == 0) return Check::fail(QCHEFF_EINVAL, "unknown dtype");
+  if (B > 0x7fffffff) return Check::fail(QCHEFF_EINVAL, "B too large");
+  if (B > 0 && !x) return Check::fail(QCHEFF_EINVAL, "x must not be NULL");
+  if (B > 0 && M > 0 && !U) return Check::fail(QCHEFF_EINVAL, "U must not be NULL");
+  return Check::ok();
+}
+
 size_t workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int order, int dtype) {
   if (d < 1 || d > kMaxDim) return 0;
   switch (fn) {

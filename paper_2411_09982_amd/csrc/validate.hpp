@@ -36,6 +36,8 @@ Check check_expm(const void* omega, int64_t batch, int64_t d, int dtype, const v
 Check check_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, const void* x,
                       const void* traj, const void* ws, size_t ws_bytes);
 
+Check check_propagate_batched(const void* U, int64_t B, int64_t M, int64_t d, int dtype, const void* x);
+
 // Workspace layouts.  Each region starts on a 256-byte boundary.
 size_t align256(size_t n);
 size_t generators_ws_bytes(int64_t d, int64_t K, int order);

@@ -15,7 +15,7 @@ def test_exports_every_header_symbol():
     names = q.header_symbols()
     assert set(names) == {"qcheff_magnus_coeffs", "qcheff_magnus_generators", "qcheff_expm_batched",
                           "qcheff_propagate", "qcheff_workspace_bytes", "qcheff_last_error",
-                          "qcheff_timing_enable", "qcheff_timing_read"}
+                          "qcheff_timing_enable", "qcheff_timing_read", "qcheff_propagate_batched"}
     L = q.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -91,6 +91,17 @@ def test_propagate_validation():
     # product tree: ceil(M/2) + ceil(M/4) matrices of 256-byte-rounded size
     assert q.workspace_bytes(q.FN_PROPAGATE, 5, 4, 1, q.PRODUCT, q.C64) == (3 + 2) * 256
     assert q.workspace_bytes(9, 5, 4, 1, 1, q.C64) == 0
+
+
+def test_propagate_batched_validation():
+    L = q.lib()
+    p = L.qcheff_propagate_batched
+    assert p(FAKE, 2, 3, 0, q.C64, FAKE, None) == q.EINVAL
+    assert p(FAKE, 2, 3, 2049, q.C64, FAKE, None) == q.EINVAL
+    assert p(FAKE, 2, 3, 8, 9, FAKE, None) == q.EINVAL
+    assert p(FAKE, 2, 3, 8, q.C64, None, None) == q.EINVAL
+    assert p(None, 2, 3, 8, q.C64, FAKE, None) == q.EINVAL
+    assert p(None, 0, 3, 8, q.C64, None, None) == q.OK
 
 
 def test_timing_api_without_gpu():

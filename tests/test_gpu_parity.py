@@ -117,7 +117,7 @@ def test_generators_parity(d, K, order, dtype):
 
 # ------------------------------------------------------------- exponential
 
-EXPM_DIMS = [1, 2, 3, 7, 8, 16, 33, 64, 100, 128, 257]
+EXPM_DIMS = [1, 2, 3, 7, 8, 16, 17, 31, 32, 33, 64, 100, 128, 257]
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
@@ -165,9 +165,11 @@ def test_expm_parity_large(d, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
-def test_expm_chunked_alias_and_nonfinite(dtype):
-    say(f"expm chunking {dtype}")
-    d, B = 45, 7
+@pytest.mark.parametrize("d", [20, 45])
+def test_expm_chunked_alias_and_nonfinite(d, dtype):
+    # d <= 32 runs the fused one-workgroup kernel, larger d the batched path
+    say(f"expm chunking d={d} {dtype}")
+    B = 7
     Om = wl.random_skew_hermitian_batch(B, d, np.linspace(0.5, 300, B), config_id=77)
     om = gpu(Om).to(dtype)
     U1, s1 = q.expm_batched(om)                        # one chunk
@@ -247,3 +249,20 @@ def test_random_system_order2_end_to_end(dtype):
     assert np.all(oracle.propagator_infidelity(ref["U"], U) <= tol)
     assert oracle.state_infidelity(ref["psi"], host(out["psi"])) <= tol
     assert oracle.propagator_infidelity(ref["P"], host(out["P"]).astype(np.complex128)) <= tol
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("B,M,d", [(1, 1, 3), (5, 7, 3), (4, 9, 64), (3, 5, 130)])
+def test_propagate_batched_parity(B, M, d, dtype):
+    say(f"propagate_batched B={B} M={M} d={d} {dtype}")
+    Om = wl.random_skew_hermitian_batch(B * M, d, 2.0, config_id=900 + d)
+    Uo = oracle.expm_skew_hermitian(Om).reshape(B, M, d, d)
+    Ud = gpu(Uo).to(dtype)
+    Uref = host(Ud).astype(np.complex128)
+    psi0 = np.stack([wl.random_state(d, 40 + b) for b in range(B)])
+    x = gpu(psi0)
+    q.propagate_batched(Ud, x)
+    torch.cuda.synchronize()
+    for b in range(B):
+        ref = oracle.propagate_state(Uref[b], psi0[b])
+        assert np.abs(host(x)[b] - ref).max() <= 1e-13 * M * math.sqrt(d)

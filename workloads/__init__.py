@@ -275,6 +275,71 @@ def random_system(d: int, K: int, n_samples: int, M: int, order: int, config_id:
                     dict(t_total=t_total))
 
 
+def serving_request_system(d: int, M: int, order: int, g: np.random.Generator, samples_per_interval: int = 64,
+                           t_total: float = 50.0) -> Workload:
+    """One request of the serving stream: H0 = diag(2pi U[-1, 1]) + nearest-neighbour
+    coupling 2pi*0.02 (tridiagonal), one drive H_1 = (a + a^dag)/sqrt(d) with a
+    Gaussian envelope (sigma = T/5) on a carrier drawn from U[0.5, 1.5] GHz,
+    amplitude 2pi U[0.01, 0.1] GHz; T = 50 ns, 64 samples per interval."""
+    diag = TWO_PI * g.uniform(-1.0, 1.0, size=d)
+    H0 = np.diag(diag).astype(np.complex128)
+    off = np.full(d - 1, TWO_PI * 0.02)
+    H0 += np.diag(off, 1) + np.diag(off, -1)
+    a = destroy(d)
+    Hk = ((a + a.conj().T) / math.sqrt(d))[None]
+    N = M * samples_per_interval
+    t, dt = midpoints(N, t_total)
+    f = g.uniform(0.5, 1.5)
+    amp = TWO_PI * g.uniform(0.01, 0.1)
+    u = (amp * gaussian(t, t_total, t_total / 5.0) * np.cos(TWO_PI * f * t))[None]
+    psi0 = np.zeros(d, dtype=np.complex128)
+    psi0[0] = 1.0
+    return Workload(f"serving_d{d}_M{M}", H0, Hk, np.ascontiguousarray(u), dt, M, order, psi0,
+                    dict(f=f, amp=amp))
+
+
+SWEEP_FACTORS = {16: (4, 2), 32: (2, 5), 64: (4, 3), 128: (2, 7), 256: (4, 4), 512: (8, 3)}
+
+
+def transmon_chain(d: int, g: np.random.Generator, M: int = 256, samples_per_interval: int = 64,
+                   order: int = 2, t_total: float = 50.0) -> Workload:
+    """One instance of the batched sweep: a chain of Duffing transmons with
+    nearest-neighbour exchange, d = levels**sites (16 = 4^2, 32 = 2^5, 64 = 4^3,
+    128 = 2^7, 256 = 4^4, 512 = 8^3).  omega_j ~ U[4.5, 5.5]*2pi, alpha_j ~
+    U[-0.35, -0.25]*2pi, J ~ U[0.01, 0.02]*2pi GHz; 1-3 drives (b_j + b_j^dag) on
+    random sites with Gaussian envelopes (sigma = T/5) at the site frequency,
+    random phase, amplitude U[0.01, 0.1]*2pi GHz; T = 50 ns, 64 samples per interval."""
+    levels, sites = SWEEP_FACTORS[d]
+    dims = [levels] * sites
+    b = destroy(levels)
+    omegas = TWO_PI * g.uniform(4.5, 5.5, size=sites)
+    alphas = TWO_PI * g.uniform(-0.35, -0.25, size=sites)
+    J = TWO_PI * g.uniform(0.01, 0.02)
+    H0 = np.zeros((d, d), dtype=np.complex128)
+    B = [site_op(b, j, dims) for j in range(sites)]
+    for j in range(sites):
+        H0 += site_op(duffing(levels, omegas[j], alphas[j]), j, dims)
+    for j in range(sites - 1):
+        X = B[j] @ B[j + 1].conj().T
+        H0 += J * (X + X.conj().T)
+    K = int(g.integers(1, 4))
+    drive_sites = g.choice(sites, size=K, replace=True)
+    N = M * samples_per_interval
+    t, dt = midpoints(N, t_total)
+    env = gaussian(t, t_total, t_total / 5.0)
+    Hk = np.stack([B[j] + B[j].conj().T for j in drive_sites])
+    u = np.stack([TWO_PI * g.uniform(0.01, 0.1) * env * np.cos(omegas[j] * t + g.uniform(0, TWO_PI))
+                  for j in drive_sites])
+    return Workload(f"transmon_chain_d{d}", H0, Hk, np.ascontiguousarray(u), dt, M, order, basis_state(d, 0),
+                    dict(levels=levels, sites=sites, drive_sites=[int(x) for x in drive_sites]))
+
+
+def sweep_instances(n: int = 512, M: int = 256, config_id: int = 3, dims=(16, 32, 64, 128, 256, 512)) -> list:
+    """The batched sweep: n transmon-chain instances with d drawn uniformly from dims."""
+    g = rng(config_id)
+    return [transmon_chain(int(g.choice(dims)), g, M=M) for _ in range(n)]
+
+
 # The bench / parity configurations, by name.
 CONFIGS = {
     "transmon_duffing_d8": lambda: transmon_duffing(),
