@@ -26,7 +26,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}   # MI355X dense FP32 / FP64 matrix peaks
+# MI355X dense matrix peaks: FP32, FP64, and BF16 for the split-BF16 products
+MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6, "bf16x3": 2500.0}
+# BF16 MFMA flops executed per algorithmic flop of a split-BF16 product: each real
+# product is six BF16 part products
+BF16X3_PARTS = 6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cgemm_f32_traffic_transmon_resonator_d1000.md")
 GEMM_SOURCE = os.path.join(ROOT, "paper_2411_09982_amd", "csrc", "cgemm.hpp")
 
@@ -46,7 +50,7 @@ def measured_traffic():
         return None
     return float(fields["hbm_bytes_per_launch"])
 HBM_PEAK_GBS = 8000.0
-DEFAULT_CHUNK = {"c64": 256, "c128": 128}          # intervals per expm chunk
+DEFAULT_CHUNK = {"c64": 256, "c128": 128, "bf16x3": 256}   # intervals per expm chunk
 
 
 def parse():
@@ -55,7 +59,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="transmon10x_resonator100_d1000")
-    ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--dtype", default="c64", choices=["c64", "c128", "bf16x3"],
+                    help="c64: FP32 MFMA products; bf16x3: the same complex64 path with the products on BF16 "
+                         "MFMA (three-way split operands); c128: FP64 throughout")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-fp64-compare", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -107,8 +113,9 @@ class Job:
         import paper_2411_09982_amd as q
         self.q, self.torch, self.w = q, torch, w
         dev = "cuda:0"
-        self.dtype = torch.complex64 if dtype_name == "c64" else torch.complex128
-        code = q.C64 if dtype_name == "c64" else q.C128
+        self.dtype = torch.complex128 if dtype_name == "c128" else torch.complex64
+        self.bf16x3 = dtype_name == "bf16x3"
+        code = q.C128 if dtype_name == "c128" else q.C64
         d, K, M = w.d, w.K, w.M
         self.H0 = torch.from_numpy(w.H0).to(dev)
         self.Hk = torch.from_numpy(w.Hk).to(dev)
@@ -140,7 +147,7 @@ class Job:
         for c0 in range(0, w.M, self.chunk):
             c1 = min(w.M, c0 + self.chunk)
             U = self.omega[c0:c1]
-            q.expm_batched(U, U=U, s_out=self.s[c0:c1], ws=self.exp_ws)
+            q.expm_batched(U, U=U, s_out=self.s[c0:c1], ws=self.exp_ws, skew_hermitian=True, bf16x3=self.bf16x3)
             ev = torch.cuda.Event()
             ev.record(main)
             self.side.wait_event(ev)
@@ -169,6 +176,7 @@ def timed(job, steps, warmup, roofline=True):
     if roofline:
         kern["f32"] = q.timing_read(q.KERNEL_GEMM_F32)
         kern["f64"] = q.timing_read(q.KERNEL_GEMM_F64)
+        kern["bf16x3"] = q.timing_read(q.KERNEL_GEMM_BF16X3)
         q.timing_enable(False)
     return elapsed, times, kern
 
@@ -224,8 +232,13 @@ def serve(a):
         res = srv.run(reqs)
         wall = time.perf_counter() - t0
         lat = latency_percentiles(res)
+        props = sum(r.M for r in reqs)
         print(json.dumps(dict(metric="serving latency (Magnus propagation requests)", rate_req_s=rate,
                               requests=len(reqs), p50_ms=round(lat["p50_ms"], 1), p99_ms=round(lat["p99_ms"], 1),
+                              wait_p50_ms=round(lat["wait_p50_ms"], 1), wait_p99_ms=round(lat["wait_p99_ms"], 1),
+                              service_p50_ms=round(lat["service_p50_ms"], 1),
+                              service_p99_ms=round(lat["service_p99_ms"], 1),
+                              interval_propagators_s=round(props / wall, 1),
                               wall_s=round(wall, 2), completed_req_s=round(len(reqs) / wall, 2),
                               max_in_flight=max_overlap(res), d_range=[64, a.serve_dmax],
                               M_range=[64, a.serve_mmax], data="synthetic")), flush=True)
@@ -241,26 +254,32 @@ def sweep(a):
     jobs = wl.sweep_instances(a.sweep_jobs)
     dtype = torch.complex64 if a.dtype == "c64" else torch.complex128
     sw = Sweep(jobs, dtype)
-    for _ in range(max(a.warmup, 0)):
-        sw.run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    per = {}
-    for _ in range(a.steps):
-        for d, t in sw.run().items():
-            per[d] = per.get(d, 0.0) + t
-    torch.cuda.synchronize()
-    el = (time.perf_counter() - t0) / a.steps
     n_int = sum(j.M for j in jobs)
     counts = {}
     for j in jobs:
         counts[j.d] = counts.get(j.d, 0) + 1
-    print(json.dumps(dict(metric="batched sweep: interval propagators/s", value=round(n_int / el, 1),
-                          unit="interval propagators/s", ms_per_step=round(1000 * el, 1), steps=a.steps,
-                          jobs=len(jobs), intervals=n_int, dtype=a.dtype, data="synthetic",
-                          jobs_per_d={str(k): v for k, v in sorted(counts.items())},
-                          ms_per_d={str(k): round(1000 * v / a.steps, 1) for k, v in sorted(per.items())})),
-          flush=True)
+
+    def timed_runs(mode):
+        for _ in range(max(a.warmup, 0)):
+            sw.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        per = {}
+        for _ in range(a.steps):
+            for d, t in sw.run().items():
+                per[d] = per.get(d, 0.0) + t
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / a.steps
+        print(json.dumps(dict(metric="batched sweep: interval propagators/s", mode=mode, value=round(n_int / el, 1),
+                              unit="interval propagators/s", ms_per_step=round(1000 * el, 1), steps=a.steps,
+                              jobs=len(jobs), intervals=n_int, dtype=a.dtype, data="synthetic",
+                              jobs_per_d={str(k): v for k, v in sorted(counts.items())},
+                              ms_per_d={str(k): round(1000 * v / a.steps, 1) for k, v in sorted(per.items())})),
+              flush=True)
+
+    timed_runs("eager")
+    sw.capture()
+    timed_runs("hip graph per group")
 
 
 def main():
@@ -290,15 +309,18 @@ def main():
     ms = 1000.0 * elapsed / a.steps
     fl_step = flop_count(w, s_hist)
 
-    k = kern["f32"] if a.dtype == "c64" else kern["f64"]
-    achieved = k["flops"] / (k["ms"] * 1e-3) / 1e12 if k["ms"] > 0 else 0.0
+    k = kern["f32"] if a.dtype == "c64" else kern["bf16x3"] if a.dtype == "bf16x3" else kern["f64"]
+    executed = BF16X3_PARTS if a.dtype == "bf16x3" else 1    # MFMA flops per algorithmic flop
+    achieved = executed * k["flops"] / (k["ms"] * 1e-3) / 1e12 if k["ms"] > 0 else 0.0
     peak = MFMA_PEAK_TFLOPS[a.dtype]
     roof = dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
                 frac=round(achieved / peak, 4), traffic=measured_traffic() if a.dtype == "c64" else None,
-                kernel=("cgemm_kernel<float,...> (Pade products, squarings)" if a.dtype == "c64"
-                        else "cgemm_kernel<double,...> (Pade products, squarings, LU updates)"),
+                kernel={"c64": "cgemm_kernel<float,...> (Pade products, squarings)",
+                        "bf16x3": "cgemm_bf16x3_kernel (Pade products, squarings; BF16 MFMA flops executed, "
+                                  "6 per algorithmic flop)",
+                        "c128": "cgemm_kernel<double,...> (Pade products, squarings, LU updates)"}[a.dtype],
                 launches=k["launches"], avg_launch_ms=round(k["ms"] / max(k["launches"], 1), 4),
-                flops_per_launch=k["flops"] / max(k["launches"], 1))
+                flops_per_launch=executed * k["flops"] / max(k["launches"], 1))
     extra = dict(
         whole_step_tflops=round(fl_step / (ms * 1e-3) / 1e12, 2),
         step_ms_p50=round(1000 * float(np.percentile(times, 50)), 2),
@@ -307,6 +329,9 @@ def main():
         fp64_gemm=dict(launches=kern["f64"]["launches"], ms_per_step=round(kern["f64"]["ms"] / a.steps, 2),
                        tflops=round(kern["f64"]["flops"] / max(kern["f64"]["ms"], 1e-9) * 1e-9, 2)),
         fp32_gemm=dict(launches=kern["f32"]["launches"], ms_per_step=round(kern["f32"]["ms"] / a.steps, 2)),
+        bf16x3_gemm=dict(launches=kern["bf16x3"]["launches"], ms_per_step=round(kern["bf16x3"]["ms"] / a.steps, 2),
+                         algorithmic_tflops=round(kern["bf16x3"]["flops"] / max(kern["bf16x3"]["ms"], 1e-9) * 1e-9,
+                                                  2)),
         chunk=job.chunk,
     )
     psi_mixed = job.psi.cpu().numpy()
@@ -314,15 +339,21 @@ def main():
     del job
     torch.cuda.empty_cache()
 
-    if a.dtype == "c64" and not a.no_fp64_compare:
+    if a.dtype in ("c64", "bf16x3") and not a.no_fp64_compare:
         job64 = Job(w, "c128", DEFAULT_CHUNK["c128"])
         el64, _, _ = timed(job64, 1, 1, roofline=False)
         v64 = w.M / el64
         psi64 = job64.psi.cpu().numpy()
         extra["fp64_plain"] = dict(value=round(v64, 2), ms_per_step=round(1000 * el64, 1),
                                    mixed_speedup=round(value / v64, 3),
+                                   # direction (norms divided out) and norm separately: the
+                                   # FP32 squarings leave a small radial error that accumulates
+                                   # coherently along the chain
                                    state_infidelity_fp32_vs_fp64=float(
-                                       1 - abs(np.vdot(psi64, psi_mixed)) ** 2))
+                                       1 - abs(np.vdot(psi64, psi_mixed)) ** 2
+                                       / (np.vdot(psi64, psi64).real * np.vdot(psi_mixed, psi_mixed).real)),
+                                   state_norm_fp32_minus_1=float(np.linalg.norm(psi_mixed) - 1),
+                                   state_norm_fp64_minus_1=float(np.linalg.norm(psi64) - 1))
         del job64
         torch.cuda.empty_cache()
 
@@ -337,11 +368,13 @@ def main():
         metric="Magnus interval propagators/s at d=1024 (MFMA %) vs FP64 plain; p50/p99 latency",
         value=round(value, 3), unit="interval propagators/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
         ms_per_step=round(ms, 2), higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="c64+f64" if a.dtype == "c64" else "c128",
+        dtype={"c64": "c64+f64", "bf16x3": "c64(bf16x3)+f64", "c128": "c128"}[a.dtype],
         data="synthetic",
         config=dict(workload=w.name, d=w.d, K=w.K, N=w.N, M=w.M, order=w.order,
-                    precision=("complex64 MFMA products and squarings, FP64 norm/scaling/Pade solve"
-                               if a.dtype == "c64" else "complex128 throughout")),
+                    precision={"c64": "complex64 MFMA products and squarings, FP64 norm/scaling/Pade solve",
+                               "bf16x3": "complex64 storage, products and squarings on BF16 MFMA with three-way "
+                                         "split operands, FP64 norm/scaling/Pade solve",
+                               "c128": "complex128 throughout"}[a.dtype]),
         roofline=roof, cpu_baseline=cpu, extra=extra,
     )
     print(json.dumps(out), flush=True)

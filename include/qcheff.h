@@ -54,6 +54,31 @@ extern "C" {
 #define QCHEFF_C64  2           /* complex float; products and squarings in FP32
                                    on MFMA, the norm, the scaling choice and the
                                    Pade denominator solve in FP64               */
+#define QCHEFF_C64_BF16X3 3     /* qcheff_expm_batched (and its workspace size)
+                                   only: complex float storage as QCHEFF_C64,
+                                   products and squarings of d > 32 on the BF16
+                                   matrix cores with every FP32 operand split in
+                                   three BF16 parts (six part products per real
+                                   product, FP32 accumulation); norm, scaling
+                                   choice and solve in FP64 as for QCHEFF_C64.
+                                   d <= 32 runs as QCHEFF_C64.                  */
+
+/* qcheff_expm_batched: OR into dtype to declare every input skew-Hermitian
+   (Omega^dag = -Omega, as the Magnus generators are).  The even powers of A and
+   the two Pade polynomials are then Hermitian and A W skew-Hermitian, so only the
+   upper triangle of each of those products is formed and the lower one is its
+   mirror (results exactly (skew-)Hermitian).  Inputs that are not skew-Hermitian
+   give wrong results in this mode. */
+#define QCHEFF_SKEW_HERMITIAN 0x100
+
+/* qcheff_expm_batched: OR QCHEFF_SQUARING_BOUND(n), 0 <= n <= 254, into dtype to
+   enqueue exactly n squaring passes without reading the scaling exponents back
+   to the host.  The call then never waits on the host and may be captured into
+   a HIP graph (without a bound, a stream under capture gets QCHEFF_EUNSUPPORTED
+   for d > 32).  An item that needs more than n squarings comes back with
+   s_out = -2 and every entry NaN.  d <= 32 never waits; the bound does not
+   apply there. */
+#define QCHEFF_SQUARING_BOUND(n) ((((n) + 1) & 0xff) << 16)
 
 /* qcheff_propagate modes */
 #define QCHEFF_STATE   1
@@ -134,7 +159,8 @@ int qcheff_magnus_generators(const void* H0, const void* Hk, int64_t d, int64_t 
  * with the norm, outweighs the squaring a larger theta would save).
  *
  *   omega      [batch][d][d], device, dtype.  Any square matrix; the Magnus
- *              generators are skew-Hermitian.
+ *              generators are skew-Hermitian (dtype | QCHEFF_SKEW_HERMITIAN
+ *              halves the Pade products for them).
  *   U          [batch][d][d], device, dtype, written.  May be the same buffer
  *              as omega (the input is consumed).
  *   s_out      optional [batch] int32, device: the number of squarings used,
@@ -201,13 +227,14 @@ const char* qcheff_last_error(void);
  *   qcheff_timing_enable(1) clears old records and starts recording;
  *   qcheff_timing_enable(0) clears them and stops.
  *   qcheff_timing_read(kernel, ...) waits for the recorded events of `kernel`
- *   (QCHEFF_KERNEL_GEMM_F32 / _F64), returns the number of launches, the summed
+ *   (QCHEFF_KERNEL_GEMM_F32 / _F64 / _BF16X3), returns the number of launches, the summed
  *   event-to-event time in ms and the summed flops and bytes, and releases
  *   those records.  Returns QCHEFF_OK, QCHEFF_EINVAL, QCHEFF_EDEVICE.
  * Recording costs two event records per GEMM launch; leave it off otherwise.
  */
 #define QCHEFF_KERNEL_GEMM_F32 1
 #define QCHEFF_KERNEL_GEMM_F64 2
+#define QCHEFF_KERNEL_GEMM_BF16X3 3
 int qcheff_timing_enable(int on);
 int qcheff_timing_read(int kernel, int64_t* launches, double* total_ms, double* flops, double* bytes);
 

@@ -216,18 +216,40 @@ def propagate_product(U):
 
 # ------------------------------------------------------------------ metrics
 
-def propagator_infidelity(U_ref, U):
-    """1 - |tr(U_ref^dag U)|^2 / d^2 (global-phase insensitive)."""
+def propagator_infidelity(U_ref, U, normalized=False):
+    """1 - |tr(U_ref^dag U)|^2 / d^2 (global-phase insensitive).
+
+    normalized=True divides by tr(U_ref^dag U_ref) tr(U^dag U) instead of d^2:
+    equal for unitary operands, and for a finite-precision product whose norm
+    has drifted it compares the operator's direction only (like a state's ray);
+    its distance from unitarity is judged on its own (unitarity_error).
+    """
     U_ref = np.asarray(U_ref, dtype=np.complex128)
     U = np.asarray(U, dtype=np.complex128)
     d = U.shape[-1]
     tr = np.einsum("...ij,...ij->...", U_ref.conj(), U)
+    if normalized:
+        na = np.einsum("...ij,...ij->...", U_ref.conj(), U_ref).real
+        nb = np.einsum("...ij,...ij->...", U.conj(), U).real
+        return 1.0 - np.abs(tr) ** 2 / (na * nb)
     return 1.0 - np.abs(tr) ** 2 / (d * d)
 
 
 def state_infidelity(psi_ref, psi):
-    """1 - |<psi_ref|psi>|^2 (the state error of Sec. 4.3)."""
-    return 1.0 - abs(np.vdot(np.asarray(psi_ref), np.asarray(psi))) ** 2
+    """1 - |<psi_ref|psi>|^2 / (<psi_ref|psi_ref> <psi|psi>) (the state error of Sec. 4.3).
+
+    A pure state is a ray, so the overlap is taken between the normalised
+    vectors: a result whose norm finite precision has moved off 1 is compared by
+    its direction, and its norm is judged on its own (norm_error).
+    """
+    a, b = np.asarray(psi_ref), np.asarray(psi)
+    na, nb = np.vdot(a, a).real, np.vdot(b, b).real
+    return 1.0 - abs(np.vdot(a, b)) ** 2 / (na * nb)
+
+
+def norm_error(psi):
+    """| ||psi|| - 1 |: the evolution is unitary, so every exact state has norm 1."""
+    return abs(float(np.linalg.norm(np.asarray(psi))) - 1.0)
 
 
 def unitarity_error(U):

@@ -27,11 +27,12 @@ LIB_PATH = os.path.join(HERE, "libqcheff_magnus.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "qcheff.h")
 
 OK, EINVAL, EWORKSPACE, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -5
-C128, C64 = 1, 2
+C128, C64, C64_BF16X3 = 1, 2, 3
 STATE, PRODUCT = 1, 2
 REUSE_BASIS = 1
 FN_GENERATORS, FN_EXPM, FN_PROPAGATE = 1, 2, 3
-KERNEL_GEMM_F32, KERNEL_GEMM_F64 = 1, 2
+SKEW_HERMITIAN = 0x100
+KERNEL_GEMM_F32, KERNEL_GEMM_F64, KERNEL_GEMM_BF16X3 = 1, 2, 3
 
 _DTYPES = {torch.complex128: C128, torch.complex64: C64}
 _TORCH = {C128: torch.complex128, C64: torch.complex64}
@@ -148,15 +149,33 @@ def magnus_generators(H0, Hk, c1, c2, dt_interval: float, order: int, out_dtype=
     return omega, ws
 
 
-def expm_batched(omega, U=None, s_out=None, ws=None, chunk: int | None = None, stream=None):
+def squaring_bound_flag(n: int) -> int:
+    """The QCHEFF_SQUARING_BOUND(n) flag bits."""
+    if not 0 <= n <= 254:
+        raise ValueError("squaring bound must lie in [0, 254]")
+    return (n + 1) << 16
+
+
+def expm_batched(omega, U=None, s_out=None, ws=None, chunk: int | None = None, stream=None,
+                 skew_hermitian: bool = False, squaring_bound: int | None = None, bf16x3: bool = False):
     """U_b = exp(omega_b) by [13/13] Pade scaling and squaring (qcheff_expm_batched).
 
     ``U`` may be ``omega`` itself.  ``chunk`` caps the items processed at once
-    (the workspace is sized for it).  Returns (U, s).
+    (the workspace is sized for it).  ``skew_hermitian=True`` declares every
+    omega_b skew-Hermitian (QCHEFF_SKEW_HERMITIAN): the Hermitian Pade products
+    are then formed by halves.  ``squaring_bound=n`` enqueues exactly n squaring
+    passes and never waits on the host (graph-capturable); items that need more
+    come back with s = -2 and NaN entries.  ``bf16x3=True`` (complex64 only)
+    runs the products on the BF16 matrix cores with three-way split operands
+    (QCHEFF_C64_BF16X3).  Returns (U, s).
     """
     _dev(omega, "omega")
     B, d = omega.shape[0], omega.shape[-1]
     dt = _DTYPES[omega.dtype]
+    if bf16x3:
+        if dt != C64:
+            raise ValueError("bf16x3 products take complex64 matrices")
+        dt = C64_BF16X3
     if U is None:
         U = torch.empty_like(omega)
     if s_out is None:
@@ -164,7 +183,10 @@ def expm_batched(omega, U=None, s_out=None, ws=None, chunk: int | None = None, s
     if ws is None:
         ws = _workspace(workspace_bytes(FN_EXPM, max(1, min(B, chunk or B)), d, 1, 1, dt), omega.device)
     _check("qcheff_expm_batched", lib().qcheff_expm_batched(
-        _ptr(omega), B, d, dt, _ptr(U), _ptr(s_out), _ptr(ws), ws.numel(), _stream(stream)))
+        _ptr(omega), B, d,
+        dt | (SKEW_HERMITIAN if skew_hermitian else 0)
+        | (0 if squaring_bound is None else squaring_bound_flag(squaring_bound)),
+        _ptr(U), _ptr(s_out), _ptr(ws), ws.numel(), _stream(stream)))
     return U, s_out
 
 
@@ -206,17 +228,23 @@ def timing_read(kernel: int) -> dict:
 
 
 def evolve(H0, Hk, u, dt_sample: float, M: int, order: int, psi0=None, dtype=torch.complex64,
-           product: bool = False, trajectory: bool = False, chunk: int | None = None, stream=None):
+           product: bool = False, trajectory: bool = False, chunk: int | None = None, stream=None,
+           hermitian: bool = True, bf16x3: bool = False):
     """The whole path on the GPU: coefficients -> Omega_n -> U_n -> chain.
 
     Inputs are GPU tensors (H0 [d][d] and Hk [K][d][d] complex128, u [K][N]
-    float64, psi0 [d] complex128).  Returns a dict with c1, c2, U, s and, as
-    asked, psi (final state), traj, P.
+    float64, psi0 [d] complex128).  ``hermitian`` states that H0 and every H_k
+    are exactly Hermitian (H[c, r] == conj(H[r, c]) bit for bit), as for a
+    closed system; the generators are then exactly skew-Hermitian and the
+    exponentials use the structured Pade products.  ``bf16x3`` (with
+    dtype=complex64) takes the products on the BF16 matrix cores with split
+    operands.  Returns a dict with c1, c2,
+    U, s and, as asked, psi (final state), traj, P.
     """
     N = u.shape[1]
     c1, c2 = magnus_coeffs(u, dt_sample, M, order, stream=stream)
     omega, _ = magnus_generators(H0, Hk, c1, c2, dt_sample * (N // M), order, dtype, stream=stream)
-    U, s = expm_batched(omega, U=omega, chunk=chunk, stream=stream)
+    U, s = expm_batched(omega, U=omega, chunk=chunk, stream=stream, skew_hermitian=hermitian, bf16x3=bf16x3)
     out = dict(c1=c1, c2=c2, U=U, s=s)
     if psi0 is not None:
         psi = psi0.clone()

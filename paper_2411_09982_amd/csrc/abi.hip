@@ -13,7 +13,7 @@
 #include <vector>
 
 #include "../../include/qcheff.h"
-#include "cgemm.hpp"
+#include "gemm_launch.hpp"
 #include "kernels.hpp"
 #include "lu.hpp"
 #include "expm_small.hpp"
@@ -151,6 +151,14 @@ int square_cfg(int64_t d, int64_t nb, const typename Cx<T>::t* A, typename Cx<T>
   }
   const char* env = std::getenv("QCHEFF_AUTOTUNE");
   int best = rule_cfg(d);
+  // Timing waits on the host, which a stream under graph capture must not do:
+  // there the size rule stands in (and is not stored).
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  QC_HIP(hipStreamIsCapturing(st, &cs));
+  if (cs != hipStreamCaptureStatusNone) {
+    *cfg_out = best;
+    return QCHEFF_OK;
+  }
   if (!(env && env[0] == '0')) {
     float best_ms = 3.4e38f;
     hipEvent_t e0, e1;
@@ -287,10 +295,11 @@ template <typename T> bool carve_expm(void* ws, size_t bytes, int64_t chunk, int
 // out = A B (+ sum_i xc[i] X_i + gamma I) over a batch of d x d items; with bc,
 // the right operand is bc[0] X_0 + bc[1] X_1 + bc[2] X_2 instead of B.
 template <typename T>
-int gemm_sq(int cfg, typename Cx<T>::t* out, const typename Cx<T>::t* A, const typename Cx<T>::t* B, int64_t d,
-            int64_t nb, hipStream_t st, int nx = 0, const typename Cx<T>::t* const* X = nullptr,
+int gemm_sq(int cfg, int herm, typename Cx<T>::t* out, const typename Cx<T>::t* A, const typename Cx<T>::t* B,
+            int64_t d, int64_t nb, hipStream_t st, int nx = 0, const typename Cx<T>::t* const* X = nullptr,
             const T* xc = nullptr, T gamma = T(0), const T* bc = nullptr) {
   auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
+  p.herm = herm;
   const int64_t dd = d * d;
   p.A = A; p.lda = d; p.sA = dd;
   p.B = B; p.ldb = d; p.sB = dd;
@@ -415,7 +424,7 @@ int lu_solve(double2* aug, int* piv, int64_t d, int64_t nb, hipStream_t st) {
 
 template <typename T>
 int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t* s_out, int64_t nb, int64_t d,
-                   ExpmWs<T>& w, hipStream_t st) {
+                   ExpmWs<T>& w, bool skew, int bound, bool bf16x3, hipStream_t st) {
   using C2 = typename Cx<T>::t;
   const int64_t dd = d * d;
   double b[14];
@@ -432,22 +441,25 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
   QC_HIP(hipGetLastError());
   const unsigned sblocks = unsigned(std::min<int64_t>(nblocks(dd, 256), 1024));
   hipLaunchKernelGGL(scale_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, omega, w.X[0], dd, w.norms,
-                     kTheta13, w.s_ws, s_out, w.smax);
+                     kTheta13, bound, w.s_ws, s_out, w.smax);
   QC_HIP(hipGetLastError());
   C2 *A = w.X[0], *A2 = w.X[1], *A4 = w.X[2], *A6 = w.X[3], *W = w.X[4], *V = w.X[5];
-  int r, cfg = 0;
-  if ((r = square_cfg<T>(d, nb, A, W, st, &cfg))) return r;
-  if ((r = gemm_sq<T>(cfg, A2, A, A, d, nb, st))) return r;
-  if ((r = gemm_sq<T>(cfg, A4, A2, A2, d, nb, st))) return r;
-  if ((r = gemm_sq<T>(cfg, A6, A4, A2, d, nb, st))) return r;
+  int r, cfg = 2;   // the split-BF16 tile, or the tuned FP32 / FP64 one
+  if (!bf16x3 && (r = square_cfg<T>(d, nb, A, W, st, &cfg))) return r;
+  // For skew-Hermitian A every even power, W and V are Hermitian (and A W
+  // skew-Hermitian): only half of each of those products is formed.
+  const int h = skew ? 1 : 0;
+  if ((r = gemm_sq<T>(cfg, h, A2, A, A, d, nb, st))) return r;
+  if ((r = gemm_sq<T>(cfg, h, A4, A2, A2, d, nb, st))) return r;
+  if ((r = gemm_sq<T>(cfg, h, A6, A4, A2, d, nb, st))) return r;
   // W = A6 (b13 A6 + b11 A4 + b9 A2) + b7 A6 + b5 A4 + b3 A2 + b1 I   (U = A W)
   // V = A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I
   // The right operand's linear combination is formed as the GEMM loads it.
   const C2* Xs[3] = {A6, A4, A2};
   const T xw[3] = {c[7], c[5], c[3]}, bw[3] = {c[13], c[11], c[9]};
-  if ((r = gemm_sq<T>(cfg, W, A6, A6, d, nb, st, 3, Xs, xw, c[1], bw))) return r;
+  if ((r = gemm_sq<T>(cfg, h, W, A6, A6, d, nb, st, 3, Xs, xw, c[1], bw))) return r;
   const T xv[3] = {c[6], c[4], c[2]}, bv[3] = {c[12], c[10], c[8]};
-  if ((r = gemm_sq<T>(cfg, V, A6, A6, d, nb, st, 3, Xs, xv, c[0], bv))) return r;
+  if ((r = gemm_sq<T>(cfg, h, V, A6, A6, d, nb, st, 3, Xs, xv, c[0], bv))) return r;
   // [q | p] = [V - A W | V + A W] in FP64
   {
     auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
@@ -456,6 +468,7 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
     p.C = V; p.ldc = d; p.sC = dd;
     p.X[0] = V;
     p.epi = EPI_AUG;
+    p.herm = -h;
     p.aug = w.aug; p.ld_aug = 2 * d; p.s_aug = 2 * dd; p.aug_off = d;
     QC_HIP((launch_cgemm<T>(p, st)));
   }
@@ -463,10 +476,14 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
   hipLaunchKernelGGL(place_result_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, w.aug, int(d), w.s_ws,
                      U, A);
   QC_HIP(hipGetLastError());
-  // the host needs the squaring counts to size the squaring launches
-  std::vector<int> s_host(size_t(nb), 0);
-  QC_HIP(hipMemcpyAsync(s_host.data(), w.s_ws, size_t(nb) * sizeof(int), hipMemcpyDeviceToHost, st));
-  QC_HIP(hipStreamSynchronize(st));
+  // Without a bound the host reads the squaring counts back to size the
+  // squaring launches; with one it enqueues exactly `bound` passes (an item
+  // leaves the passes once its own count is done) and never waits.
+  std::vector<int> s_host(size_t(nb), bound);
+  if (bound < 0) {
+    QC_HIP(hipMemcpyAsync(s_host.data(), w.s_ws, size_t(nb) * sizeof(int), hipMemcpyDeviceToHost, st));
+    QC_HIP(hipStreamSynchronize(st));
+  }
   const int smax = std::max(0, *std::max_element(s_host.begin(), s_host.end()));
   for (int step = 0; step < smax; ++step) {
     const int64_t active = std::count_if(s_host.begin(), s_host.end(), [step](int s) { return s > step; });
@@ -481,7 +498,7 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
 
 template <typename T>
 int run_expm(const void* omega, int64_t batch, int64_t d, void* U, int32_t* s_out, void* ws, size_t ws_bytes,
-             int dtype, hipStream_t st) {
+             int dtype, bool skew, int bound, bool bf16x3, hipStream_t st) {
   using C2 = typename Cx<T>::t;
   if (d <= kSmallD) {
     // one workgroup per item, everything in LDS; no workspace and no host sync
@@ -498,7 +515,7 @@ int run_expm(const void* omega, int64_t batch, int64_t d, void* U, int32_t* s_ou
   for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
     const int64_t nb = std::min(chunk, batch - b0);
     int r = expm_chunk_run<T>(static_cast<const C2*>(omega) + b0 * dd, static_cast<C2*>(U) + b0 * dd,
-                              s_out ? s_out + b0 : nullptr, nb, d, w, st);
+                              s_out ? s_out + b0 : nullptr, nb, d, w, skew, bound, bf16x3, st);
     if (r) return r;
   }
   return QCHEFF_OK;
@@ -587,12 +604,25 @@ int qcheff_magnus_generators(const void* H0, const void* Hk, int64_t d, int64_t 
 
 int qcheff_expm_batched(const void* omega, int64_t batch, int64_t d, int dtype, void* U, int32_t* s_out, void* ws,
                         size_t ws_bytes, void* stream) {
+  const bool skew = (dtype & QCHEFF_SKEW_HERMITIAN) != 0;
+  const int bound = ((dtype >> 16) & 0xff) - 1;   // -1: none
+  dtype &= ~(QCHEFF_SKEW_HERMITIAN | (0xff << 16));
+  const bool bf16x3 = dtype == QCHEFF_C64_BF16X3;
+  if (bf16x3) dtype = QCHEFF_C64;
   Check c = check_expm(omega, batch, d, dtype, U, ws, ws_bytes);
   if (c.status) return fail(c);
   if (batch == 0) return QCHEFF_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  return dtype == QCHEFF_C128 ? run_expm<double>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, st)
-                              : run_expm<float>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, st);
+  if (bound < 0 && d > kSmallD) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    QC_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+      return fail(Check::fail(QCHEFF_EUNSUPPORTED,
+                              "qcheff_expm_batched: a stream under graph capture needs QCHEFF_SQUARING_BOUND(n)"));
+  }
+  return dtype == QCHEFF_C128
+             ? run_expm<double>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, skew, bound, false, st)
+             : run_expm<float>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, skew, bound, bf16x3, st);
 }
 
 int qcheff_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, void* x, void* traj, void* ws,

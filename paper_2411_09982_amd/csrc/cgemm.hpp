@@ -20,7 +20,7 @@ namespace qcheff {
 enum { EPI_STD = 0, EPI_AUG = 1 };
 
 // Kernel ids of the timing instrumentation (match QCHEFF_KERNEL_* in qcheff.h).
-enum { KERNEL_GEMM_F32 = 1, KERNEL_GEMM_F64 = 2 };
+enum { KERNEL_GEMM_F32 = 1, KERNEL_GEMM_F64 = 2, KERNEL_GEMM_BF16X3 = 3 };
 
 // Records a HIP event pair around a launch while timing is enabled.
 struct LaunchTimer {
@@ -39,6 +39,8 @@ template <typename T> struct GemmParams {
   C2* C; int64_t ldc, sC;
   T alpha, beta, gamma;
   int cfg;                      // tile configuration (GemmTile<T, cfg>)
+  int herm;                     // 0: general; +1 / -1: the result is Hermitian / skew-Hermitian
+                                // (M == N, BM == BN): only the upper triangle of tiles runs
   int epi;                      // EPI_STD or EPI_AUG
   int sq;                       // 1: squaring mode (sq_* fields)
   int nx;                       // number of X terms (0..3); X share C's ld and stride
@@ -52,6 +54,136 @@ template <typename T> struct GemmParams {
   // squaring mode: A = B = in, C = out, chosen per item from the remaining count
   const int* sq_s; int sq_step; C2* sq_p0; C2* sq_p1;
 };
+
+// The item and tile a workgroup computes, and its operand pointers.
+template <typename T> struct TileJob {
+  using C2 = typename Cx<T>::t;
+  int b, tm, tn, row0, col0;
+  const C2* A;
+  const C2* B;
+  C2* C;
+  const C2* BX0;
+  const C2* BX1;
+};
+
+// Fills `j` for this workgroup; false when it has nothing to do (past the last
+// item, or an item whose squarings are done).  With a (skew-)Hermitian result
+// only the tiles on and above the diagonal run; each element above the diagonal
+// is also written, conjugated, below it.
+template <typename T, int BM, int BN>
+__device__ __forceinline__ bool tile_job(const GemmParams<T>& p, TileJob<T>& j) {
+  using C2 = typename Cx<T>::t;
+  const int tiles = p.herm ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = bid / tiles;
+  if (b >= p.batch) return false;
+  const int t = bid - b * tiles;
+  int tm, tn;
+  if (p.herm) {
+    tm = 0;
+    int rem = t;
+    while (rem >= p.tiles_m - tm) {
+      rem -= p.tiles_m - tm;
+      ++tm;
+    }
+    tn = tm + rem;
+  } else {
+    tm = t / p.tiles_n;
+    tn = t % p.tiles_n;
+  }
+  j.b = b;
+  j.tm = tm;
+  j.tn = tn;
+  j.row0 = tm * BM;
+  j.col0 = tn * BN;
+  if (p.sq) {
+    const int s = p.sq_s[b];
+    if (s <= p.sq_step) return false;        // this item needs no more squarings
+    const int rem = s - p.sq_step;           // squarings left, this one included
+    C2* in = (rem % 2 == 0) ? p.sq_p0 : p.sq_p1;
+    C2* out = (rem % 2 == 0) ? p.sq_p1 : p.sq_p0;
+    j.A = in + b * p.sA;
+    j.B = in + b * p.sB;
+    j.C = out + b * p.sC;
+  } else {
+    j.A = p.A + b * p.sA;
+    j.B = p.B + b * p.sB;
+    j.C = p.C + b * p.sC;
+  }
+  j.BX0 = p.nbx > 0 ? p.BX[0] + b * p.sB : j.B;
+  j.BX1 = p.nbx > 0 ? p.BX[1] + b * p.sB : j.B;
+  return true;
+}
+
+// Writes a wave's TM x TN blocks of 16 x 16 accumulators (rows as acc_row<T>,
+// column lane % 16) through the epilogue the parameters select.
+template <typename T, int TM, int TN>
+__device__ __forceinline__ void tile_epilogue(const GemmParams<T>& p, const TileJob<T>& jb,
+                                              const typename Cx<T>::acc (&accr)[TM][TN],
+                                              const typename Cx<T>::acc (&acci)[TM][TN], int wm, int wn,
+                                              int lane) {
+  using C2 = typename Cx<T>::t;
+  const int b = jb.b;
+  C2* C = jb.C;
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int c = jb.col0 + wn + j * 16 + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = jb.row0 + wm + i * 16 + acc_row<T>(lane, e);
+        if (r >= p.M || c >= p.N) continue;
+        if (p.herm && r > c) continue;   // written as the mirror of (c, r)
+        const int64_t off = int64_t(r) * p.ldc + c;
+        if (p.epi == EPI_AUG) {
+          // U = A W is skew-Hermitian here and V Hermitian: q = V - U, p = V + U,
+          // and below the diagonal q(c, r) = conj(p(r, c)), p(c, r) = conj(q(r, c))
+          C2 v = p.X[0][b * p.sC + off];
+          double pr = double(accr[i][j][e]), pi = double(acci[i][j][e]);
+          if (p.herm && r == c) {
+            v.y = T(0);
+            pr = 0.0;
+          }
+          double2* base = p.aug + b * p.s_aug;
+          const double2 q = make_double2(double(v.x) - pr, double(v.y) - pi);
+          const double2 pp = make_double2(double(v.x) + pr, double(v.y) + pi);
+          base[int64_t(r) * p.ld_aug + c] = q;
+          base[int64_t(r) * p.ld_aug + p.aug_off + c] = pp;
+          if (p.herm && r != c) {
+            base[int64_t(c) * p.ld_aug + r] = make_double2(pp.x, -pp.y);
+            base[int64_t(c) * p.ld_aug + p.aug_off + r] = make_double2(q.x, -q.y);
+          }
+        } else {
+          T vr = p.alpha * accr[i][j][e], vi = p.alpha * acci[i][j][e];
+          if (p.beta != T(0)) {
+            const C2 old = C[off];
+            vr += p.beta * old.x;
+            vi += p.beta * old.y;
+          }
+          for (int x = 0; x < p.nx; ++x) {
+            const C2 xv = p.X[x][b * p.sC + off];
+            vr += p.xc[x] * xv.x;
+            vi += p.xc[x] * xv.y;
+          }
+          if (r == c) vr += p.gamma;
+          if (p.herm && r == c) {   // a Hermitian diagonal is real, a skew-Hermitian one imaginary
+            if (p.herm > 0) vi = T(0); else vr = T(0);
+          }
+          C2 o;
+          o.x = vr;
+          o.y = vi;
+          C[off] = o;
+          if (p.herm && r != c) {
+            o.x = p.herm > 0 ? vr : -vr;
+            o.y = p.herm > 0 ? -vi : vi;
+            C[int64_t(c) * p.ldc + r] = o;
+          }
+        }
+      }
+    }
+  }
+}
 
 template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int WAVES_PER_EU, bool BCOMB>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU))) void cgemm_kernel(
@@ -67,37 +199,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
   __shared__ C2 As[2][BK][BM + 1];
   __shared__ C2 Bs[2][BK][BN];
 
-  const int tiles = p.tiles_m * p.tiles_n;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = bid / tiles;
-  if (b >= p.batch) return;
-  const int t = bid - b * tiles;
-  const int row0 = (t / p.tiles_n) * BM;
-  const int col0 = (t % p.tiles_n) * BN;
-
-  const C2* A;
-  const C2* B;
-  C2* C;
-  if (p.sq) {
-    const int s = p.sq_s[b];
-    if (s <= p.sq_step) return;              // this item needs no more squarings
-    const int rem = s - p.sq_step;           // squarings left, this one included
-    C2* in = (rem % 2 == 0) ? p.sq_p0 : p.sq_p1;
-    C2* out = (rem % 2 == 0) ? p.sq_p1 : p.sq_p0;
-    A = in + b * p.sA;
-    B = in + b * p.sB;
-    C = out + b * p.sC;
-  } else {
-    A = p.A + b * p.sA;
-    B = p.B + b * p.sB;
-    C = p.C + b * p.sC;
-  }
-  const C2* BX0 = BCOMB ? p.BX[0] + b * p.sB : B;
-  const C2* BX1 = BCOMB ? p.BX[1] + b * p.sB : B;
+  TileJob<T> jb;
+  if (!tile_job<T, BM, BN>(p, jb)) return;
+  const int row0 = jb.row0, col0 = jb.col0;
+  const C2* A = jb.A;
+  const C2* B = jb.B;
+  const C2* BX0 = jb.BX0;
+  const C2* BX1 = jb.BX1;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
+  // in a diagonal tile of a (skew-)Hermitian result a wave whose sub-tile lies
+  // wholly below the diagonal has nothing to compute (it still helps load)
+  const bool idle = p.herm && jb.tm == jb.tn && wm >= wn + WN;
 
   Acc accr[TM][TN], acci[TM][TN];
 #pragma unroll
@@ -161,6 +276,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
     if (kt + 1 < nk) load((kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
+      if (idle) break;
       C2 a[TM], bb[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) a[i] = As[cur][kk + lr][wm + i * 16 + lc];
@@ -186,44 +302,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
     __syncthreads();
   }
 
-  // epilogue
-#pragma unroll
-  for (int i = 0; i < TM; ++i) {
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int c = col0 + wn + j * 16 + lc;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = row0 + wm + i * 16 + acc_row<T>(lane, e);
-        if (r >= p.M || c >= p.N) continue;
-        const int64_t off = int64_t(r) * p.ldc + c;
-        if (p.epi == EPI_AUG) {
-          const C2 v = p.X[0][b * p.sC + off];
-          const double pr = double(accr[i][j][e]), pi = double(acci[i][j][e]);
-          double2* out = p.aug + b * p.s_aug + int64_t(r) * p.ld_aug + c;
-          out[0] = make_double2(double(v.x) - pr, double(v.y) - pi);
-          out[p.aug_off] = make_double2(double(v.x) + pr, double(v.y) + pi);
-        } else {
-          T vr = p.alpha * accr[i][j][e], vi = p.alpha * acci[i][j][e];
-          if (p.beta != T(0)) {
-            const C2 old = C[off];
-            vr += p.beta * old.x;
-            vi += p.beta * old.y;
-          }
-          for (int x = 0; x < p.nx; ++x) {
-            const C2 xv = p.X[x][b * p.sC + off];
-            vr += p.xc[x] * xv.x;
-            vi += p.xc[x] * xv.y;
-          }
-          if (r == c) vr += p.gamma;
-          C2 o;
-          o.x = vr;
-          o.y = vi;
-          C[off] = o;
-        }
-      }
-    }
-  }
+  tile_epilogue<T, TM, TN>(p, jb, accr, acci, wm, wn, lane);
 }
 
 // Tile configurations per precision: cfg 0 is the large tile, cfg 1 the small
@@ -238,6 +317,11 @@ template <> struct GemmTile<float, 0> {
 template <> struct GemmTile<float, 1> {
   static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, NT = 256, WPE = 4;
 };
+// FP32 cfg 2: FP32 operands on the BF16 matrix cores, three-way split
+// (cgemm_bf16x3_kernel); 128x128 tile, eight waves of 64x32, K steps of 32.
+template <> struct GemmTile<float, 2> {
+  static constexpr int BM = 128, BN = 128, BK = 32, WM = 64, WN = 32, NT = 512, WPE = 2;
+};
 template <> struct GemmTile<double, 0> {
   static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, NT = 256, WPE = 2;
 };
@@ -249,51 +333,12 @@ template <typename T> GemmParams<T> gemm_params(int M, int N, int K, int batch, 
   GemmParams<T> p{};
   p.M = M; p.N = N; p.K = K; p.batch = batch;
   p.cfg = cfg;
-  const int bm = cfg ? GemmTile<T, 1>::BM : GemmTile<T, 0>::BM;
-  const int bn = cfg ? GemmTile<T, 1>::BN : GemmTile<T, 0>::BN;
+  const int bm = cfg == 2 ? 128 : cfg ? GemmTile<T, 1>::BM : GemmTile<T, 0>::BM;
+  const int bn = cfg == 2 ? 128 : cfg ? GemmTile<T, 1>::BN : GemmTile<T, 0>::BN;
   p.tiles_m = (M + bm - 1) / bm;
   p.tiles_n = (N + bn - 1) / bn;
   p.alpha = T(1); p.beta = T(0); p.gamma = T(0); p.nx = 0;
   return p;
-}
-
-template <typename T, int CFG> void launch_tile(const GemmParams<T>& p, unsigned blocks, hipStream_t stream) {
-  using G = GemmTile<T, CFG>;
-  if (p.nbx > 0)
-    hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT, G::WPE, true>), dim3(blocks),
-                       dim3(G::NT), 0, stream, p);
-  else
-    hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT, G::WPE, false>), dim3(blocks),
-                       dim3(G::NT), 0, stream, p);
-}
-
-// Launch; `active` is the number of items that do work (squaring mode skips
-// the others) and feeds the timing record's algorithmic flop and byte counts.
-template <typename T>
-hipError_t launch_cgemm(const GemmParams<T>& p, hipStream_t stream, int64_t active = -1) {
-  if (p.M <= 0 || p.N <= 0 || p.batch <= 0) return hipSuccess;
-  if (p.lda * int64_t(p.M) >= (int64_t(1) << 31) || p.ldb * int64_t(p.K) >= (int64_t(1) << 31) ||
-      p.ldc * int64_t(p.M) >= (int64_t(1) << 31))
-    return hipErrorInvalidValue;
-  const int64_t blocks = int64_t(p.tiles_m) * p.tiles_n * p.batch;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  if (active < 0) active = p.batch;
-  LaunchTimer tm;
-  tm.begin(stream);
-  if (p.cfg == 1)
-    launch_tile<T, 1>(p, unsigned(blocks), stream);
-  else
-    launch_tile<T, 0>(p, unsigned(blocks), stream);
-  const hipError_t e = hipGetLastError();
-  if (tm.on) {
-    const double mn = double(p.M) * p.N, es = double(sizeof(typename Cx<T>::t));
-    const double flops = 8.0 * mn * double(p.K) * double(active);
-    double elems = double(p.M) * p.K + double(p.K) * p.N + mn * (1 + p.nx + (p.beta != T(0) ? 1 : 0));
-    double bytes = elems * es;
-    if (p.epi == EPI_AUG) bytes += mn * 32.0;  // V is the generic M N term; two FP64 halves are written
-    tm.end(stream, sizeof(T) == 4 ? KERNEL_GEMM_F32 : KERNEL_GEMM_F64, flops, bytes * double(active));
-  }
-  return e;
 }
 
 }  // namespace qcheff

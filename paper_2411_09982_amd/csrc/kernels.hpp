@@ -186,15 +186,17 @@ __device__ __forceinline__ int squarings_for(double nrm, double theta) {
   return s;
 }
 
-// A = Omega / 2^s per item (exact); records s.
+// A = Omega / 2^s per item (exact); records s.  With bound >= 0 an item whose s
+// exceeds it is recorded as -2 and scaled by NaN (its result is all NaN).
 template <typename C2>
 __global__ __launch_bounds__(256) void scale_kernel(const C2* __restrict__ omega, C2* __restrict__ A,
                                                     int64_t dd, const unsigned long long* __restrict__ norms,
-                                                    double theta, int* __restrict__ s_ws,
+                                                    double theta, int bound, int* __restrict__ s_ws,
                                                     int* __restrict__ s_out, int* __restrict__ smax) {
   const int b = blockIdx.y;
   const double nrm = __longlong_as_double((long long)norms[b]);
-  const int s = squarings_for(nrm, theta);
+  int s = squarings_for(nrm, theta);
+  if (bound >= 0 && s > bound) s = -2;   // needs more squarings than enqueued: NaN result
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     s_ws[b] = s;
     if (s_out) s_out[b] = s;

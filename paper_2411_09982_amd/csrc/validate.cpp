@@ -140,7 +140,7 @@ size_t workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int order, i
       if (K < 1 || (order != 1 && order != 2)) return 0;
       return generators_ws_bytes(d, K, order);
     case QCHEFF_FN_EXPM:
-      return expm_ws_bytes(batch, d, dtype);
+      return expm_ws_bytes(batch, d, dtype == QCHEFF_C64_BF16X3 ? QCHEFF_C64 : dtype);
     case QCHEFF_FN_PROPAGATE:
       return propagate_ws_bytes(batch, d, dtype, order);
     default:

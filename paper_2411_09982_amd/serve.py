@@ -25,8 +25,8 @@ import numpy as np
 @dataclasses.dataclass
 class Request:
     rid: int
-    H0: np.ndarray            # complex128 [d][d]
-    Hk: np.ndarray            # complex128 [K][d][d]
+    H0: np.ndarray            # complex128 [d][d], exactly Hermitian
+    Hk: np.ndarray            # complex128 [K][d][d], each exactly Hermitian
     u: np.ndarray             # float64 [K][N]
     dt_sample: float
     M: int
@@ -143,7 +143,7 @@ class Server:
                 N = r.u.shape[1]
                 omega, _ = q.magnus_generators(H0, Hk, c1, c2, r.dt_sample * (N // r.M), r.order, dtype,
                                                stream=st)
-                U, s = q.expm_batched(omega, U=omega, chunk=self.chunk, stream=st)
+                U, s = q.expm_batched(omega, U=omega, chunk=self.chunk, stream=st, skew_hermitian=True)
                 q.propagate(U, q.STATE, psi, stream=st)
                 psi_h = psi.cpu().numpy()
                 s_max = int(s.max().cpu())
@@ -216,6 +216,14 @@ def max_overlap(results: dict[int, Result]) -> int:
 
 
 def latency_percentiles(results: dict[int, Result]) -> dict:
-    lat = np.array([r.latency for r in results.values()])
-    return dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
-                n=int(lat.size))
+    """p50/p99 of the latency (arrival to completion) and of its two parts: the
+    wait for admission and the service time (admission to completion)."""
+    vals = list(results.values())
+    lat = np.array([r.latency for r in vals])
+    wait = np.array([r.admitted - r.arrival for r in vals])
+    svc = np.array([r.done - r.admitted for r in vals])
+    out = dict(n=int(lat.size))
+    for name, a in (("", lat), ("wait_", wait), ("service_", svc)):
+        out[f"{name}p50_ms"] = float(np.percentile(a, 50) * 1e3)
+        out[f"{name}p99_ms"] = float(np.percentile(a, 99) * 1e3)
+    return out

@@ -6,6 +6,14 @@ buffer, all of the group's interval exponentials run as one batched call
 (d <= 32: one fused workgroup per matrix; larger d: the MFMA GEMM path in
 chunks), and all of the group's state chains advance in one launch
 (qcheff_propagate_batched).  Every step is a call of the C ABI.
+
+``capture()`` records each group's whole sequence into a HIP graph (via
+torch.cuda.CUDAGraph), after one eager pass has tuned the GEMM tiles and shown
+the largest scaling exponent of the group.  The graphs take the exponentials
+with a squaring bound (that exponent plus a margin), so nothing in them waits
+on the host; ``run()`` then replays them, and a group whose replay reports an
+exponent above its bound (new controls with larger norms) is run eagerly and
+captured again.
 """
 from __future__ import annotations
 
@@ -16,7 +24,11 @@ import numpy as np
 
 
 class Sweep:
-    """Device buffers for a list of Workload-like jobs (H0, Hk, u, dt_sample, M, order, psi0)."""
+    """Device buffers for a list of Workload-like jobs (H0, Hk, u, dt_sample, M, order, psi0).
+
+    H0 and every H_k must be exactly Hermitian (closed systems): the
+    exponentials are taken with the skew-Hermitian structure of the generators.
+    """
 
     def __init__(self, jobs, dtype, chunk: int = 256, device: str = "cuda:0"):
         import torch
@@ -50,27 +62,72 @@ class Sweep:
             nb = min(chunk, len(idx) * M)
             g["exp_ws"] = torch.empty(q.workspace_bytes(q.FN_EXPM, nb, d, 1, 1, code), dtype=torch.uint8,
                                       device=device)
+            g["s"] = torch.empty(len(idx) * M, dtype=torch.int32, device=device)
+            g["graph"] = None
+            g["bound"] = None
             self.groups.append(g)
+        self.margin = 1
+        self.replays = 0
+        self.recaptures = 0
+
+    def _enqueue(self, g, bound=None) -> None:
+        """The group's whole sequence on the current stream."""
+        q = self.q
+        M, d = g["M"], g["d"]
+        for k, i in enumerate(g["idx"]):
+            j = self.jobs[i]
+            H0, Hk, u = g["ops"][k]
+            q.magnus_coeffs(u, j.dt_sample, M, j.order, c1=g["c1"][k], c2=g["c2"][k])
+            q.magnus_generators(H0, Hk, g["c1"][k], g["c2"][k], j.dt_interval, j.order, self.dtype,
+                                omega=g["omega"][k * M:(k + 1) * M], ws=g["gen_ws"])
+        q.expm_batched(g["omega"], U=g["omega"], s_out=g["s"], ws=g["exp_ws"], skew_hermitian=True,
+                       squaring_bound=bound)
+        g["psi"].copy_(g["psi0"])
+        q.propagate_batched(g["omega"].view(len(g["idx"]), M, d, d), g["psi"])
+
+    def _capture(self, g) -> None:
+        torch = self.torch
+        g["bound"] = int(g["s"].cpu().numpy().max()) + self.margin
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()   # default priority
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                self._enqueue(g, g["bound"])
+        torch.cuda.current_stream().wait_stream(side)
+        g["graph"] = graph
+
+    def capture(self) -> None:
+        """One eager pass per group, then a graph per group (see the module doc)."""
+        torch = self.torch
+        for g in self.groups:
+            self._enqueue(g)
+            torch.cuda.synchronize()
+            self._capture(g)
+        torch.cuda.synchronize()
 
     def run(self) -> dict:
-        """One pass over every job; returns per-group wall times (s) measured with host clocks."""
-        q, torch = self.q, self.torch
+        """One pass over every job (graph replays once captured); returns per-group
+        wall times (s) measured with host clocks."""
+        torch = self.torch
         times = {}
         for g in self.groups:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            M, d = g["M"], g["d"]
-            for k, i in enumerate(g["idx"]):
-                j = self.jobs[i]
-                H0, Hk, u = g["ops"][k]
-                q.magnus_coeffs(u, j.dt_sample, M, j.order, c1=g["c1"][k], c2=g["c2"][k])
-                q.magnus_generators(H0, Hk, g["c1"][k], g["c2"][k], j.dt_interval, j.order, self.dtype,
-                                    omega=g["omega"][k * M:(k + 1) * M], ws=g["gen_ws"])
-            q.expm_batched(g["omega"], U=g["omega"], ws=g["exp_ws"])
-            g["psi"].copy_(g["psi0"])
-            q.propagate_batched(g["omega"].view(len(g["idx"]), M, d, d), g["psi"])
+            if g["graph"] is None:
+                self._enqueue(g)
+            else:
+                g["graph"].replay()
+                self.replays += 1
             torch.cuda.synchronize()
-            times[d] = time.perf_counter() - t0
+            times[g["d"]] = time.perf_counter() - t0
+            if g["graph"] is not None and g["d"] > 32 and (g["s"].cpu().numpy() == -2).any():
+                # an exponent above the bound: redo eagerly, capture with the new maximum
+                self._enqueue(g)
+                torch.cuda.synchronize()
+                self._capture(g)
+                self.recaptures += 1
+                times[g["d"]] = time.perf_counter() - t0
         return times
 
     def states(self) -> dict:

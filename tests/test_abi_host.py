@@ -78,6 +78,22 @@ def test_expm_validation_and_workspace():
     assert c64 >= 6 * d * d * 8 + 2 * d * d * 16 and c64 < 6 * d * d * 8 + 2 * d * d * 16 + 8192
     assert c128 >= 6 * d * d * 16 + 2 * d * d * 16
     assert e(FAKE, 0, 8, q.C64, FAKE, None, None, 0, None) == q.OK   # empty batch is a no-op
+    # the split-BF16 products take the complex64 layout and workspace
+    assert q.workspace_bytes(q.FN_EXPM, 2, 40, 1, 1, q.C64_BF16X3) == q.workspace_bytes(q.FN_EXPM, 2, 40, 1, 1, q.C64)
+    assert e(FAKE, 0, 8, q.C64_BF16X3, FAKE, None, None, 0, None) == q.OK
+    assert e(FAKE, 2, 8, q.C64_BF16X3, FAKE, None, None, 0, None) == q.EWORKSPACE
+    # the skew-Hermitian flag rides on the dtype; other bits stay invalid
+    assert e(FAKE, 0, 8, q.C64 | q.SKEW_HERMITIAN, FAKE, None, None, 0, None) == q.OK
+    assert e(FAKE, 2, 8, 5 | q.SKEW_HERMITIAN, FAKE, None, FAKE, 1 << 30, None) == q.EINVAL
+    assert e(FAKE, 2, 8, q.C64 | 0x200, FAKE, None, FAKE, 1 << 30, None) == q.EINVAL
+    assert e(FAKE, 2, 8, q.C64 | q.SKEW_HERMITIAN, FAKE, None, None, 0, None) == q.EWORKSPACE
+    # the squaring bound rides on bits 16..23
+    assert e(FAKE, 0, 8, q.C128 | q.squaring_bound_flag(7), FAKE, None, None, 0, None) == q.OK
+    assert e(FAKE, 2, 8, 5 | q.squaring_bound_flag(7), FAKE, None, FAKE, 1 << 30, None) == q.EINVAL
+    assert e(FAKE, 2, 8, q.C64 | (1 << 24), FAKE, None, FAKE, 1 << 30, None) == q.EINVAL
+    assert q.squaring_bound_flag(0) == 1 << 16 and q.squaring_bound_flag(254) == 255 << 16
+    with pytest.raises(ValueError):
+        q.squaring_bound_flag(255)
 
 
 def test_propagate_validation():

@@ -120,17 +120,20 @@ def test_generators_parity(d, K, order, dtype):
 EXPM_DIMS = [1, 2, 3, 7, 8, 16, 17, 31, 32, 33, 64, 100, 128, 257]
 
 
+@pytest.mark.parametrize("skew", [False, True], ids=["general", "skew"])
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 @pytest.mark.parametrize("d", EXPM_DIMS)
-def test_expm_parity(d, dtype):
-    say(f"expm d={d} {dtype}")
+def test_expm_parity(d, dtype, skew):
+    # skew=True declares the inputs skew-Hermitian: the Hermitian Pade products
+    # are formed by halves and mirrored
+    say(f"expm d={d} {dtype} skew={skew}")
     norms = [0.0, 0.01, 1.0, 5.3, 5.4, 11.0, 11.5, 20.0, 170.0, 1500.0]   # s = 0 .. 9
     Om = wl.random_skew_hermitian_batch(len(norms), d, norms, config_id=300 + d)
     ref = oracle.expm_skew_hermitian(Om)
     seen = Om.astype(np.complex64).astype(np.complex128) if dtype == torch.complex64 else Om
     s_ref = [oracle.scaling_exponent(x) for x in seen]
     om = gpu(Om).to(dtype)
-    U, s = q.expm_batched(om)
+    U, s = q.expm_batched(om, skew_hermitian=skew)
     torch.cuda.synchronize()
     Ug = host(U).astype(np.complex128)
     assert list(host(s)) == s_ref
@@ -143,18 +146,19 @@ def test_expm_parity(d, dtype):
         assert oracle.unitarity_error(Ug) <= 1e-3
 
 
+@pytest.mark.parametrize("skew", [False, True], ids=["general", "skew"])
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 @pytest.mark.parametrize("d", [1024, 1030])
-def test_expm_parity_large(d, dtype):
+def test_expm_parity_large(d, dtype, skew):
     # d <= 1024 factors with register-resident panels, d > 1024 through the
     # global-memory panel kernel
-    say(f"expm large d={d} {dtype}")
+    say(f"expm large d={d} {dtype} skew={skew}")
     norms = [3.0, 60.0, 900.0]
     Om = wl.random_skew_hermitian_batch(len(norms), d, norms, config_id=400 + d)
     ref = oracle.expm_skew_hermitian(Om)
     seen = Om.astype(np.complex64).astype(np.complex128) if dtype == torch.complex64 else Om
     s_ref = [oracle.scaling_exponent(x) for x in seen]
-    U, s = q.expm_batched(gpu(Om).to(dtype))
+    U, s = q.expm_batched(gpu(Om).to(dtype), skew_hermitian=skew)
     torch.cuda.synchronize()
     Ug = host(U).astype(np.complex128)
     assert list(host(s)) == s_ref
@@ -164,28 +168,93 @@ def test_expm_parity_large(d, dtype):
         assert np.abs(Ug - ref).max() <= 1e-10
 
 
+@pytest.mark.parametrize("skew", [False, True], ids=["general", "skew"])
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
-@pytest.mark.parametrize("d", [20, 45])
-def test_expm_chunked_alias_and_nonfinite(d, dtype):
+@pytest.mark.parametrize("d", [20, 45, 200])
+def test_expm_chunked_alias_and_nonfinite(d, dtype, skew):
     # d <= 32 runs the fused one-workgroup kernel, larger d the batched path
-    say(f"expm chunking d={d} {dtype}")
+    say(f"expm chunking d={d} {dtype} skew={skew}")
     B = 7
     Om = wl.random_skew_hermitian_batch(B, d, np.linspace(0.5, 300, B), config_id=77)
     om = gpu(Om).to(dtype)
-    U1, s1 = q.expm_batched(om)                        # one chunk
-    U2, s2 = q.expm_batched(om, chunk=3)               # chunks of 3, 3, 1
+    U1, s1 = q.expm_batched(om, skew_hermitian=skew)                        # one chunk
+    U2, s2 = q.expm_batched(om, chunk=3, skew_hermitian=skew)               # chunks of 3, 3, 1
     om3 = om.clone()
-    U3, s3 = q.expm_batched(om3, U=om3, chunk=2)       # in place
+    U3, s3 = q.expm_batched(om3, U=om3, chunk=2, skew_hermitian=skew)       # in place
     torch.cuda.synchronize()
     assert torch.equal(U1, U2) and torch.equal(U1, U3)
     assert torch.equal(s1, s2) and torch.equal(s1, s3)
     bad = om.clone()
     bad[2, 3, 4] = float("nan")
-    U4, s4 = q.expm_batched(bad)
+    U4, s4 = q.expm_batched(bad, skew_hermitian=skew)
     torch.cuda.synchronize()
     assert int(s4[2]) == -1 and torch.isnan(U4[2]).all()
     keep = [0, 1, 3, 4, 5, 6]
     assert torch.equal(U4[keep], U1[keep])
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("d", [33, 129, 300])
+def test_expm_skew_matches_general(d, dtype):
+    # the structured products are the general ones up to rounding; with one
+    # tile (d = 33 on the FP32 128 tile) and several (129, 300, ragged)
+    say(f"expm skew vs general d={d} {dtype}")
+    norms = [0.7, 6.0, 45.0, 400.0]
+    Om = wl.random_skew_hermitian_batch(len(norms), d, norms, config_id=900 + d)
+    om = gpu(Om).to(dtype)
+    Ug, sg = q.expm_batched(om)
+    Us, ss = q.expm_batched(om, skew_hermitian=True)
+    torch.cuda.synchronize()
+    assert torch.equal(sg, ss)
+    a, b = host(Ug).astype(np.complex128), host(Us).astype(np.complex128)
+    inf = np.abs(oracle.propagator_infidelity(a, b))
+    assert np.all(inf <= 2 * inf_tol(dtype, host(ss))), inf
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_expm_squaring_bound(dtype):
+    # a bound at or above every exponent changes no bit; items above a smaller
+    # bound come back with s = -2 and NaN, the others unchanged
+    d = 70
+    norms = [0.5, 20.0, 300.0, 6000.0]       # s = 0, 2, 6, 11
+    Om = wl.random_skew_hermitian_batch(len(norms), d, norms, config_id=950)
+    om = gpu(Om).to(dtype)
+    say(f"expm squaring bound {dtype}")
+    U0, s0 = q.expm_batched(om, skew_hermitian=True)
+    U1, s1 = q.expm_batched(om, skew_hermitian=True, squaring_bound=int(s0.max()))
+    U2, s2 = q.expm_batched(om, skew_hermitian=True, squaring_bound=20)
+    U3, s3 = q.expm_batched(om, skew_hermitian=True, squaring_bound=5, chunk=3)
+    torch.cuda.synchronize()
+    assert host(s0).tolist() == [0, 2, 6, 11]
+    assert torch.equal(U0, U1) and torch.equal(U0, U2) and torch.equal(s0, s1) and torch.equal(s0, s2)
+    assert host(s3).tolist() == [0, 2, -2, -2]
+    assert torch.equal(U3[:2], U0[:2]) and torch.isnan(U3[2:]).all()
+
+
+def test_expm_capture_needs_a_bound():
+    dtype = torch.complex64
+    om = gpu(wl.random_skew_hermitian_batch(2, 50, 10.0, config_id=951)).to(dtype)
+    U = torch.empty_like(om)
+    s = torch.empty(2, dtype=torch.int32, device=DEV)
+    ws = torch.empty(q.workspace_bytes(q.FN_EXPM, 2, 50, 1, 1, q.C64), dtype=torch.uint8, device=DEV)
+    q.expm_batched(om, U=U, s_out=s, ws=ws, skew_hermitian=True)      # tunes the tile outside capture
+    torch.cuda.synchronize()
+    ref = U.clone()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            with pytest.raises(q.QcheffError):
+                q.expm_batched(om, U=U, s_out=s, ws=ws, skew_hermitian=True)
+            q.expm_batched(om, U=U, s_out=s, ws=ws, skew_hermitian=True, squaring_bound=8)
+    torch.cuda.current_stream().wait_stream(side)
+    for _ in range(3):
+        U.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(U, ref)
 
 
 # -------------------------------------------------------------------- chain
@@ -248,7 +317,15 @@ def test_random_system_order2_end_to_end(dtype):
     tol = INF_TOL[dtype]
     assert np.all(oracle.propagator_infidelity(ref["U"], U) <= tol)
     assert oracle.state_infidelity(ref["psi"], host(out["psi"])) <= tol
-    assert oracle.propagator_infidelity(ref["P"], host(out["P"]).astype(np.complex128)) <= tol
+    # The chained state and product are compared by direction (normalised); their
+    # norm / distance from unitarity on its own: each interval may leave a radial
+    # error up to 2^s u (FP32), and over M intervals these add at worst linearly.
+    P = host(out["P"]).astype(np.complex128)
+    assert oracle.propagator_infidelity(ref["P"], P, normalized=True) <= tol
+    s_max = int(out["s"].max())
+    nbound = 1e-12 if dtype == torch.complex128 else w.M * 2.0 ** s_max * U32
+    assert oracle.norm_error(host(out["psi"])) <= nbound
+    assert oracle.unitarity_error(P) <= nbound
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])

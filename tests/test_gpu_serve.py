@@ -45,7 +45,8 @@ def test_mix_equals_alone_and_oracle():
         assert np.array_equal(psi_alone, res[r.rid].psi), r.rid        # bit-identical
         ref = oracle.run(r.H0, r.Hk, r.u, r.dt_sample, r.M, r.order, psi0=r.psi0)
         inf = abs(oracle.state_infidelity(ref["psi"], res[r.rid].psi))
+        assert inf <= (1e-12 if r.precision == "c128" else 1e-6), (r.rid, inf)
         # FP32: every interval may leave a radial error up to 2^s u (see the parity
         # tests); over M intervals they add at worst linearly
-        tol = 1e-12 if r.precision == "c128" else max(1e-6, r.M * 2.0 ** res[r.rid].s_max * 2.0 ** -24)
-        assert inf <= tol, (r.rid, inf, tol)
+        nbound = r.M * 1e-13 if r.precision == "c128" else r.M * 2.0 ** res[r.rid].s_max * 2.0 ** -24
+        assert oracle.norm_error(res[r.rid].psi) <= nbound, r.rid

@@ -28,6 +28,9 @@ MUTANTS = {
     "scaling_step": ("        s += 1\n    return s", "        s += 2\n    return s"),
     "state_adjoint": ("psi = Un @ psi", "psi = Un.conj().T @ psi"),
     "drift_dropped": ("H = dt_interval * H0", "H = 0.0 * H0"),
+    "infidelity_unnormalised": ("/ (na * nb)", "/ 1.0"),
+    "infidelity_no_square": ("abs(np.vdot(a, b)) ** 2", "abs(np.vdot(a, b))"),
+    "prop_infidelity_norm_one_side": ("np.abs(tr) ** 2 / (na * nb)", "np.abs(tr) ** 2 / (na * na)"),
 }
 
 

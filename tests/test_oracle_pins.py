@@ -178,6 +178,39 @@ def test_determinant_and_unitarity():
     np.testing.assert_allclose(res["P"] @ w.psi0, res["psi"], atol=1e-12)
 
 
+def test_state_infidelity_of_rays():
+    # a global phase or a rescaling leaves the state (a ray) unchanged; orthogonal
+    # states are infidelity 1; two unit vectors at angle a give sin^2 a
+    g = np.random.default_rng(3)
+    psi = g.standard_normal(6) + 1j * g.standard_normal(6)
+    psi /= np.linalg.norm(psi)
+    assert abs(oracle.state_infidelity(psi, 1.7 * np.exp(0.4j) * psi)) < 1e-15
+    e0, e1 = np.eye(2)[0].astype(complex), np.eye(2)[1].astype(complex)
+    assert oracle.state_infidelity(e0, e1) == pytest.approx(1.0, abs=1e-15)
+    a = 0.3
+    assert oracle.state_infidelity(e0, math.cos(a) * e0 + 1j * math.sin(a) * e1) == pytest.approx(math.sin(a) ** 2,
+                                                                                                   abs=1e-15)
+    assert oracle.norm_error(1.25 * psi) == pytest.approx(0.25, abs=1e-15)
+    assert oracle.norm_error(psi) < 1e-15
+
+
+def test_normalized_propagator_infidelity():
+    # equal to the d^2 form for unitary operands; blind to a rescaling; 1 for
+    # trace-orthogonal operators; never negative (Cauchy-Schwarz)
+    U = sl.expm(-1j * wl.random_hermitian(5, np.random.default_rng(4)))
+    V = sl.expm(-1j * wl.random_hermitian(5, np.random.default_rng(5)))
+    assert oracle.propagator_infidelity(U, V, normalized=True) == pytest.approx(oracle.propagator_infidelity(U, V),
+                                                                                abs=1e-14)
+    assert abs(oracle.propagator_infidelity(U, 1.3 * np.exp(0.2j) * U, normalized=True)) < 1e-15
+    assert abs(oracle.propagator_infidelity(U, 1.3 * U)) > 0.5                 # the d^2 form sees the norm
+    Z = np.diag([1.0, -1.0]).astype(complex)
+    assert oracle.propagator_infidelity(np.eye(2), Z, normalized=True) == pytest.approx(1.0, abs=1e-15)
+    g = np.random.default_rng(6)
+    A = g.standard_normal((3, 4, 4)) + 1j * g.standard_normal((3, 4, 4))
+    B = g.standard_normal((3, 4, 4)) + 1j * g.standard_normal((3, 4, 4))
+    assert np.all(oracle.propagator_infidelity(A, B, normalized=True) >= -1e-15)
+
+
 def test_scaling_exponent_definition():
     th = oracle.THETA13_F64
     g = np.random.default_rng(5)

@@ -2,7 +2,8 @@
 import numpy as np
 import pytest
 
-from paper_2411_09982_amd.serve import Admission, Request, job_bytes, poisson_requests
+from paper_2411_09982_amd.serve import (Admission, Request, Result, job_bytes, latency_percentiles, max_overlap,
+                                         poisson_requests)
 
 
 def test_fifo_budget_and_slots():
@@ -54,3 +55,14 @@ def test_poisson_arrivals_deterministic():
     t = np.array([r.arrival for r in r1])
     assert np.all(np.diff(t) > 0) and np.allclose(t, [r.arrival for r in r2])
     assert 0.2 < t[-1] < 1.0            # 50 arrivals at 100 /s
+
+
+def test_latency_split_into_wait_and_service():
+    res = {i: Result(i, np.zeros(1), 0, arrival=0.0, admitted=0.1 * i, done=0.1 * i + 1.0) for i in range(5)}
+    lat = latency_percentiles(res)
+    assert lat["n"] == 5
+    assert lat["service_p50_ms"] == pytest.approx(1000.0) and lat["service_p99_ms"] == pytest.approx(1000.0)
+    assert lat["wait_p50_ms"] == pytest.approx(200.0)
+    assert lat["p50_ms"] == pytest.approx(1200.0)
+    assert lat["p99_ms"] == pytest.approx(1000.0 + 0.99 * 400.0)
+    assert max_overlap(res) == 5
