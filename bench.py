@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128", "bf16x3"],
                     help="c64: FP32 MFMA products; bf16x3: the same complex64 path with the products on BF16 "
                          "MFMA (three-way split operands); c128: FP64 throughout")
+    ap.add_argument("--lanes", type=int, default=1,
+                    help="exponential pipelines (streams + host threads) that take the chunks in turn")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-fp64-compare", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -77,6 +79,10 @@ def parse():
                     help="batched-sweep mode: 512 transmon-chain instances, d in {16..512}, M = 256, order 2; "
                          "prints one JSON line")
     ap.add_argument("--sweep-jobs", type=int, default=512)
+    ap.add_argument("--action", action="store_true",
+                    help="state-only mode: the first intervals of the d = 4096 job by the Taylor action vs the "
+                         "propagator path; prints one JSON line")
+    ap.add_argument("--action-intervals", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
@@ -108,7 +114,7 @@ def build_workload(name):
 class Job:
     """Device-resident inputs and preallocated buffers for one workload."""
 
-    def __init__(self, w, dtype_name, chunk):
+    def __init__(self, w, dtype_name, chunk, lanes=1):
         import torch
         import paper_2411_09982_amd as q
         self.q, self.torch, self.w = q, torch, w
@@ -129,11 +135,19 @@ class Job:
         gen_ws = q.workspace_bytes(q.FN_GENERATORS, 1, d, K, w.order, q.C128)
         self.gen_ws = torch.empty(max(gen_ws, 1), dtype=torch.uint8, device=dev) if gen_ws else None
         self.chunk = min(chunk, M)
-        self.exp_ws = torch.empty(q.workspace_bytes(q.FN_EXPM, self.chunk, d, 1, 1, code), dtype=torch.uint8,
-                                  device=dev)
+        # `lanes` exponential pipelines, each with its own workspace, HIP stream and
+        # host thread, take the chunks in turn, so that one chunk's latency-bound
+        # LU kernels overlap another chunk's GEMMs
+        self.lanes = max(1, int(lanes))
+        ws_bytes = q.workspace_bytes(q.FN_EXPM, self.chunk, d, 1, 1, code)
+        self.exp_ws = [torch.empty(ws_bytes, dtype=torch.uint8, device=dev) for _ in range(self.lanes)]
+        self.lane_streams = [torch.cuda.Stream() for _ in range(self.lanes)] if self.lanes > 1 else None
         self.prop_ws = torch.empty(q.workspace_bytes(q.FN_PROPAGATE, M, d, 1, q.STATE, code), dtype=torch.uint8,
                                    device=dev)
         self.side = torch.cuda.Stream()   # default priority
+        if self.lanes > 1:
+            import concurrent.futures
+            self.pool = concurrent.futures.ThreadPoolExecutor(self.lanes)
 
     def step(self):
         """The whole path; the state chain of chunk c runs on a side stream while the
@@ -144,14 +158,44 @@ class Job:
         q.magnus_generators(self.H0, self.Hk, self.c1, self.c2, w.dt_interval, w.order, self.dtype,
                             omega=self.omega, ws=self.gen_ws)
         self.psi.copy_(self.psi0)
-        for c0 in range(0, w.M, self.chunk):
-            c1 = min(w.M, c0 + self.chunk)
+        if self.lanes == 1:
+            for c0 in range(0, w.M, self.chunk):
+                c1 = min(w.M, c0 + self.chunk)
+                U = self.omega[c0:c1]
+                q.expm_batched(U, U=U, s_out=self.s[c0:c1], ws=self.exp_ws[0], skew_hermitian=True,
+                               bf16x3=self.bf16x3)
+                ev = torch.cuda.Event()
+                ev.record(main)
+                self.side.wait_event(ev)
+                q.propagate(U, q.STATE, self.psi, ws=self.prop_ws, stream=self.side)
+            main.wait_stream(self.side)
+            return
+        ready = torch.cuda.Event()
+        ready.record(main)
+        chunks = [(c0, min(w.M, c0 + self.chunk)) for c0 in range(0, w.M, self.chunk)]
+
+        def run(idx):
+            lane = idx % self.lanes
+            st = self.lane_streams[lane]
+            c0, c1 = chunks[idx]
+            st.wait_event(ready)
             U = self.omega[c0:c1]
-            q.expm_batched(U, U=U, s_out=self.s[c0:c1], ws=self.exp_ws, skew_hermitian=True, bf16x3=self.bf16x3)
+            q.expm_batched(U, U=U, s_out=self.s[c0:c1], ws=self.exp_ws[lane], skew_hermitian=True,
+                           bf16x3=self.bf16x3, stream=st)
             ev = torch.cuda.Event()
-            ev.record(main)
-            self.side.wait_event(ev)
-            q.propagate(U, q.STATE, self.psi, ws=self.prop_ws, stream=self.side)
+            ev.record(st)
+            return ev
+
+        # lane l takes chunks l, l + lanes, ...; a lane's next chunk is enqueued
+        # after its previous one (same stream), the chain follows chunk order
+        futs = {}
+        for idx in range(len(chunks)):
+            prev = futs.get(idx - self.lanes)
+            futs[idx] = self.pool.submit(lambda i=idx, p=prev: (p.result() if p else None, run(i))[1])
+        for idx in range(len(chunks)):
+            c0, c1 = chunks[idx]
+            self.side.wait_event(futs[idx].result())
+            q.propagate(self.omega[c0:c1], q.STATE, self.psi, ws=self.prop_ws, stream=self.side)
         main.wait_stream(self.side)
 
 
@@ -282,8 +326,76 @@ def sweep(a):
     timed_runs("hip graph per group")
 
 
+def action(a):
+    """State-only propagation at d = 4096 (four coupled transmons, K = 4, order 2): the
+    first `--action-intervals` intervals by the Taylor action on the generators, against
+    the propagator path (expm + chain) of the same intervals."""
+    import torch
+    import paper_2411_09982_amd as q
+    import workloads as wl
+    w = wl.coupled_transmons()
+    P = a.action_intervals
+    dev = "cuda:0"
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    H0, Hk, u, psi0 = t(w.H0), t(w.Hk), t(w.u), t(w.psi0)
+    c1, c2 = q.magnus_coeffs(u, w.dt_sample, w.M, w.order)
+    c1p, c2p = c1[:P].contiguous(), c2[:P].contiguous()
+    out = {}
+    for dt_name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
+        om, gws = q.magnus_generators(H0, Hk, c1p, c2p, w.dt_interval, w.order, dtype)
+        ws = torch.empty(q.workspace_bytes(q.FN_ACTION, P, w.d, 1, 1, q.C64 if dt_name == "c64" else q.C128),
+                         dtype=torch.uint8, device=dev)
+        x = psi0.clone()
+        q.propagate_action(om, x, ws=ws)              # warm-up
+        torch.cuda.synchronize()
+        q.timing_enable(True)
+        x = psi0.clone()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            x.copy_(psi0)
+            q.magnus_generators(H0, Hk, c1p, c2p, w.dt_interval, w.order, dtype, omega=om, ws=gws,
+                                reuse_basis=True)
+            q.propagate_action(om, x, ws=ws)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / a.steps
+        k = q.timing_read(q.KERNEL_ACTION)
+        q.timing_enable(False)
+        out[f"action_{dt_name}"] = dict(intervals_per_s=round(P / el, 2), ms_per_interval=round(1000 * el / P, 3),
+                                        products_per_interval=round(k["launches"] / a.steps / P, 1),
+                                        term_kernel_avg_us=round(1000 * k["ms"] / max(k["launches"], 1), 2),
+                                        term_kernel_gbs=round(k["bytes"] / max(k["ms"], 1e-9) * 1e-6, 1))
+        out[f"psi_action_{dt_name}"] = x.cpu().numpy()
+        del om, ws
+        torch.cuda.empty_cache()
+    # the propagator path of the same intervals (FP32 products, FP64 solve)
+    om, _ = q.magnus_generators(H0, Hk, c1p, c2p, w.dt_interval, w.order, torch.complex64)
+    ews = torch.empty(q.workspace_bytes(q.FN_EXPM, min(P, 32), w.d, 1, 1, q.C64), dtype=torch.uint8, device=dev)
+    pws = torch.empty(q.workspace_bytes(q.FN_PROPAGATE, P, w.d, 1, q.STATE, q.C64), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q.magnus_generators(H0, Hk, c1p, c2p, w.dt_interval, w.order, torch.complex64, omega=om)
+    q.expm_batched(om, U=om, ws=ews, skew_hermitian=True)
+    x = psi0.clone()
+    q.propagate(om, q.STATE, x, ws=pws)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    psi_full = x.cpu().numpy()
+    a64, a32 = out.pop("psi_action_c128"), out.pop("psi_action_c64")
+    inf = lambda p, r: float(1 - abs(np.vdot(r, p)) ** 2 / (np.vdot(r, r).real * np.vdot(p, p).real))
+    out["propagators_c64"] = dict(intervals_per_s=round(P / el, 2), ms_per_interval=round(1000 * el / P, 3))
+    out["speedup_action_c64_vs_propagators"] = round(out["action_c64"]["intervals_per_s"] / (P / el), 2)
+    out["state_infidelity_action_c64_vs_action_c128"] = inf(a32, a64)
+    out["state_infidelity_propagators_c64_vs_action_c128"] = inf(psi_full, a64)
+    print(json.dumps(dict(metric="state-only propagation (Taylor action): intervals/s",
+                          config=dict(workload=w.name, d=w.d, K=w.K, M=w.M, order=w.order, intervals_timed=P),
+                          data="synthetic", **out)), flush=True)
+
+
 def main():
     a = parse()
+    if a.action:
+        action(a)
+        return
     if a.sweep:
         sweep(a)
         return
@@ -302,7 +414,7 @@ def main():
     q.lib()
     w = build_workload(a.workload)
     chunk = a.chunk or DEFAULT_CHUNK[a.dtype]
-    job = Job(w, a.dtype, chunk)
+    job = Job(w, a.dtype, chunk, a.lanes)
     elapsed, times, kern = timed(job, a.steps, a.warmup)
     s_hist = job.s.cpu().numpy().tolist()
     value = w.M * a.steps / elapsed
@@ -333,6 +445,7 @@ def main():
                          algorithmic_tflops=round(kern["bf16x3"]["flops"] / max(kern["bf16x3"]["ms"], 1e-9) * 1e-9,
                                                   2)),
         chunk=job.chunk,
+        lanes=job.lanes,
     )
     psi_mixed = job.psi.cpu().numpy()
     U_samples = {n: job.omega[n].cpu().numpy().astype(np.complex128) for n in (0, w.M // 2, w.M - 1)}

@@ -91,6 +91,7 @@ extern "C" {
 #define QCHEFF_FN_GENERATORS 1
 #define QCHEFF_FN_EXPM       2
 #define QCHEFF_FN_PROPAGATE  3
+#define QCHEFF_FN_ACTION     4  /* qcheff_propagate_action: batch = M */
 
 /*
  * qcheff_magnus_coeffs - per-interval Magnus coefficients of the control
@@ -206,6 +207,32 @@ int qcheff_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, v
 int qcheff_propagate_batched(const void* U, int64_t B, int64_t M, int64_t d, int dtype, void* x, void* stream);
 
 /*
+ * qcheff_propagate_action - the stroboscopic state chain of Sec. 4.1 taken from
+ * the generators, psi_M = exp(Omega_M) ... exp(Omega_1) psi_0, without forming
+ * any exp(Omega_n): each factor acts on the state through a truncated Taylor
+ * series (O(d^2) per matrix-vector product instead of O(d^3) per propagator;
+ * pays off when d is large and ||Omega_n|| moderate, e.g. many short intervals).
+ *
+ *   omega      [M][d][d], device, dtype (QCHEFF_C128 or QCHEFF_C64): the
+ *              generators as qcheff_magnus_generators writes them.
+ *   x          [d] complex128, device, in: psi_0, out: psi_M (FP64 state,
+ *              products accumulate in FP64).
+ *   traj       optional [M+1][d] complex128: psi_0 ... psi_M.
+ *   tol        truncation tolerance per interval relative to |psi| (0: the unit
+ *              roundoff of dtype, 2^-53 or 2^-24).
+ *   Per interval, mu = tr(Omega)/d is split off (exp(Omega) = e^mu exp(Omega -
+ *   mu I)); nu = sqrt(||Omega - mu I||_1 ||Omega - mu I||_inf) bounds the
+ *   2-norm; the degree m <= 55 and the number of steps s minimise m s subject to
+ *   s * sum_{k>m} (nu/s)^k / k! <= tol.  A non-finite generator makes the state
+ *   NaN.  The call waits on `stream` once (to read the M shifts and norms).
+ *   ws         qcheff_workspace_bytes(QCHEFF_FN_ACTION, M, d, ..) bytes.
+ *   Returns QCHEFF_OK, QCHEFF_EINVAL, QCHEFF_EWORKSPACE, QCHEFF_EDEVICE,
+ *   QCHEFF_EUNSUPPORTED (an interval would need more than 2^24 products).
+ */
+int qcheff_propagate_action(const void* omega, int64_t M, int64_t d, int dtype, void* x, void* traj,
+                            double tol, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * qcheff_workspace_bytes - workspace needed by `fn` (QCHEFF_FN_*):
  *   GENERATORS: (batch, K, order, d) -> commutator basis bytes (0 for order 1);
  *   EXPM:       bytes to process `batch` items at once (per-item size x batch);
@@ -227,7 +254,7 @@ const char* qcheff_last_error(void);
  *   qcheff_timing_enable(1) clears old records and starts recording;
  *   qcheff_timing_enable(0) clears them and stops.
  *   qcheff_timing_read(kernel, ...) waits for the recorded events of `kernel`
- *   (QCHEFF_KERNEL_GEMM_F32 / _F64 / _BF16X3), returns the number of launches, the summed
+ *   (QCHEFF_KERNEL_GEMM_F32 / _F64 / _BF16X3 / _ACTION), returns the number of launches, the summed
  *   event-to-event time in ms and the summed flops and bytes, and releases
  *   those records.  Returns QCHEFF_OK, QCHEFF_EINVAL, QCHEFF_EDEVICE.
  * Recording costs two event records per GEMM launch; leave it off otherwise.
@@ -235,6 +262,7 @@ const char* qcheff_last_error(void);
 #define QCHEFF_KERNEL_GEMM_F32 1
 #define QCHEFF_KERNEL_GEMM_F64 2
 #define QCHEFF_KERNEL_GEMM_BF16X3 3
+#define QCHEFF_KERNEL_ACTION 4   /* one Taylor term of qcheff_propagate_action: 8 d^2 flops, d^2 elements read */
 int qcheff_timing_enable(int on);
 int qcheff_timing_read(int kernel, int64_t* launches, double* total_ms, double* flops, double* bytes);
 

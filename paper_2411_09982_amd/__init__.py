@@ -12,7 +12,8 @@ Functions (same names as the C entry points, minus the ``qcheff_`` prefix):
   magnus_generators(H0, Hk, c1, c2, dt_interval, order, out_dtype) -> omega
   expm_batched(omega)                                   -> U, s
   propagate(U, mode, x)                                 -> x (in place)
-and ``evolve(...)``, the four calls in sequence (the paper's evolve()).
+and ``evolve(...)``, the four calls in sequence (the paper's evolve()), and
+``evolve_state(...)``, the state-only path through qcheff_propagate_action.
 """
 from __future__ import annotations
 
@@ -30,9 +31,9 @@ OK, EINVAL, EWORKSPACE, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -5
 C128, C64, C64_BF16X3 = 1, 2, 3
 STATE, PRODUCT = 1, 2
 REUSE_BASIS = 1
-FN_GENERATORS, FN_EXPM, FN_PROPAGATE = 1, 2, 3
+FN_GENERATORS, FN_EXPM, FN_PROPAGATE, FN_ACTION = 1, 2, 3, 4
 SKEW_HERMITIAN = 0x100
-KERNEL_GEMM_F32, KERNEL_GEMM_F64, KERNEL_GEMM_BF16X3 = 1, 2, 3
+KERNEL_GEMM_F32, KERNEL_GEMM_F64, KERNEL_GEMM_BF16X3, KERNEL_ACTION = 1, 2, 3, 4
 
 _DTYPES = {torch.complex128: C128, torch.complex64: C64}
 _TORCH = {C128: torch.complex128, C64: torch.complex64}
@@ -61,8 +62,9 @@ def lib() -> ctypes.CDLL:
     L.qcheff_expm_batched.argtypes = [vp, i64, i64, i32, vp, vp, vp, ctypes.c_size_t, vp]
     L.qcheff_propagate.argtypes = [vp, i64, i64, i32, i32, vp, vp, vp, ctypes.c_size_t, vp]
     L.qcheff_propagate_batched.argtypes = [vp, i64, i64, i64, i32, vp, vp]
+    L.qcheff_propagate_action.argtypes = [vp, i64, i64, i32, vp, vp, dbl, vp, ctypes.c_size_t, vp]
     for f in ("qcheff_magnus_coeffs", "qcheff_magnus_generators", "qcheff_expm_batched", "qcheff_propagate",
-              "qcheff_propagate_batched"):
+              "qcheff_propagate_batched", "qcheff_propagate_action"):
         getattr(L, f).restype = i32
     L.qcheff_workspace_bytes.argtypes = [i32, i64, i64, i64, i32, i32]
     L.qcheff_workspace_bytes.restype = ctypes.c_size_t
@@ -212,6 +214,42 @@ def propagate_batched(U, x, stream=None):
     _check("qcheff_propagate_batched", lib().qcheff_propagate_batched(
         _ptr(U), B, M, d, _DTYPES[U.dtype], _ptr(x), _stream(stream)))
     return x
+
+
+def propagate_action(omega, x, traj=None, tol: float = 0.0, ws=None, stream=None):
+    """psi <- exp(omega[M-1]) ... exp(omega[0]) psi by the truncated Taylor action
+    (qcheff_propagate_action); omega [M][d][d] generators, x [d] complex128 in place."""
+    _dev(omega, "omega")
+    _dev(x, "x")
+    M, d = omega.shape[0], omega.shape[-1]
+    if ws is None:
+        ws = _workspace(workspace_bytes(FN_ACTION, M, d, 1, 1, _DTYPES[omega.dtype]), omega.device)
+    _check("qcheff_propagate_action", lib().qcheff_propagate_action(
+        _ptr(omega), M, d, _DTYPES[omega.dtype], _ptr(x), _ptr(traj), float(tol), _ptr(ws), ws.numel(),
+        _stream(stream)))
+    return x
+
+
+def evolve_state(H0, Hk, u, dt_sample: float, M: int, order: int, psi0, dtype=torch.complex64,
+                 chunk: int = 64, tol: float = 0.0, stream=None):
+    """State-only path: coefficients, then per chunk of intervals the generators
+    and the Taylor action on the state (no propagator is formed; the generators
+    of only `chunk` intervals are held at a time).  Returns psi_M."""
+    N = u.shape[1]
+    c1, c2 = magnus_coeffs(u, dt_sample, M, order, stream=stream)
+    d = H0.shape[0]
+    psi = psi0.clone()
+    omega = torch.empty((min(chunk, M), d, d), dtype=dtype, device=H0.device)
+    gen_ws = None
+    act_ws = _workspace(workspace_bytes(FN_ACTION, min(chunk, M), d, 1, 1, _DTYPES[dtype]), H0.device)
+    for c0 in range(0, M, chunk):
+        c1_ = min(M, c0 + chunk)
+        om = omega[: c1_ - c0]
+        _, gen_ws = magnus_generators(H0, Hk, c1[c0:c1_], None if c2 is None else c2[c0:c1_],
+                                      dt_sample * (N // M), order, dtype, omega=om, ws=gen_ws,
+                                      reuse_basis=gen_ws is not None, stream=stream)
+        propagate_action(om, psi, tol=tol, ws=act_ws, stream=stream)
+    return psi
 
 
 def timing_enable(on: bool) -> None:

@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <cstring>
 #include <vector>
 
 #include "../../include/qcheff.h"
@@ -17,6 +18,7 @@
 #include "kernels.hpp"
 #include "lu.hpp"
 #include "expm_small.hpp"
+#include "action.hpp"
 #include "validate.hpp"
 
 namespace qcheff {
@@ -522,6 +524,127 @@ int run_expm(const void* omega, int64_t batch, int64_t d, void* U, int32_t* s_ou
 }
 
 // ---------------------------------------------------------------- propagate
+// ------------------------------------------------------- state-only action
+// sum_{k > m} x^k / k! (x >= 0), summed until the terms stop mattering.
+double taylor_tail(double x, int m) {
+  if (x <= 0.0) return 0.0;
+  double term = std::exp((m + 1) * std::log(x) - std::lgamma(m + 2.0));
+  double sum = 0.0;
+  for (int k = m + 1; k < m + 2000; ++k) {
+    sum += term;
+    term *= x / double(k + 1);
+    if (term <= 1e-17 * sum) break;
+  }
+  return sum;
+}
+
+// Degree m <= 55 and step count s of the truncated Taylor action for a generator
+// whose shifted 2-norm is at most nu: the smallest m s with
+// s * sum_{k>m} (nu/s)^k / k! <= tol (the truncation error of s steps, each
+// exp of a matrix of 2-norm nu/s applied to a unit vector).  s * tail(nu/s) falls
+// with s, so a bisection finds the smallest s for each m.
+void action_params(double nu, double tol, int* m_out, int64_t* s_out) {
+  int best_m = 0;
+  int64_t best_s = 0;
+  double best = 0.0;
+  for (int m = 1; m <= 55; ++m) {
+    auto ok = [&](int64_t s) { return double(s) * taylor_tail(nu / double(s), m) <= tol; };
+    int64_t hi = 1;
+    while (!ok(hi) && hi < (int64_t(1) << 40)) hi *= 2;
+    if (!ok(hi)) continue;
+    int64_t lo = hi / 2 + 1;
+    if (hi == 1) lo = 1;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (ok(mid)) hi = mid; else lo = mid + 1;
+    }
+    const double cost = double(m) * double(hi);
+    if (best_m == 0 || cost < best) {
+      best = cost;
+      best_m = m;
+      best_s = hi;
+    }
+  }
+  *m_out = best_m;
+  *s_out = best_s;
+}
+
+constexpr double kMaxActionTerms = double(1 << 24);   // products per interval
+
+template <typename T>
+int run_action(const void* Ov, int64_t M, int64_t d, void* x, void* traj, double tol, void* ws, size_t ws_bytes,
+               hipStream_t st) {
+  using C2 = typename Cx<T>::t;
+  const C2* Om = static_cast<const C2*>(Ov);
+  const int64_t dd = d * d;
+  Carver cv{static_cast<char*>(ws), ws_bytes};
+  double2* X = cv.take<double2>(size_t(d) * 16);
+  double2* Y = cv.take<double2>(size_t(d) * 16);
+  double2* mu = cv.take<double2>(size_t(M) * 16);
+  unsigned long long* norms = cv.take<unsigned long long>(size_t(M) * 16);
+  double2* F = static_cast<double2*>(x);
+  double2* t = static_cast<double2*>(traj);
+  if (t) QC_HIP(hipMemcpyAsync(t, F, size_t(d) * 16, hipMemcpyDeviceToDevice, st));
+  if (M == 0) return QCHEFF_OK;
+  if (tol <= 0.0) tol = sizeof(T) == 8 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(nblocks(4 * M, 256)), dim3(256), 0, st,
+                     reinterpret_cast<uint32_t*>(norms), 4 * M, 0u);
+  hipLaunchKernelGGL(trace_mean_kernel<C2>, dim3(unsigned(M)), dim3(256), 0, st, Om, int(d), mu);
+  hipLaunchKernelGGL(shifted_norms_kernel<C2>, dim3(nblocks(d, 256), unsigned(M), 2), dim3(256), 0, st, Om, int(d),
+                     mu, norms);
+  QC_HIP(hipGetLastError());
+  // the host sizes every interval's launches from the shift and the norms
+  std::vector<double2> mu_h(static_cast<size_t>(M));
+  std::vector<unsigned long long> nb_h(static_cast<size_t>(2 * M));
+  QC_HIP(hipMemcpyAsync(mu_h.data(), mu, size_t(M) * 16, hipMemcpyDeviceToHost, st));
+  QC_HIP(hipMemcpyAsync(nb_h.data(), norms, size_t(2 * M) * 8, hipMemcpyDeviceToHost, st));
+  QC_HIP(hipStreamSynchronize(st));
+  const double qnan = std::nan("");
+  for (int64_t n = 0; n < M; ++n) {
+    double n1, ninf;
+    std::memcpy(&n1, &nb_h[2 * n], 8);
+    std::memcpy(&ninf, &nb_h[2 * n + 1], 8);
+    const double nu = std::sqrt(n1 * ninf);   // ||.||_2 <= sqrt(||.||_1 ||.||_inf)
+    const double2 m_n = mu_h[n];
+    int m = 0;
+    int64_t s = 1;
+    if (!(nu <= 1.7976931348623157e308) || !std::isfinite(m_n.x) || !std::isfinite(m_n.y)) {
+      m = -1;   // non-finite generator: the state becomes NaN
+    } else if (nu > 0.0) {
+      action_params(nu, tol, &m, &s);
+      if (m == 0 || double(m) * double(s) > kMaxActionTerms)
+        return fail(QCHEFF_EUNSUPPORTED, "qcheff_propagate_action: generator norm too large for the Taylor action "
+                                         "(use qcheff_expm_batched and qcheff_propagate)");
+    }
+    if (m <= 0) {
+      const double2 eta = m < 0 ? make_double2(qnan, qnan)
+                                : make_double2(std::exp(m_n.x) * std::cos(m_n.y), std::exp(m_n.x) * std::sin(m_n.y));
+      hipLaunchKernelGGL(scale_state_kernel, dim3(nblocks(d, 256)), dim3(256), 0, st, F, int(d), eta);
+      QC_HIP(hipGetLastError());
+    } else {
+      const double er = std::exp(m_n.x / double(s)), ph = m_n.y / double(s);
+      const double2 eta = make_double2(er * std::cos(ph), er * std::sin(ph));
+      QC_HIP(hipMemcpyAsync(X, F, size_t(d) * 16, hipMemcpyDeviceToDevice, st));
+      double2* cur = X;
+      double2* nxt = Y;
+      for (int64_t step = 0; step < s; ++step) {
+        for (int j = 1; j <= m; ++j) {
+          LaunchTimer tm;
+          tm.begin(st);
+          hipLaunchKernelGGL(action_term_kernel<C2>, dim3(nblocks(d, 4)), dim3(256), 0, st, Om + n * dd, int(d), cur,
+                             nxt, F, 1.0 / (double(s) * double(j)), m_n, j == m ? 1 : 0, eta);
+          // one complex multiply-add per matrix element; the matrix is read once
+          tm.end(st, KERNEL_ACTION, 8.0 * double(dd), double(dd) * sizeof(C2) + 4.0 * 16.0 * double(d));
+          std::swap(cur, nxt);
+        }
+      }
+      QC_HIP(hipGetLastError());
+    }
+    if (t) QC_HIP(hipMemcpyAsync(t + (n + 1) * d, F, size_t(d) * 16, hipMemcpyDeviceToDevice, st));
+  }
+  return QCHEFF_OK;
+}
+
 template <typename T>
 int run_propagate(const void* Uv, int64_t M, int64_t d, int mode, void* x, void* traj, void* ws, hipStream_t st) {
   using C2 = typename Cx<T>::t;
@@ -632,6 +755,15 @@ int qcheff_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, v
   hipStream_t st = static_cast<hipStream_t>(stream);
   return dtype == QCHEFF_C128 ? run_propagate<double>(U, M, d, mode, x, traj, ws, st)
                               : run_propagate<float>(U, M, d, mode, x, traj, ws, st);
+}
+
+int qcheff_propagate_action(const void* omega, int64_t M, int64_t d, int dtype, void* x, void* traj, double tol,
+                            void* ws, size_t ws_bytes, void* stream) {
+  Check c = check_action(omega, M, d, dtype, x, tol, ws, ws_bytes);
+  if (c.status) return fail(c);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return dtype == QCHEFF_C128 ? run_action<double>(omega, M, d, x, traj, tol, ws, ws_bytes, st)
+                              : run_action<float>(omega, M, d, x, traj, tol, ws, ws_bytes, st);
 }
 
 int qcheff_propagate_batched(const void* U, int64_t B, int64_t M, int64_t d, int dtype, void* x, void* stream) {

@@ -20,7 +20,7 @@ namespace qcheff {
 enum { EPI_STD = 0, EPI_AUG = 1 };
 
 // Kernel ids of the timing instrumentation (match QCHEFF_KERNEL_* in qcheff.h).
-enum { KERNEL_GEMM_F32 = 1, KERNEL_GEMM_F64 = 2, KERNEL_GEMM_BF16X3 = 3 };
+enum { KERNEL_GEMM_F32 = 1, KERNEL_GEMM_F64 = 2, KERNEL_GEMM_BF16X3 = 3, KERNEL_ACTION = 4 };
 
 // Records a HIP event pair around a launch while timing is enabled.
 struct LaunchTimer {

@@ -1,18 +1,18 @@
 // Batched complex GEMM with FP32 operands on the BF16 matrix cores (gfx950).
 //
 // Every FP32 operand value x is split into three BF16 parts, each rounded to
-// nearest from what the previous ones leave: x = h + m + l + r with |m| <= 2^-8 |x|,
-// |l| <= 2^-16 |x| and |r| <= 2^-24 |x|.  A real product keeps the six part
-// products down to order 2^-16 (l*h, h*l, m*m, m*h, h*m, h*h, in rising size);
-// the three it drops (m*l, l*m, l*l) are below 2^-23 of |x||y|, so a sum of
-// products is as accurate as FP32 arithmetic while it runs on 16x16x32 BF16
-// MFMA (FP32 accumulation) at 2.5 PFLOP/s instead of FP32 MFMA at 157 TFLOP/s.
+// nearest from what the previous ones leave: x = h + m + l exactly for normal
+// numbers, with |m| <= 2^-9 |x| and |l| <= 2^-18 |x|.  A real product keeps the
+// six part products down to order 2^-18 (l*h, h*l, m*m, m*h, h*m, h*h, in rising
+// size); the three it drops (m*l, l*m, l*l) are below 2^-26 of |x||y|.  The part
+// products are exact in FP32, so a sum of products carries the accumulation
+// error of the BF16 instruction instead of that of FP32 MFMA, and runs on
+// 16x16x32 BF16 MFMA (FP32 accumulation) at 2.5 PFLOP/s instead of 157 TFLOP/s.
 //
-// Same parameters, tile mapping and epilogues as cgemm_kernel<float>.  The loader
-// splits each value once as it moves a tile into LDS, where every operand is
-// stored as six BF16 planes (re h, m, l; im h, m, l) with k contiguous, so that a
-// lane reads the eight consecutive k values of one 16x16x32 fragment at once.
-// LDS holds one K step (122 KB); the next is fetched into registers meanwhile.
+// Same parameters, tile mapping and epilogues as cgemm_kernel<float>.  Tiles sit
+// in LDS as FP32 (k-major, double-buffered: one barrier per K step); each wave
+// splits the fragments it reads (v_cvt_pk_bf16_f32 rounds two values at once),
+// so the splitting runs on the vector ALU beside the wave's MFMAs.
 #pragma once
 
 #include "cgemm.hpp"
@@ -29,18 +29,38 @@ __device__ __forceinline__ f32x4 mfma16_bf16(u32x4 a, u32x4 b, f32x4 c) {
                                                   0, 0, 0);
 }
 
-// BF16 bits of x rounded to nearest even (NaN stays a quiet NaN).
-__device__ __forceinline__ unsigned bf16_rne(float x) {
-  const unsigned u = __float_as_uint(x);
-  return (x != x) ? 0x7fc0u : (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values rounded to nearest-even BF16 and packed (a in the low half).
+__device__ __forceinline__ unsigned pk_bf16(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{a, b}, bf16x2));
 }
 
-__device__ __forceinline__ void split3(float x, unsigned& h, unsigned& m, unsigned& l) {
-  h = bf16_rne(x);
-  const float r1 = x - __uint_as_float(h << 16);
-  m = bf16_rne(r1);
-  const float r2 = r1 - __uint_as_float(m << 16);
-  l = bf16_rne(r2);
+// Three-way split of two values into packed (hi, mid, lo) pairs.
+__device__ __forceinline__ void split2(float a, float b, unsigned& h, unsigned& m, unsigned& l) {
+  h = pk_bf16(a, b);
+  const float ra = a - __uint_as_float(h << 16), rb = b - __uint_as_float(h & 0xffff0000u);
+  m = pk_bf16(ra, rb);
+  const float sa = ra - __uint_as_float(m << 16), sb = rb - __uint_as_float(m & 0xffff0000u);
+  l = pk_bf16(sa, sb);
+}
+
+// The re and im parts of eight consecutive complex values as split fragments:
+// re[0..2] = (h, m, l) of the real parts, im[0..2] of the imaginary parts.
+__device__ __forceinline__ void split_frag(const float2 (&v)[8], u32x4 (&re)[3], u32x4 (&im)[3]) {
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    unsigned h, m, l;
+    split2(v[2 * w].x, v[2 * w + 1].x, h, m, l);
+    re[0][w] = h;
+    re[1][w] = m;
+    re[2][w] = l;
+    split2(v[2 * w].y, v[2 * w + 1].y, h, m, l);
+    im[0][w] = h;
+    im[1][w] = m;
+    im[2][w] = l;
+  }
 }
 
 // c += x y for split operands x = (h, m, l), y = (h, m, l): six part products,
@@ -60,14 +80,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void cg
     GemmParams<float> p) {
   using C2 = float2;
   constexpr int BK = 32;        // one 16x16x32 instruction per K step
-  constexpr int KP = BK + 8;    // LDS row: 32 BF16 padded to 80 bytes
   constexpr int WAVES_N = BN / WN;
   constexpr int TM = WM / 16, TN = WN / 16;
   static_assert((BM / WM) * (BN / WN) * 64 == NT, "one wave per WM x WN sub-tile");
   static_assert(BM * (BK / 8) == NT && BN * (BK / 8) == NT, "each thread moves eight k values of A and of B");
 
-  __shared__ __attribute__((aligned(16))) unsigned short As[6][BM][KP];
-  __shared__ __attribute__((aligned(16))) unsigned short Bs[6][BN][KP];
+  // k-major tiles, as in cgemm_kernel: a lane's eight k values of one row of A
+  // (column of B) sit one LDS row apart, and the 16 lanes that read one k hit
+  // consecutive addresses
+  __shared__ __attribute__((aligned(16))) C2 As[2][BK][BM + 1];
+  __shared__ __attribute__((aligned(16))) C2 Bs[2][BK][BN];
 
   TileJob<float> jb;
   if (!tile_job<float, BM, BN>(p, jb)) return;
@@ -90,84 +112,73 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void cg
   const int ar = tid / (BK / 8), ak = (tid % (BK / 8)) * 8;
   const int bc = tid % BN, bk = (tid / BN) * 8;
   const int lda = int(p.lda), ldb = int(p.ldb);
+  // The zero-select of out-of-range values waits for the store, so that no
+  // instruction before the MFMAs depends on the loads in flight.
   C2 ra[8], rb[8];
   auto load = [&](int k0) {
-    const int gr = jb.row0 + ar;
-    const int arow = min(gr, p.M - 1) * lda;
+    const int arow = min(jb.row0 + ar, p.M - 1) * lda;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ra[q] = jb.A[arow + max(0, min(k0 + ak + q, p.K - 1))];
+    const int bcol = min(jb.col0 + bc, p.N - 1);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int gk = k0 + ak + q;
-      const C2 v = jb.A[arow + max(0, min(gk, p.K - 1))];
-      ra[q] = (gr < p.M && gk < p.K) ? v : czero<C2>();
-    }
-    const int gc = jb.col0 + bc;
-    const int bcol = min(gc, p.N - 1);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int gk = k0 + bk + q;
-      const int off = max(0, min(gk, p.K - 1)) * ldb + bcol;
+      const int off = max(0, min(k0 + bk + q, p.K - 1)) * ldb + bcol;
       C2 v = jb.B[off];
       if constexpr (BCOMB) {
         const C2 x0 = jb.BX0[off], x1 = jb.BX1[off];
         v.x = p.bxc[0] * v.x + p.bxc[1] * x0.x + p.bxc[2] * x1.x;
         v.y = p.bxc[0] * v.y + p.bxc[1] * x0.y + p.bxc[2] * x1.y;
       }
-      rb[q] = (gk < p.K && gc < p.N) ? v : czero<C2>();
+      rb[q] = v;
     }
   };
-  // Split eight values into the six planes of one 16-byte LDS row segment.
-  static_assert(BM == BN, "square tiles (the LDS planes of A and B share one shape)");
-  auto split_store = [&](unsigned short (&S)[6][BM][KP], const C2 (&v)[8], int row, int k) {
-    u32x4 pk[6];
+  auto store = [&](int buf, int k0) {
+    const bool arow_in = jb.row0 + ar < p.M, bcol_in = jb.col0 + bc < p.N;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      unsigned h0, m0, l0, h1, m1, l1;
-      split3(v[2 * w].x, h0, m0, l0);
-      split3(v[2 * w + 1].x, h1, m1, l1);
-      pk[0][w] = h0 | (h1 << 16);
-      pk[1][w] = m0 | (m1 << 16);
-      pk[2][w] = l0 | (l1 << 16);
-      split3(v[2 * w].y, h0, m0, l0);
-      split3(v[2 * w + 1].y, h1, m1, l1);
-      pk[3][w] = h0 | (h1 << 16);
-      pk[4][w] = m0 | (m1 << 16);
-      pk[5][w] = l0 | (l1 << 16);
-    }
+    for (int q = 0; q < 8; ++q) As[buf][ak + q][ar] = (arow_in && k0 + ak + q < p.K) ? ra[q] : czero<C2>();
 #pragma unroll
-    for (int pl = 0; pl < 6; ++pl) *reinterpret_cast<u32x4*>(&S[pl][row][k]) = pk[pl];
-  };
-  auto store = [&]() {
-    split_store(As, ra, ar, ak);
-    split_store(Bs, rb, bc, bk);
+    for (int q = 0; q < 8; ++q) Bs[buf][bk + q][bc] = (bcol_in && k0 + bk + q < p.K) ? rb[q] : czero<C2>();
   };
 
   const int nk = (p.K + BK - 1) / BK;
   if (nk > 0) {   // K = 0 (C = beta C + terms) reads no operand
     load(0);
-    store();
+    store(0, 0);
   }
   __syncthreads();
   const int fr = lane & 15, fk = 8 * (lane >> 4);
   for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
     if (kt + 1 < nk) load((kt + 1) * BK);
     if (!idle) {
       u32x4 bre[TN][3], bim[TN][3];
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
+      for (int j = 0; j < TN; ++j) {
+        C2 v[8];
 #pragma unroll
-        for (int pl = 0; pl < 3; ++pl) {
-          bre[j][pl] = *reinterpret_cast<const u32x4*>(&Bs[pl][wn + j * 16 + fr][fk]);
-          bim[j][pl] = *reinterpret_cast<const u32x4*>(&Bs[3 + pl][wn + j * 16 + fr][fk]);
-        }
+        for (int q = 0; q < 8; ++q) v[q] = Bs[cur][fk + q][wn + j * 16 + fr];
+        split_frag(v, bre[j], bim[j]);
+      }
+      // A fragments in a software pipeline: while the MFMAs of block i run, the
+      // fragment of block i + 1 is read and split on the vector ALU, the two
+      // streams interleaved instruction by instruction
+      u32x4 are[3], aim[3];
+      {
+        C2 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = As[cur][fk + q][wm + fr];
+        split_frag(v, are, aim);
+      }
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        u32x4 are[3], aim[3], naim[3];
+        C2 vn[8];
+        if (i + 1 < TM) {
 #pragma unroll
-        for (int pl = 0; pl < 3; ++pl) {
-          are[pl] = *reinterpret_cast<const u32x4*>(&As[pl][wm + i * 16 + fr][fk]);
-          aim[pl] = *reinterpret_cast<const u32x4*>(&As[3 + pl][wm + i * 16 + fr][fk]);
-          naim[pl] = aim[pl] ^ 0x80008000u;   // -Ai: flip the BF16 sign bits
+          for (int q = 0; q < 8; ++q) vn[q] = As[cur][fk + q][wm + (i + 1) * 16 + fr];
         }
+        u32x4 naim[3];
+#pragma unroll
+        for (int pl = 0; pl < 3; ++pl) naim[pl] = aim[pl] ^ 0x80008000u;   // -Ai: flip the BF16 sign bits
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
           // Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br
@@ -176,13 +187,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void cg
           acci[i][j] = prod3(are, bim[j], acci[i][j]);
           acci[i][j] = prod3(aim, bre[j], acci[i][j]);
         }
+        if (i + 1 < TM) {
+          split_frag(vn, are, aim);
+          // 24 TN MFMAs against about 90 VALU of the split: one MFMA, then two VALU
+#pragma unroll
+          for (int g = 0; g < 24 * TN; ++g) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+          }
+        }
       }
     }
-    __syncthreads();   // every wave is done with this K step's planes
-    if (kt + 1 < nk) {
-      store();
-      __syncthreads();
-    }
+    if (kt + 1 < nk) store(cur ^ 1, (kt + 1) * BK);
+    __syncthreads();
   }
 
   tile_epilogue<float, TM, TN>(p, jb, accr, acci, wm, wn, lane);

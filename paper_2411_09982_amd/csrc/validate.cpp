@@ -133,6 +133,25 @@ Check check_propagate_batched(const void* U, int64_t B, int64_t M, int64_t d, in
   return Check::ok();
 }
 
+size_t action_ws_bytes(int64_t M, int64_t d) {
+  if (M < 0 || d < 1) return 0;
+  // two term vectors, the per-interval shift and the two norms per interval
+  return 2 * align256(size_t(d) * 16) + align256(size_t(M) * 16) + align256(size_t(M) * 16);
+}
+
+Check check_action(const void* omega, int64_t M, int64_t d, int dtype, const void* x, double tol, const void* ws,
+                   size_t ws_bytes) {
+  if (M < 0) return Check::fail(QCHEFF_EINVAL, "M must be >= 0");
+  if (M > 0x7fffffff) return Check::fail(QCHEFF_EINVAL, "M too large");
+  if (d < 1 || d > kMaxDim) return Check::fail(QCHEFF_EINVAL, "d must be in [1, 16384]");
+  if (elem_bytes(dtype) == 0) return Check::fail(QCHEFF_EINVAL, "unknown dtype");
+  if (!x) return Check::fail(QCHEFF_EINVAL, "x must not be NULL");
+  if (M > 0 && !omega) return Check::fail(QCHEFF_EINVAL, "omega must not be NULL");
+  if (!(tol >= 0.0) || tol >= 1.0) return Check::fail(QCHEFF_EINVAL, "tol must be in [0, 1)");
+  if (!ws || ws_bytes < action_ws_bytes(M, d)) return Check::fail(QCHEFF_EWORKSPACE, "workspace too small");
+  return Check::ok();
+}
+
 size_t workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int order, int dtype) {
   if (d < 1 || d > kMaxDim) return 0;
   switch (fn) {
@@ -143,6 +162,8 @@ size_t workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int order, i
       return expm_ws_bytes(batch, d, dtype == QCHEFF_C64_BF16X3 ? QCHEFF_C64 : dtype);
     case QCHEFF_FN_PROPAGATE:
       return propagate_ws_bytes(batch, d, dtype, order);
+    case QCHEFF_FN_ACTION:
+      return elem_bytes(dtype) ? action_ws_bytes(batch, d) : 0;
     default:
       return 0;
   }

@@ -37,6 +37,8 @@ Check check_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, 
                       const void* traj, const void* ws, size_t ws_bytes);
 
 Check check_propagate_batched(const void* U, int64_t B, int64_t M, int64_t d, int dtype, const void* x);
+Check check_action(const void* omega, int64_t M, int64_t d, int dtype, const void* x, double tol, const void* ws,
+                   size_t ws_bytes);
 
 // Workspace layouts.  Each region starts on a 256-byte boundary.
 size_t align256(size_t n);
@@ -47,6 +49,7 @@ size_t expm_header_bytes(int64_t batch);
 size_t expm_ws_bytes(int64_t batch, int64_t d, int dtype);
 int64_t expm_chunk(size_t ws_bytes, int64_t batch, int64_t d, int dtype);  // items per chunk, 0 if none fit
 size_t propagate_ws_bytes(int64_t M, int64_t d, int dtype, int mode);
+size_t action_ws_bytes(int64_t M, int64_t d);
 size_t workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int order, int dtype);
 
 }  // namespace qcheff

@@ -15,7 +15,8 @@ def test_exports_every_header_symbol():
     names = q.header_symbols()
     assert set(names) == {"qcheff_magnus_coeffs", "qcheff_magnus_generators", "qcheff_expm_batched",
                           "qcheff_propagate", "qcheff_workspace_bytes", "qcheff_last_error",
-                          "qcheff_timing_enable", "qcheff_timing_read", "qcheff_propagate_batched"}
+                          "qcheff_timing_enable", "qcheff_timing_read", "qcheff_propagate_batched",
+                          "qcheff_propagate_action"}
     L = q.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -107,6 +108,29 @@ def test_propagate_validation():
     # product tree: ceil(M/2) + ceil(M/4) matrices of 256-byte-rounded size
     assert q.workspace_bytes(q.FN_PROPAGATE, 5, 4, 1, q.PRODUCT, q.C64) == (3 + 2) * 256
     assert q.workspace_bytes(9, 5, 4, 1, 1, q.C64) == 0
+
+
+def test_propagate_action_validation():
+    L = q.lib()
+    a = L.qcheff_propagate_action
+    need = q.workspace_bytes(q.FN_ACTION, 3, 10, 1, 1, q.C64)
+    # two term vectors, the shifts and the norms, each on a 256-byte boundary
+    assert need == 2 * 256 + 256 + 256
+    assert q.workspace_bytes(q.FN_ACTION, 1000, 4096, 1, 1, q.C128) == 2 * 65536 + 2 * 16128
+    assert q.workspace_bytes(q.FN_ACTION, 3, 10, 1, 1, 9) == 0
+    assert a(FAKE, -1, 10, q.C64, FAKE, None, 0.0, FAKE, need, None) == q.EINVAL
+    assert a(FAKE, 3, 0, q.C64, FAKE, None, 0.0, FAKE, need, None) == q.EINVAL
+    assert a(FAKE, 3, 10, 9, FAKE, None, 0.0, FAKE, need, None) == q.EINVAL
+    assert a(FAKE, 3, 10, q.C64, None, None, 0.0, FAKE, need, None) == q.EINVAL
+    assert a(None, 3, 10, q.C64, FAKE, None, 0.0, FAKE, need, None) == q.EINVAL
+    assert a(FAKE, 3, 10, q.C64, FAKE, None, -1e-3, FAKE, need, None) == q.EINVAL
+    assert a(FAKE, 3, 10, q.C64, FAKE, None, float("nan"), FAKE, need, None) == q.EINVAL
+    assert a(FAKE, 3, 10, q.C64, FAKE, None, 1.0, FAKE, need, None) == q.EINVAL
+    assert a(FAKE, 3, 10, q.C64, FAKE, None, 0.0, FAKE, need - 1, None) == q.EWORKSPACE
+    assert a(FAKE, 3, 10, q.C64, FAKE, None, 0.0, None, 0, None) == q.EWORKSPACE
+    # M = 0 without a trajectory enqueues nothing
+    need0 = q.workspace_bytes(q.FN_ACTION, 0, 10, 1, 1, q.C64)
+    assert a(None, 0, 10, q.C64, FAKE, None, 0.0, FAKE, need0, None) == q.OK
 
 
 def test_propagate_batched_validation():

@@ -1,0 +1,82 @@
+"""State-only propagation by the truncated Taylor action (qcheff_propagate_action)
+against the oracle's exp(Omega) psi (eigendecomposition), and against the
+propagator path of the same job."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+from tests.test_gpu_parity import gpu, host, say
+
+pytestmark = pytest.mark.gpu
+
+q = pytest.importorskip("paper_2411_09982_amd")
+DEV = "cuda:0"
+
+
+def _oracle_chain(Om, psi0):
+    U = oracle.expm_skew_hermitian(Om) if len(Om) else np.zeros((0,) + Om.shape[1:], complex)
+    return oracle.propagate_state(U, psi0, trajectory=True)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("d", [1, 3, 17, 64, 130, 300])
+def test_action_parity(d, dtype):
+    # norms from 0 (a pure phase after the shift) to one needing many steps; one
+    # generator with a large mean diagonal (the shift takes it out)
+    say(f"action d={d} {dtype}")
+    norms = [0.0, 0.3, 5.0, 60.0, 400.0]
+    Om = wl.random_skew_hermitian_batch(len(norms), d, norms, config_id=600 + d)
+    Om[2] += -1j * 37.0 * np.eye(d)
+    seen = Om.astype(np.complex64).astype(np.complex128) if dtype == torch.complex64 else Om
+    psi0 = wl.random_state(d, 11)
+    ref, traj_ref = _oracle_chain(seen, psi0)
+    x = gpu(psi0)
+    traj = torch.empty((len(norms) + 1, d), dtype=torch.complex128, device=DEV)
+    q.propagate_action(gpu(Om).to(dtype), x, traj=traj)
+    torch.cuda.synchronize()
+    # FP64 arithmetic throughout; the truncation tolerance is the storage's roundoff
+    tol = 1e-12 if dtype == torch.complex128 else 4 * len(norms) * 2.0 ** -24
+    assert np.abs(host(x) - ref).max() <= tol
+    assert np.abs(host(traj) - traj_ref).max() <= tol
+    assert abs(float(oracle.state_infidelity(ref, host(x)))) <= (1e-13 if dtype == torch.complex128 else 1e-10)
+
+
+def test_action_edge_cases():
+    d = 20
+    psi0 = wl.random_state(d, 3)
+    # M = 0: the state is unchanged and traj holds psi_0
+    x = gpu(psi0)
+    traj = torch.empty((1, d), dtype=torch.complex128, device=DEV)
+    q.propagate_action(torch.empty((0, d, d), dtype=torch.complex128, device=DEV), x, traj=traj)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(x), psi0) and np.array_equal(host(traj)[0], psi0)
+    # a non-finite generator makes the state NaN
+    Om = wl.random_skew_hermitian_batch(2, d, 3.0, config_id=5)
+    Om[1, 2, 3] = np.nan
+    x = gpu(psi0)
+    q.propagate_action(gpu(Om), x)
+    torch.cuda.synchronize()
+    assert np.isnan(host(x)).all()
+    # a norm that would need more than 2^24 products per interval is refused
+    big = wl.random_skew_hermitian_batch(1, d, 1e9, config_id=6)
+    with pytest.raises(q.QcheffError):
+        q.propagate_action(gpu(big), gpu(psi0))
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_evolve_state_matches_propagator_path(dtype):
+    w = wl.random_system(48, 3, 40 * 15, 40, 2, config_id=88, drift_scale=30.0, drive_scale=5.0)
+    say(f"evolve_state vs evolve, d=48 order 2 {dtype}")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    full = q.evolve(t(w.H0), t(w.Hk), t(w.u), w.dt_sample, w.M, 2, psi0=t(w.psi0), dtype=dtype, chunk=16)
+    act = q.evolve_state(t(w.H0), t(w.Hk), t(w.u), w.dt_sample, w.M, 2, t(w.psi0), dtype=dtype, chunk=7)
+    torch.cuda.synchronize()
+    ref = oracle.run(w.H0, w.Hk, w.u, w.dt_sample, w.M, 2, psi0=w.psi0)["psi"]
+    a, f = host(act), host(full["psi"])
+    if dtype == torch.complex128:
+        assert np.abs(a - ref).max() <= 1e-11 and np.abs(a - f).max() <= 1e-11
+    else:
+        assert abs(float(oracle.state_infidelity(ref, a))) <= 1e-6
+        assert oracle.norm_error(a) <= w.M * 2.0 ** -24 * 8
