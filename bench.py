@@ -256,7 +256,9 @@ def cpu_baseline(w, n_int):
 
 def serve(a):
     """Latency under Poisson arrivals: d ~ U{64..dmax}, M ~ U{64..mmax}, order 1 or 2,
-    FP32 or FP64 per request, admitted by an HBM budget of 200 GB, up to 8 in flight."""
+    FP32 or FP64 per request, admitted by an HBM budget of 200 GB, up to 8 in flight;
+    each request takes the path the server picks for it (propagators or the Taylor
+    action on the state)."""
     import torch
     import workloads as wl
     from paper_2411_09982_amd.serve import Request, Server, latency_percentiles, max_overlap, poisson_requests
@@ -277,12 +279,15 @@ def serve(a):
         wall = time.perf_counter() - t0
         lat = latency_percentiles(res)
         props = sum(r.M for r in reqs)
+        paths = {}
+        for r in res.values():
+            paths[r.path] = paths.get(r.path, 0) + 1
         print(json.dumps(dict(metric="serving latency (Magnus propagation requests)", rate_req_s=rate,
                               requests=len(reqs), p50_ms=round(lat["p50_ms"], 1), p99_ms=round(lat["p99_ms"], 1),
                               wait_p50_ms=round(lat["wait_p50_ms"], 1), wait_p99_ms=round(lat["wait_p99_ms"], 1),
                               service_p50_ms=round(lat["service_p50_ms"], 1),
                               service_p99_ms=round(lat["service_p99_ms"], 1),
-                              interval_propagators_s=round(props / wall, 1),
+                              intervals_s=round(props / wall, 1), paths=paths,
                               wall_s=round(wall, 2), completed_req_s=round(len(reqs) / wall, 2),
                               max_in_flight=max_overlap(res), d_range=[64, a.serve_dmax],
                               M_range=[64, a.serve_mmax], data="synthetic")), flush=True)

@@ -179,11 +179,25 @@ def norm1(A):
     return float(np.abs(np.asarray(A)).sum(axis=-2).max())
 
 
-def scaling_exponent(Omega, theta=THETA13_F64):
-    """Number of squarings s of the [13/13] scaling-and-squaring method (Higham 2005):
-    the smallest s >= 0 with ||Omega||_1 / 2^s <= theta_13 (that is,
-    max(0, ceil(log2(||Omega||_1 / theta_13)))), decided by exact float64
+def trace_shift(Omega):
+    """mu = tr(Omega) / d, the multiple of I that scaling and squaring splits off:
+    exp(Omega) = e^mu exp(Omega - mu I), because mu I commutes with Omega."""
+    Omega = np.asarray(Omega, dtype=np.complex128)
+    return complex(np.trace(Omega)) / Omega.shape[-1]
+
+
+def scaling_exponent(Omega, theta=THETA13_F64, shift=True):
+    """Number of squarings s of the [13/13] scaling-and-squaring method (Higham 2005)
+    applied to Omega - mu I (trace reduction, mu = trace_shift(Omega); shift=False
+    takes Omega itself): the smallest s >= 0 with ||Omega - mu I||_1 / 2^s <= theta_13
+    (that is, max(0, ceil(log2(||.||_1 / theta_13)))), decided by exact float64
     comparisons against theta_13 * 2^s; -1 for a non-finite norm."""
+    Omega = np.asarray(Omega, dtype=np.complex128)
+    if shift:
+        mu = trace_shift(Omega)
+        if not (math.isfinite(mu.real) and math.isfinite(mu.imag)):
+            return -1
+        Omega = Omega - mu * np.eye(Omega.shape[-1])
     nrm = norm1(Omega)
     if not math.isfinite(nrm):
         return -1

@@ -275,6 +275,7 @@ template <typename T> struct ExpmWs {
   unsigned long long* norms;
   int* s_ws;
   int* smax;
+  double2* mu;   // trace shifts
   C2* X[6];
   double2* aug;
   int* piv;
@@ -286,10 +287,11 @@ template <typename T> bool carve_expm(void* ws, size_t bytes, int64_t chunk, int
   w.norms = cv.take<unsigned long long>(size_t(chunk) * 8);
   w.s_ws = cv.take<int>(size_t(chunk) * 4);
   w.smax = cv.take<int>(256);
+  w.mu = cv.take<double2>(size_t(chunk) * 16);
   for (int i = 0; i < 6; ++i) w.X[i] = cv.take<typename Cx<T>::t>(size_t(chunk) * dd * sizeof(typename Cx<T>::t));
   w.aug = cv.take<double2>(size_t(chunk) * 2 * dd * 16);
   w.piv = cv.take<int>(size_t(chunk) * size_t(d) * 4);
-  bool ok = w.norms && w.s_ws && w.smax && w.aug && w.piv;
+  bool ok = w.norms && w.s_ws && w.smax && w.mu && w.aug && w.piv;
   for (int i = 0; i < 6; ++i) ok = ok && w.X[i];
   return ok;
 }
@@ -438,12 +440,23 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
                      reinterpret_cast<uint32_t*>(w.norms), nb * 2, 0u);
   hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(w.smax), int64_t(1), 0u);
   QC_HIP(hipGetLastError());
-  hipLaunchKernelGGL(norm1_kernel<C2>, dim3(nblocks(d, 256), unsigned(nb)), dim3(256), 0, st, omega, int(d),
+  // Trace reduction in FP64 only: exp(Omega) = e^mu exp(Omega - mu I), mu = tr(Omega) / d.
+  // It centres the spectrum, which for a drift-dominated generator halves the
+  // norm (one squaring less) but moves the low-energy end, where such a system's
+  // states live, from the middle of the scaled spectrum (where the Pade
+  // approximant is most accurate) to its edge; in FP32 that costs more accuracy
+  // in those states than the saved squaring wins.
+  const double2* mu = nullptr;
+  if (sizeof(T) == 8) {
+    hipLaunchKernelGGL(trace_mean_kernel<C2>, dim3(unsigned(nb)), dim3(256), 0, st, omega, int(d), w.mu);
+    mu = w.mu;
+  }
+  hipLaunchKernelGGL(norm1_kernel<C2>, dim3(nblocks(d, 256), unsigned(nb)), dim3(256), 0, st, omega, int(d), mu,
                      w.norms);
   QC_HIP(hipGetLastError());
   const unsigned sblocks = unsigned(std::min<int64_t>(nblocks(dd, 256), 1024));
-  hipLaunchKernelGGL(scale_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, omega, w.X[0], dd, w.norms,
-                     kTheta13, bound, w.s_ws, s_out, w.smax);
+  hipLaunchKernelGGL(scale_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, omega, w.X[0], int(d), mu,
+                     w.norms, kTheta13, bound, w.s_ws, s_out, w.smax);
   QC_HIP(hipGetLastError());
   C2 *A = w.X[0], *A2 = w.X[1], *A4 = w.X[2], *A6 = w.X[3], *W = w.X[4], *V = w.X[5];
   int r, cfg = 2;   // the split-BF16 tile, or the tuned FP32 / FP64 one
@@ -494,6 +507,10 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
     p.sA = dd; p.sB = dd; p.sC = dd;
     p.sq = 1; p.sq_s = w.s_ws; p.sq_step = step; p.sq_p0 = U; p.sq_p1 = A;
     QC_HIP((launch_cgemm<T>(p, st, active)));
+  }
+  if (mu) {
+    hipLaunchKernelGGL(phase_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, U, dd, mu);
+    QC_HIP(hipGetLastError());
   }
   return QCHEFF_OK;
 }

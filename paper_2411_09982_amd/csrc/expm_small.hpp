@@ -1,7 +1,8 @@
 // Fused [13/13] Pade scaling and squaring for small matrices (d <= 32).
 //
 // One workgroup of four waves takes one item at a time (grid-stride loop over
-// the batch) and keeps everything in LDS: the FP64 norm and scaling exponent,
+// the batch) and keeps everything in LDS: the trace reduction, the FP64 norm
+// and scaling exponent,
 // the six Pade products on 16x16x4 MFMA (one 16x16 output block per wave), the
 // FP64 elimination of the augmented system [V - U | V + U] with partial
 // pivoting and its back substitution, and the squarings.  Matrices are stored
@@ -27,6 +28,7 @@ template <typename T> struct SmallLds {
     } s;
   } u;
   double colsum[kSmallD];
+  double2 mu;   // trace shift
   int piv;
   int sq;
 };
@@ -110,6 +112,24 @@ __global__ __launch_bounds__(256) void expm_small_kernel(const typename Cx<T>::t
     for (int e = tid; e < kSmallD * kSmallD; e += 256) {
       const int i = e / kSmallD, j = e % kSmallD;
       Mx[0][i][j] = (i < d && j < d) ? src[i * d + j] : czero<C2>();
+    }
+    __syncthreads();
+    // trace reduction, in FP64 only (as in the batched path): exp(Omega) =
+    // e^mu exp(Omega - mu I), mu = tr(Omega) / d
+    constexpr bool kShift = sizeof(T) == 8;
+    if (tid == 0) {
+      double re = 0.0, im = 0.0;
+      for (int i = 0; i < d; ++i) {
+        re += double(Mx[0][i][i].x);
+        im += double(Mx[0][i][i].y);
+      }
+      L.mu = kShift ? make_double2(re / d, im / d) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const double2 mu = L.mu;
+    if (tid < d) {
+      Mx[0][tid][tid].x = T(double(Mx[0][tid][tid].x) - mu.x);
+      Mx[0][tid][tid].y = T(double(Mx[0][tid][tid].y) - mu.y);
     }
     __syncthreads();
     // 1-norm in FP64 and the scaling exponent
@@ -257,7 +277,14 @@ __global__ __launch_bounds__(256) void expm_small_kernel(const typename Cx<T>::t
       cur = nxt;
     }
     C2* dst = U + item * dd;
-    for (int e = tid; e < d * d; e += 256) dst[e] = Mx[cur][e / d][e % d];
+    const double er = exp(mu.x), pr = er * cos(mu.y), pi = er * sin(mu.y);
+    for (int e = tid; e < d * d; e += 256) {
+      const C2 v = Mx[cur][e / d][e % d];
+      C2 o;
+      o.x = T(pr * double(v.x) - pi * double(v.y));
+      o.y = T(pr * double(v.y) + pi * double(v.x));
+      dst[e] = o;
+    }
     __syncthreads();
   }
 }

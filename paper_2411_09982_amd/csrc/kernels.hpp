@@ -152,16 +152,22 @@ __global__ __launch_bounds__(256) void generators_kernel(const double2* __restri
 // Column sums of |Omega| in FP64 (one thread per column), maximum per item
 // by an atomic max on the IEEE bit pattern (monotone for non-negative values).
 template <typename C2>
-__global__ __launch_bounds__(256) void norm1_kernel(const C2* __restrict__ X, int d,
+__global__ __launch_bounds__(256) void norm1_kernel(const C2* __restrict__ X, int d, const double2* __restrict__ mu,
                                                     unsigned long long* __restrict__ norms) {
   const int b = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const double2 m = mu ? mu[b] : make_double2(0.0, 0.0);   // the norm is of X - mu I
   double sum = 0.0;
   if (j < d) {
     const C2* col = X + int64_t(b) * d * d + j;
     for (int i = 0; i < d; ++i) {
       const C2 v = col[int64_t(i) * d];
-      sum += sqrt(double(v.x) * double(v.x) + double(v.y) * double(v.y));
+      double x = double(v.x), y = double(v.y);
+      if (i == j) {
+        x -= m.x;
+        y -= m.y;
+      }
+      sum += sqrt(x * x + y * y);
     }
   }
   __shared__ double red[256];
@@ -186,15 +192,20 @@ __device__ __forceinline__ int squarings_for(double nrm, double theta) {
   return s;
 }
 
-// A = Omega / 2^s per item (exact); records s.  With bound >= 0 an item whose s
-// exceeds it is recorded as -2 and scaled by NaN (its result is all NaN).
+// A = (Omega - mu I) / 2^s per item (the shift in FP64, the scaling exact);
+// records s.  With bound >= 0 an item whose s exceeds it is recorded as -2 and
+// scaled by NaN (its result is all NaN).  mu may be null (no shift).
 template <typename C2>
-__global__ __launch_bounds__(256) void scale_kernel(const C2* __restrict__ omega, C2* __restrict__ A,
-                                                    int64_t dd, const unsigned long long* __restrict__ norms,
-                                                    double theta, int bound, int* __restrict__ s_ws,
-                                                    int* __restrict__ s_out, int* __restrict__ smax) {
+__global__ __launch_bounds__(256) void scale_kernel(const C2* __restrict__ omega, C2* __restrict__ A, int d,
+                                                    const double2* __restrict__ mu,
+                                                    const unsigned long long* __restrict__ norms, double theta,
+                                                    int bound, int* __restrict__ s_ws, int* __restrict__ s_out,
+                                                    int* __restrict__ smax) {
+  using T = decltype(C2().x);
   const int b = blockIdx.y;
+  const int64_t dd = int64_t(d) * d;
   const double nrm = __longlong_as_double((long long)norms[b]);
+  const double2 m = mu ? mu[b] : make_double2(0.0, 0.0);
   int s = squarings_for(nrm, theta);
   if (bound >= 0 && s > bound) s = -2;   // needs more squarings than enqueued: NaN result
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -206,9 +217,30 @@ __global__ __launch_bounds__(256) void scale_kernel(const C2* __restrict__ omega
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < dd; e += int64_t(gridDim.x) * blockDim.x) {
     const C2 v = omega[b * dd + e];
     C2 o;
-    o.x = v.x * f;
-    o.y = v.y * f;
+    if (e % (d + 1) == 0) {   // diagonal
+      o.x = T((double(v.x) - m.x) * f);
+      o.y = T((double(v.y) - m.y) * f);
+    } else {
+      o.x = v.x * T(f);
+      o.y = v.y * T(f);
+    }
     A[b * dd + e] = o;
+  }
+}
+
+// U_b <- e^{mu_b} U_b: the factor the trace reduction split off.
+template <typename C2>
+__global__ __launch_bounds__(256) void phase_kernel(C2* __restrict__ U, int64_t dd, const double2* __restrict__ mu) {
+  using T = decltype(C2().x);
+  const int b = blockIdx.y;
+  const double2 m = mu[b];
+  const double er = exp(m.x), pr = er * cos(m.y), pi = er * sin(m.y);
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < dd; e += int64_t(gridDim.x) * blockDim.x) {
+    const C2 v = U[b * dd + e];
+    C2 o;
+    o.x = T(pr * double(v.x) - pi * double(v.y));
+    o.y = T(pr * double(v.y) + pi * double(v.x));
+    U[b * dd + e] = o;
   }
 }
 

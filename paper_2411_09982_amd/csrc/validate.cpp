@@ -67,7 +67,8 @@ size_t expm_item_bytes(int64_t d, int dtype) {
 }
 
 size_t expm_header_bytes(int64_t batch) {
-  return align256(size_t(batch) * 8) + align256(size_t(batch) * 4) + 256;
+  // norms, squaring counts, their maximum, trace shifts
+  return align256(size_t(batch) * 8) + align256(size_t(batch) * 4) + 256 + align256(size_t(batch) * 16);
 }
 
 size_t expm_ws_bytes(int64_t batch, int64_t d, int dtype) {

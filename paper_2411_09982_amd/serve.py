@@ -3,10 +3,18 @@
 Requests (H0, H_k, u, dt, M, order, precision, psi0) arrive over time.  A
 request is admitted as soon as a slot is free and its device memory fits in the
 HBM budget next to the jobs already running; each admitted job runs the whole
-path (coefficients, generators, exponentials, state chain) on a stream of its
-own, so the kernels of different jobs overlap on the device; its state stays
-device-resident until it completes.  Admission is first-come first-served; a job
-that does not fit waits (it never overtakes an earlier one).
+path on a stream of its own, so the kernels of different jobs overlap on the
+device; its state stays device-resident until it completes.  Admission is
+first-come first-served; a job that does not fit waits (it never overtakes an
+earlier one).
+
+A request asks for the final state only, so it is served by one of two paths:
+"propagators" (coefficients, generators, exponentials, state chain) or "action"
+(coefficients, then per chunk of intervals the generators and the truncated
+Taylor action on the state, never forming a propagator).  "auto" takes the
+propagators for d <= 32, where the fused one-workgroup exponential is cheapest,
+and the action above that, where it replaces O(d^3) products per interval by a
+few O(d^2) ones.
 
 The admission and accounting logic (`Admission`) is plain host code and is
 tested without a GPU; `Server` drives it with worker threads and HIP streams.
@@ -34,6 +42,7 @@ class Request:
     precision: str            # "c64" or "c128"
     psi0: np.ndarray          # complex128 [d]
     arrival: float = 0.0      # seconds, relative to the start of the stream
+    path: str = "auto"        # "auto", "propagators" or "action"
 
     @property
     def d(self) -> int:
@@ -48,24 +57,34 @@ class Request:
 class Result:
     rid: int
     psi: np.ndarray
-    s_max: int
+    s_max: int                # largest squaring count (propagator path), -1 for the action
     arrival: float
     admitted: float
     done: float
+    path: str = "propagators"
 
     @property
     def latency(self) -> float:
         return self.done - self.arrival
 
 
-def job_bytes(d: int, K: int, M: int, order: int, precision: str, chunk: int, ws_fn=None) -> int:
-    """Device bytes one job holds while it runs: inputs, Omega/U, workspaces, state."""
+def job_bytes(d: int, K: int, M: int, order: int, precision: str, chunk: int, ws_fn=None,
+              path: str = "propagators") -> int:
+    """Device bytes one job holds while it runs: inputs, Omega/U (all M intervals
+    for the propagators, one chunk for the action), workspaces, state."""
     eb = 8 if precision == "c64" else 16
     inputs = (1 + K) * d * d * 16
-    omega = M * d * d * eb
+    omega = (M if path == "propagators" else min(chunk, M)) * d * d * eb
     coeffs = M * (2 * K + K * (K - 1) // 2) * 8
     ws = ws_fn(d, K, M, order, precision, chunk) if ws_fn else 0
     return inputs + omega + coeffs + ws + 4 * d * 16
+
+
+def path_for(r: "Request") -> str:
+    """The path a request runs ("auto" resolved by its dimension)."""
+    if r.path != "auto":
+        return r.path
+    return "propagators" if r.d <= 32 else "action"
 
 
 class Admission:
@@ -118,15 +137,19 @@ class Server:
         self.errors: dict[int, BaseException] = {}
         self.t0 = 0.0
 
-    def _ws_bytes(self, d, K, M, order, precision, chunk):
+    def _ws_bytes(self, d, K, M, order, precision, chunk, path="propagators"):
         q = self.q
         code = q.C64 if precision == "c64" else q.C128
-        return (q.workspace_bytes(q.FN_GENERATORS, 1, d, K, order, q.C128)
-                + q.workspace_bytes(q.FN_EXPM, min(chunk, M), d, 1, 1, code)
+        gen = q.workspace_bytes(q.FN_GENERATORS, 1, d, K, order, q.C128)
+        if path == "action":
+            return gen + q.workspace_bytes(q.FN_ACTION, min(chunk, M), d, 1, 1, code)
+        return (gen + q.workspace_bytes(q.FN_EXPM, min(chunk, M), d, 1, 1, code)
                 + q.workspace_bytes(q.FN_PROPAGATE, M, d, 1, q.STATE, code))
 
     def bytes_for(self, r: Request) -> int:
-        return job_bytes(r.d, r.K, r.M, r.order, r.precision, self.chunk, self._ws_bytes)
+        path = path_for(r)
+        return job_bytes(r.d, r.K, r.M, r.order, r.precision, self.chunk,
+                         lambda *a: self._ws_bytes(*a, path=path), path=path)
 
     def _run_job(self, r: Request, sidx: int, admitted: float) -> None:
         torch, q = self.torch, self.q
@@ -139,17 +162,23 @@ class Server:
                 Hk = torch.from_numpy(r.Hk).to(dev)
                 u = torch.from_numpy(np.ascontiguousarray(r.u)).to(dev)
                 psi = torch.from_numpy(r.psi0).to(dev)
-                c1, c2 = q.magnus_coeffs(u, r.dt_sample, r.M, r.order, stream=st)
-                N = r.u.shape[1]
-                omega, _ = q.magnus_generators(H0, Hk, c1, c2, r.dt_sample * (N // r.M), r.order, dtype,
-                                               stream=st)
-                U, s = q.expm_batched(omega, U=omega, chunk=self.chunk, stream=st, skew_hermitian=True)
-                q.propagate(U, q.STATE, psi, stream=st)
+                path = path_for(r)
+                if path == "action":
+                    psi = q.evolve_state(H0, Hk, u, r.dt_sample, r.M, r.order, psi, dtype=dtype, chunk=self.chunk,
+                                         stream=st)
+                    s_max = -1
+                else:
+                    c1, c2 = q.magnus_coeffs(u, r.dt_sample, r.M, r.order, stream=st)
+                    N = r.u.shape[1]
+                    omega, _ = q.magnus_generators(H0, Hk, c1, c2, r.dt_sample * (N // r.M), r.order, dtype,
+                                                   stream=st)
+                    U, s = q.expm_batched(omega, U=omega, chunk=self.chunk, stream=st, skew_hermitian=True)
+                    q.propagate(U, q.STATE, psi, stream=st)
+                    s_max = int(s.max().cpu())
                 psi_h = psi.cpu().numpy()
-                s_max = int(s.max().cpu())
                 st.synchronize()
             done = time.perf_counter() - self.t0
-            res = Result(r.rid, psi_h, s_max, r.arrival, admitted, done)
+            res = Result(r.rid, psi_h, s_max, r.arrival, admitted, done, path)
             with self.lock:
                 self.results[r.rid] = res
         except BaseException as e:  # noqa: BLE001 - reported to the caller

@@ -26,7 +26,7 @@ def test_expm_bf16x3_parity(d, skew):
     Om = wl.random_skew_hermitian_batch(len(norms), d, norms, config_id=700 + d)
     ref = oracle.expm_skew_hermitian(Om)
     seen = Om.astype(np.complex64).astype(np.complex128)
-    s_ref = [oracle.scaling_exponent(x) for x in seen]
+    s_ref = [oracle.scaling_exponent(x, shift=False) for x in seen]   # FP32 path: no trace reduction
     om = gpu(Om).to(torch.complex64)
     U, s = q.expm_batched(om, skew_hermitian=skew, bf16x3=True)
     U32, _ = q.expm_batched(om, skew_hermitian=skew)

@@ -50,7 +50,8 @@ def test_transmon_resonator_d1000_full_size(job_and_ref, dt_name):
         assert inf <= inf_tol(job.dtype, s[n])
         if dt_name == "c128":
             assert np.abs(Ug - Uo[j]).max() <= 1e-10
-        assert s[n] == oracle.scaling_exponent(-1j * Hb[j])
+        # the FP64 path applies the trace reduction, the FP32 path does not
+        assert s[n] == oracle.scaling_exponent(-1j * Hb[j], shift=(dt_name == "c128"))
     # generators of the sampled intervals, formed again into a scratch buffer
     idx = torch.tensor(SAMPLED, device="cuda:0")
     om, _ = job.q.magnus_generators(job.H0, job.Hk, job.c1[idx].contiguous(), job.c2[idx].contiguous(),

@@ -31,6 +31,8 @@ MUTANTS = {
     "infidelity_unnormalised": ("/ (na * nb)", "/ 1.0"),
     "infidelity_no_square": ("abs(np.vdot(a, b)) ** 2", "abs(np.vdot(a, b))"),
     "prop_infidelity_norm_one_side": ("np.abs(tr) ** 2 / (na * nb)", "np.abs(tr) ** 2 / (na * na)"),
+    "shift_sign": ("Omega = Omega - mu * np.eye", "Omega = Omega + mu * np.eye"),
+    "shift_not_mean": ("complex(np.trace(Omega)) / Omega.shape[-1]", "complex(np.trace(Omega))"),
 }
 
 

@@ -216,13 +216,27 @@ def test_scaling_exponent_definition():
     g = np.random.default_rng(5)
     for target in [0.1, th, th * 1.0000001, 2 * th, 3 * th, 100.0, 1234.5]:
         Om = wl.random_skew_hermitian_batch(1, 9, target, config_id=int(target * 1000) % 97)[0]
-        s = oracle.scaling_exponent(Om)
-        n1 = oracle.norm1(Om)
-        assert n1 / 2 ** s <= th * (1 + 1e-15)
-        if s > 0:
-            assert n1 / 2 ** (s - 1) > th
+        for shift in (False, True):
+            s = oracle.scaling_exponent(Om, shift=shift)
+            n1 = oracle.norm1(Om - (oracle.trace_shift(Om) if shift else 0.0) * np.eye(9))
+            assert n1 / 2 ** s <= th * (1 + 1e-15)
+            if s > 0:
+                assert n1 / 2 ** (s - 1) > th
     assert oracle.norm1(np.array([[1, -2j], [3, 0.5]])) == pytest.approx(2.5 + 1.5)
     del g
+
+
+def test_trace_shift():
+    # exp(Omega) = e^mu exp(Omega - mu I) (scipy's expm on both sides); a large
+    # multiple of I in the generator costs no squaring once it is split off
+    B = wl.random_skew_hermitian_batch(1, 6, 2.0, config_id=9)[0]
+    Om = B - 300j * np.eye(6)
+    mu = oracle.trace_shift(Om)
+    assert mu == pytest.approx(np.trace(B) / 6 - 300j, abs=1e-12)
+    np.testing.assert_allclose(sl.expm(Om), np.exp(mu) * sl.expm(Om - mu * np.eye(6)), atol=1e-11)
+    assert oracle.scaling_exponent(Om, shift=False) == 6          # ||Om||_1 ~ 302 <= 64 theta_13
+    assert oracle.scaling_exponent(Om) == oracle.scaling_exponent(B - oracle.trace_shift(B) * np.eye(6)) == 0
+    assert oracle.scaling_exponent(np.full((3, 3), np.nan)) == -1
 
 
 # -------------------------------------------------------------------- chain

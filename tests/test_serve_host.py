@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 from paper_2411_09982_amd.serve import (Admission, Request, Result, job_bytes, latency_percentiles, max_overlap,
-                                         poisson_requests)
+                                         path_for, poisson_requests)
 
 
 def test_fifo_budget_and_slots():
@@ -66,3 +66,15 @@ def test_latency_split_into_wait_and_service():
     assert lat["p50_ms"] == pytest.approx(1200.0)
     assert lat["p99_ms"] == pytest.approx(1000.0 + 0.99 * 400.0)
     assert max_overlap(res) == 5
+
+
+def test_path_choice_and_action_memory():
+    def req(d, path="auto"):
+        return Request(0, np.eye(d, dtype=complex), np.eye(d, dtype=complex)[None], np.zeros((1, 8)), 0.1, 4, 1,
+                       "c64", np.eye(d, dtype=complex)[0], path=path)
+    assert path_for(req(32)) == "propagators" and path_for(req(33)) == "action"
+    assert path_for(req(500, "propagators")) == "propagators" and path_for(req(8, "action")) == "action"
+    # the action holds one chunk of generators, the propagators all M
+    d, K, M, chunk = 100, 2, 40, 8
+    assert (job_bytes(d, K, M, 2, "c64", chunk, path="propagators") - job_bytes(d, K, M, 2, "c64", chunk, path="action")
+            == (M - chunk) * d * d * 8)
