@@ -18,6 +18,7 @@ pytestmark = pytest.mark.gpu
 
 SAMPLED = [0, 1, 517, 999]
 PREFIX = 6
+FINAL = {}      # psi_M of each precision's run, for the comparison of the whole chains
 
 
 @pytest.fixture(scope="module")
@@ -75,3 +76,15 @@ def test_transmon_resonator_d1000_full_size(job_and_ref, dt_name):
     bound = w.M * 1e-13 if dt_name == "c128" else w.M * 2.0 ** smax * 2.0 ** -24
     say(f"  |psi_M| - 1 = {norm - 1:.3e} (bound {bound:.1e})")
     assert abs(norm - 1) <= bound
+    FINAL[dt_name] = job.psi.cpu().numpy()
+
+
+def test_transmon_resonator_d1000_whole_chain_fp32_vs_fp64():
+    # The whole 1000-interval chain of the FP32 path against the FP64 path's, whose
+    # sampled propagators and prefix match the oracle to 1e-12: the state's
+    # direction must hold the FP32 target over the whole job.
+    if set(FINAL) != {"c64", "c128"}:
+        pytest.skip("needs both full-size runs of this module")
+    inf = abs(float(oracle.state_infidelity(FINAL["c128"], FINAL["c64"])))
+    say(f"  1000-interval chain, FP32 vs FP64 path: state infidelity {inf:.3e}")
+    assert inf <= 1e-6
