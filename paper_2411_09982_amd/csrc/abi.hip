@@ -189,6 +189,15 @@ int square_cfg(int64_t d, int64_t nb, const typename Cx<T>::t* A, typename Cx<T>
   return QCHEFF_OK;
 }
 
+// The split-BF16 GEMM variant: the split done once per workgroup at the LDS
+// store (cfg 3, the default: 181 algorithmic TFLOP/s on the d = 1000 job), or
+// by each wave as it reads a fragment (cfg 2, QCHEFF_BF16X3_KERNEL=fragments:
+// 158); both give the same bits.
+int bf16x3_cfg() {
+  const char* v = std::getenv("QCHEFF_BF16X3_KERNEL");
+  return (v && std::strcmp(v, "fragments") == 0) ? 2 : 3;
+}
+
 // ------------------------------------------------------------------- coeffs
 int run_coeffs(const double* u, int64_t K, int64_t N, double dt, int64_t M, int order, double* c1,
                double* c2, hipStream_t st) {
@@ -459,7 +468,7 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
                      w.norms, kTheta13, bound, w.s_ws, s_out, w.smax);
   QC_HIP(hipGetLastError());
   C2 *A = w.X[0], *A2 = w.X[1], *A4 = w.X[2], *A6 = w.X[3], *W = w.X[4], *V = w.X[5];
-  int r, cfg = 2;   // the split-BF16 tile, or the tuned FP32 / FP64 one
+  int r, cfg = bf16x3_cfg();   // a split-BF16 tile, or the tuned FP32 / FP64 one
   if (!bf16x3 && (r = square_cfg<T>(d, nb, A, W, st, &cfg))) return r;
   // For skew-Hermitian A every even power, W and V are Hermitian (and A W
   // skew-Hermitian): only half of each of those products is formed.

@@ -322,6 +322,11 @@ template <> struct GemmTile<float, 1> {
 template <> struct GemmTile<float, 2> {
   static constexpr int BM = 128, BN = 128, BK = 32, WM = 64, WN = 32, NT = 512, WPE = 2;
 };
+// FP32 cfg 3: the split-BF16 products with the split done once per workgroup as
+// the tile is stored to LDS (cgemm_bf16x3_planes_kernel); same tile as cfg 2.
+template <> struct GemmTile<float, 3> {
+  static constexpr int BM = 128, BN = 128, BK = 32, WM = 64, WN = 32, NT = 512, WPE = 2;
+};
 template <> struct GemmTile<double, 0> {
   static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, NT = 256, WPE = 2;
 };
@@ -333,8 +338,8 @@ template <typename T> GemmParams<T> gemm_params(int M, int N, int K, int batch, 
   GemmParams<T> p{};
   p.M = M; p.N = N; p.K = K; p.batch = batch;
   p.cfg = cfg;
-  const int bm = cfg == 2 ? 128 : cfg ? GemmTile<T, 1>::BM : GemmTile<T, 0>::BM;
-  const int bn = cfg == 2 ? 128 : cfg ? GemmTile<T, 1>::BN : GemmTile<T, 0>::BN;
+  const int bm = cfg >= 2 ? 128 : cfg ? GemmTile<T, 1>::BM : GemmTile<T, 0>::BM;
+  const int bn = cfg >= 2 ? 128 : cfg ? GemmTile<T, 1>::BN : GemmTile<T, 0>::BN;
   p.tiles_m = (M + bm - 1) / bm;
   p.tiles_n = (N + bn - 1) / bn;
   p.alpha = T(1); p.beta = T(0); p.gamma = T(0); p.nx = 0;

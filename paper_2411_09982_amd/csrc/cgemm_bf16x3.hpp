@@ -205,4 +205,138 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void cg
   tile_epilogue<float, TM, TN>(p, jb, accr, acci, wm, wn, lane);
 }
 
+// Variant that splits each value once per workgroup, as it is stored to LDS: the
+// tile sits in LDS as six BF16 planes (re and im times hi, mid, lo) with k
+// contiguous, each 16-byte chunk of a row at chunk index c ^ ((row >> 2) & 3) so
+// that the 16 lanes reading one fragment hit 16 different bank groups.  One K
+// step of planes takes 96 KB, so LDS holds one step; the next step's values wait
+// in registers and are split and stored between two barriers after the MFMAs.
+// The MFMA loop itself has no vector-ALU work but the sign flips of -Ai.
+template <int BM, int BN, int WM, int WN, int NT, bool BCOMB>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void cgemm_bf16x3_planes_kernel(
+    GemmParams<float> p) {
+  using C2 = float2;
+  constexpr int BK = 32;
+  constexpr int WAVES_N = BN / WN;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  static_assert((BM / WM) * (BN / WN) * 64 == NT, "one wave per WM x WN sub-tile");
+  static_assert(BM * (BK / 8) == NT && BN * (BK / 8) == NT, "each thread moves eight k values of A and of B");
+
+  // [plane][row][k] as 16-byte chunks of eight BF16: row r, chunk c at index
+  // r * 4 + (c ^ ((r >> 2) & 3))
+  __shared__ u32x4 As[6][BM * (BK / 8)];
+  __shared__ u32x4 Bs[6][BN * (BK / 8)];
+
+  TileJob<float> jb;
+  if (!tile_job<float, BM, BN>(p, jb)) return;
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
+  const bool idle = p.herm && jb.tm == jb.tn && wm >= wn + WN;
+
+  f32x4 accr[TM][TN], acci[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) { accr[i][j][e] = 0.f; acci[i][j][e] = 0.f; }
+
+  const int ar = tid / (BK / 8), ak = (tid % (BK / 8)) * 8;
+  const int bc = tid % BN, bk = (tid / BN) * 8;
+  const int lda = int(p.lda), ldb = int(p.ldb);
+  C2 ra[8], rb[8];
+  auto load = [&](int k0) {
+    const int arow = min(jb.row0 + ar, p.M - 1) * lda;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ra[q] = jb.A[arow + max(0, min(k0 + ak + q, p.K - 1))];
+    const int bcol = min(jb.col0 + bc, p.N - 1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int off = max(0, min(k0 + bk + q, p.K - 1)) * ldb + bcol;
+      C2 v = jb.B[off];
+      if constexpr (BCOMB) {
+        const C2 x0 = jb.BX0[off], x1 = jb.BX1[off];
+        v.x = p.bxc[0] * v.x + p.bxc[1] * x0.x + p.bxc[2] * x1.x;
+        v.y = p.bxc[0] * v.y + p.bxc[1] * x0.y + p.bxc[2] * x1.y;
+      }
+      rb[q] = v;
+    }
+  };
+  auto chunk = [](int row, int c) { return row * (BK / 8) + (c ^ ((row >> 2) & 3)); };
+  auto store = [&](int k0) {
+    const bool arow_in = jb.row0 + ar < p.M, bcol_in = jb.col0 + bc < p.N;
+    C2 va[8], vb[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      va[q] = (arow_in && k0 + ak + q < p.K) ? ra[q] : czero<C2>();
+      vb[q] = (bcol_in && k0 + bk + q < p.K) ? rb[q] : czero<C2>();
+    }
+    u32x4 re[3], im[3];
+    split_frag(va, re, im);
+    const int ca = chunk(ar, ak / 8);
+#pragma unroll
+    for (int pl = 0; pl < 3; ++pl) {
+      As[pl][ca] = re[pl];
+      As[3 + pl][ca] = im[pl];
+    }
+    split_frag(vb, re, im);
+    const int cb = chunk(bc, bk / 8);
+#pragma unroll
+    for (int pl = 0; pl < 3; ++pl) {
+      Bs[pl][cb] = re[pl];
+      Bs[3 + pl][cb] = im[pl];
+    }
+  };
+
+  const int nk = (p.K + BK - 1) / BK;
+  if (nk > 0) {   // K = 0 (C = beta C + terms) reads no operand
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  const int fr = lane & 15, fc = lane >> 4;
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) load((kt + 1) * BK);
+    if (!idle) {
+      u32x4 bre[TN][3], bim[TN][3];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int cb = chunk(wn + j * 16 + fr, fc);
+#pragma unroll
+        for (int pl = 0; pl < 3; ++pl) {
+          bre[j][pl] = Bs[pl][cb];
+          bim[j][pl] = Bs[3 + pl][cb];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int ca = chunk(wm + i * 16 + fr, fc);
+        u32x4 are[3], aim[3], naim[3];
+#pragma unroll
+        for (int pl = 0; pl < 3; ++pl) {
+          are[pl] = As[pl][ca];
+          aim[pl] = As[3 + pl][ca];
+          naim[pl] = aim[pl] ^ 0x80008000u;   // -Ai: flip the BF16 sign bits
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          accr[i][j] = prod3(are, bre[j], accr[i][j]);
+          accr[i][j] = prod3(naim, bim[j], accr[i][j]);
+          acci[i][j] = prod3(are, bim[j], acci[i][j]);
+          acci[i][j] = prod3(aim, bre[j], acci[i][j]);
+        }
+      }
+    }
+    if (kt + 1 < nk) {
+      __syncthreads();   // every wave is done with this K step's planes
+      store((kt + 1) * BK);
+    }
+    __syncthreads();
+  }
+
+  tile_epilogue<float, TM, TN>(p, jb, accr, acci, wm, wn, lane);
+}
+
 }  // namespace qcheff

@@ -12,7 +12,14 @@ namespace qcheff {
 
 template <typename T, int CFG> void launch_tile(const GemmParams<T>& p, unsigned blocks, hipStream_t stream) {
   using G = GemmTile<T, CFG>;
-  if constexpr (std::is_same_v<T, float> && CFG == 2) {
+  if constexpr (std::is_same_v<T, float> && CFG == 3) {
+    if (p.nbx > 0)
+      hipLaunchKernelGGL((cgemm_bf16x3_planes_kernel<G::BM, G::BN, G::WM, G::WN, G::NT, true>), dim3(blocks),
+                         dim3(G::NT), 0, stream, p);
+    else
+      hipLaunchKernelGGL((cgemm_bf16x3_planes_kernel<G::BM, G::BN, G::WM, G::WN, G::NT, false>), dim3(blocks),
+                         dim3(G::NT), 0, stream, p);
+  } else if constexpr (std::is_same_v<T, float> && CFG == 2) {
     if (p.nbx > 0)
       hipLaunchKernelGGL((cgemm_bf16x3_kernel<G::BM, G::BN, G::WM, G::WN, G::NT, true>), dim3(blocks), dim3(G::NT), 0,
                          stream, p);
@@ -44,6 +51,7 @@ hipError_t launch_cgemm(const GemmParams<T>& p, hipStream_t stream, int64_t acti
   tm.begin(stream);
   if constexpr (std::is_same_v<T, float>) {
     if (p.cfg == 2) launch_tile<T, 2>(p, unsigned(blocks), stream);
+    if (p.cfg == 3) launch_tile<T, 3>(p, unsigned(blocks), stream);
   }
   if (p.cfg == 1)
     launch_tile<T, 1>(p, unsigned(blocks), stream);
@@ -58,7 +66,7 @@ hipError_t launch_cgemm(const GemmParams<T>& p, hipStream_t stream, int64_t acti
     double elems = double(p.M) * p.K + double(p.K) * p.N + mn * (1 + p.nx + (p.beta != T(0) ? 1 : 0));
     double bytes = elems * es;
     if (p.epi == EPI_AUG) bytes += mn * 32.0;  // V is the generic M N term; two FP64 halves are written
-    const int kid = sizeof(T) == 8 ? KERNEL_GEMM_F64 : p.cfg == 2 ? KERNEL_GEMM_BF16X3 : KERNEL_GEMM_F32;
+    const int kid = sizeof(T) == 8 ? KERNEL_GEMM_F64 : p.cfg >= 2 ? KERNEL_GEMM_BF16X3 : KERNEL_GEMM_F32;
     tm.end(stream, kid, flops, bytes * double(active));
   }
   return e;
