@@ -440,6 +440,12 @@ def main():
                 flops_per_launch=executed * k["flops"] / max(k["launches"], 1))
     extra = dict(
         whole_step_tflops=round(fl_step / (ms * 1e-3) / 1e12, 2),
+        # the metric's "MFMA %" for a mixed pipeline: each precision's matrix flops
+        # over its own peak, summed, over the step time
+        mfma_frac_whole_step=round(
+            (kern["f32"]["flops"] / (MFMA_PEAK_TFLOPS["c64"] * 1e12)
+             + kern["bf16x3"]["flops"] * BF16X3_PARTS / (MFMA_PEAK_TFLOPS["bf16x3"] * 1e12)
+             + kern["f64"]["flops"] / (MFMA_PEAK_TFLOPS["c128"] * 1e12)) / (a.steps * ms * 1e-3), 4),
         step_ms_p50=round(1000 * float(np.percentile(times, 50)), 2),
         step_ms_p99=round(1000 * float(np.percentile(times, 99)), 2),
         s_hist={str(v): s_hist.count(v) for v in sorted(set(s_hist))},
