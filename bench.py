@@ -486,7 +486,10 @@ def main():
         import oracle
         cpu, U_or, _ = cpu_baseline(w, a.cpu_intervals)
         # sampled parity of the benchmarked run: interval 0 from the oracle sample
-        extra["infidelity_U0_vs_oracle"] = float(oracle.propagator_infidelity(U_or[0], U_samples[0]))
+        # (direction of U_0 against the oracle's, and its distance from unitarity)
+        extra["infidelity_U0_vs_oracle"] = float(oracle.propagator_infidelity(U_or[0], U_samples[0],
+                                                                             normalized=True))
+        extra["unitarity_error_U0"] = float(oracle.unitarity_error(U_samples[0]))
 
     out = dict(
         metric="Magnus interval propagators/s at d=1024 (MFMA %) vs FP64 plain; p50/p99 latency",
