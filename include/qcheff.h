@@ -162,8 +162,10 @@ int qcheff_magnus_generators(const void* H0, const void* Hk, int64_t d, int64_t 
  *   omega      [batch][d][d], device, dtype.  Any square matrix; the Magnus
  *              generators are skew-Hermitian (dtype | QCHEFF_SKEW_HERMITIAN
  *              halves the Pade products for them).
- *   U          [batch][d][d], device, dtype, written.  May be the same buffer
- *              as omega (the input is consumed).
+ *   U          [batch][d][d], device, dtype, written.  Either the same buffer
+ *              as omega (the input is consumed) or one that does not overlap it
+ *              (QCHEFF_EINVAL otherwise); it also serves as scratch before the
+ *              result is written.
  *   s_out      optional [batch] int32, device: the number of squarings used,
  *              -1 where the norm was not finite (that item's U is NaN).
  *   ws         workspace of at least qcheff_workspace_bytes(QCHEFF_FN_EXPM, 1, d, ..);

@@ -213,9 +213,15 @@ hipError_t launch_generators(const double2* H0, const double2* Hk, const double2
                              const double* c1, const double* c2, int64_t M, double dt, OutC2* omega,
                              hipStream_t st) {
   constexpr int NC = K + ((ORDER == 2) ? K + K * (K - 1) / 2 : 0);
-  const int nch = 16;
   const int64_t dd = d * d;
-  dim3 grid(nblocks(dd, 256), unsigned((M + nch - 1) / nch));
+  // A block reads its operator values once per chunk of nch intervals, so the
+  // chunks are as long as 48 KB of coefficients allow, unless the grid would
+  // then have fewer than 2048 blocks.
+  const int64_t xb = int64_t(nblocks(dd, 256));
+  const int64_t cap = std::min<int64_t>(256, 49152 / (NC * int64_t(sizeof(double))));
+  const int64_t ych = std::max<int64_t>(1, (2048 + xb - 1) / xb);
+  const int nch = int(std::max<int64_t>(1, std::min<int64_t>(cap, (M + ych - 1) / ych)));
+  dim3 grid(unsigned(xb), unsigned((M + nch - 1) / nch));
   hipLaunchKernelGGL((generators_kernel<K, ORDER, OutC2>), grid, dim3(256), size_t(nch) * NC * sizeof(double), st,
                      H0, Hk, Cb, dd, c1, c2, M, nch, dt, omega);
   return hipGetLastError();
@@ -305,12 +311,11 @@ template <typename T> bool carve_expm(void* ws, size_t bytes, int64_t chunk, int
   return ok;
 }
 
-// out = A B (+ sum_i xc[i] X_i + gamma I) over a batch of d x d items; with bc,
-// the right operand is bc[0] X_0 + bc[1] X_1 + bc[2] X_2 instead of B.
+// out = A B (+ sum_i xc[i] X_i + gamma I) over a batch of d x d items.
 template <typename T>
 int gemm_sq(int cfg, int herm, typename Cx<T>::t* out, const typename Cx<T>::t* A, const typename Cx<T>::t* B,
             int64_t d, int64_t nb, hipStream_t st, int nx = 0, const typename Cx<T>::t* const* X = nullptr,
-            const T* xc = nullptr, T gamma = T(0), const T* bc = nullptr) {
+            const T* xc = nullptr, T gamma = T(0)) {
   auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
   p.herm = herm;
   const int64_t dd = d * d;
@@ -320,13 +325,6 @@ int gemm_sq(int cfg, int herm, typename Cx<T>::t* out, const typename Cx<T>::t* 
   p.nx = nx;
   for (int i = 0; i < nx; ++i) { p.X[i] = X[i]; p.xc[i] = xc[i]; }
   p.gamma = gamma;
-  if (bc) {
-    p.B = X[0];
-    p.nbx = 2;
-    p.BX[0] = X[1];
-    p.BX[1] = X[2];
-    for (int i = 0; i < 3; ++i) p.bxc[i] = bc[i];
-  }
   QC_HIP((launch_cgemm<T>(p, st)));
   return QCHEFF_OK;
 }
@@ -478,12 +476,18 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
   if ((r = gemm_sq<T>(cfg, h, A6, A4, A2, d, nb, st))) return r;
   // W = A6 (b13 A6 + b11 A4 + b9 A2) + b7 A6 + b5 A4 + b3 A2 + b1 I   (U = A W)
   // V = A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I
-  // The right operand's linear combination is formed as the GEMM loads it.
+  // The inner combinations go to buffers that are free at this point: the
+  // chunk's U (its input was consumed by the scaling) and W.  V is formed first
+  // (from W), then W (from U) overwrites its own buffer.  The outer terms are
+  // added by the epilogues.
+  hipLaunchKernelGGL((pade_inner_kernel<C2, T>), dim3(unsigned(std::min<int64_t>(nblocks(nb * dd, 256), 8192))),
+                     dim3(256), 0, st, A6, A4, A2, nb * dd, c[13], c[11], c[9], c[12], c[10], c[8], U, W);
+  QC_HIP(hipGetLastError());
   const C2* Xs[3] = {A6, A4, A2};
-  const T xw[3] = {c[7], c[5], c[3]}, bw[3] = {c[13], c[11], c[9]};
-  if ((r = gemm_sq<T>(cfg, h, W, A6, A6, d, nb, st, 3, Xs, xw, c[1], bw))) return r;
-  const T xv[3] = {c[6], c[4], c[2]}, bv[3] = {c[12], c[10], c[8]};
-  if ((r = gemm_sq<T>(cfg, h, V, A6, A6, d, nb, st, 3, Xs, xv, c[0], bv))) return r;
+  const T xv[3] = {c[6], c[4], c[2]};
+  if ((r = gemm_sq<T>(cfg, h, V, A6, W, d, nb, st, 3, Xs, xv, c[0]))) return r;
+  const T xw[3] = {c[7], c[5], c[3]};
+  if ((r = gemm_sq<T>(cfg, h, W, A6, U, d, nb, st, 3, Xs, xw, c[1]))) return r;
   // [q | p] = [V - A W | V + A W] in FP64
   {
     auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);

@@ -45,10 +45,6 @@ template <typename T> struct GemmParams {
   int sq;                       // 1: squaring mode (sq_* fields)
   int nx;                       // number of X terms (0..3); X share C's ld and stride
   const C2* X[3]; T xc[3];
-  // B operand as a linear combination: B_eff = bxc[0] B + bxc[1] BX[0] + bxc[2] BX[1]
-  // (BX share B's ld and stride) when nbx = 2; nbx = 0 uses B as it is
-  int nbx;
-  const C2* BX[2]; T bxc[3];
   // EPI_AUG target (FP64 always)
   double2* aug; int64_t ld_aug, s_aug, aug_off;
   // squaring mode: A = B = in, C = out, chosen per item from the remaining count
@@ -62,8 +58,6 @@ template <typename T> struct TileJob {
   const C2* A;
   const C2* B;
   C2* C;
-  const C2* BX0;
-  const C2* BX1;
 };
 
 // Fills `j` for this workgroup; false when it has nothing to do (past the last
@@ -110,8 +104,6 @@ __device__ __forceinline__ bool tile_job(const GemmParams<T>& p, TileJob<T>& j) 
     j.B = p.B + b * p.sB;
     j.C = p.C + b * p.sC;
   }
-  j.BX0 = p.nbx > 0 ? p.BX[0] + b * p.sB : j.B;
-  j.BX1 = p.nbx > 0 ? p.BX[1] + b * p.sB : j.B;
   return true;
 }
 
@@ -185,7 +177,7 @@ __device__ __forceinline__ void tile_epilogue(const GemmParams<T>& p, const Tile
   }
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int WAVES_PER_EU, bool BCOMB>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int WAVES_PER_EU>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU))) void cgemm_kernel(
     GemmParams<T> p) {
   using C2 = typename Cx<T>::t;
@@ -204,8 +196,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
   const int row0 = jb.row0, col0 = jb.col0;
   const C2* A = jb.A;
   const C2* B = jb.B;
-  const C2* BX0 = jb.BX0;
-  const C2* BX1 = jb.BX1;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -241,13 +231,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
       const int e = tid + NT * q, k = e / BN, c = e % BN;
       const int gk = k0 + k, gc = col0 + c;
       const bool in = gk < p.K && gc < p.N;
-      const int off = max(0, min(gk, p.K - 1)) * ldb + min(gc, p.N - 1);
-      C2 v = B[off];
-      if constexpr (BCOMB) {
-        const C2 x0 = BX0[off], x1 = BX1[off];
-        v.x = p.bxc[0] * v.x + p.bxc[1] * x0.x + p.bxc[2] * x1.x;
-        v.y = p.bxc[0] * v.y + p.bxc[1] * x0.y + p.bxc[2] * x1.y;
-      }
+      const C2 v = B[max(0, min(gk, p.K - 1)) * ldb + min(gc, p.N - 1)];
       rb[q] = in ? v : czero<C2>();
     }
   };

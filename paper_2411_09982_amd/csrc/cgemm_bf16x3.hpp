@@ -75,7 +75,7 @@ __device__ __forceinline__ f32x4 prod3(const u32x4 (&x)[3], const u32x4 (&y)[3],
   return c;
 }
 
-template <int BM, int BN, int WM, int WN, int NT, bool BCOMB>
+template <int BM, int BN, int WM, int WN, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void cgemm_bf16x3_kernel(
     GemmParams<float> p) {
   using C2 = float2;
@@ -122,14 +122,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void cg
     const int bcol = min(jb.col0 + bc, p.N - 1);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int off = max(0, min(k0 + bk + q, p.K - 1)) * ldb + bcol;
-      C2 v = jb.B[off];
-      if constexpr (BCOMB) {
-        const C2 x0 = jb.BX0[off], x1 = jb.BX1[off];
-        v.x = p.bxc[0] * v.x + p.bxc[1] * x0.x + p.bxc[2] * x1.x;
-        v.y = p.bxc[0] * v.y + p.bxc[1] * x0.y + p.bxc[2] * x1.y;
-      }
-      rb[q] = v;
+      rb[q] = jb.B[max(0, min(k0 + bk + q, p.K - 1)) * ldb + bcol];
     }
   };
   auto store = [&](int buf, int k0) {
@@ -212,7 +205,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void cg
 // step of planes takes 96 KB, so LDS holds one step; the next step's values wait
 // in registers and are split and stored between two barriers after the MFMAs.
 // The MFMA loop itself has no vector-ALU work but the sign flips of -Ai.
-template <int BM, int BN, int WM, int WN, int NT, bool BCOMB>
+template <int BM, int BN, int WM, int WN, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void cgemm_bf16x3_planes_kernel(
     GemmParams<float> p) {
   using C2 = float2;
@@ -254,14 +247,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void cg
     const int bcol = min(jb.col0 + bc, p.N - 1);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int off = max(0, min(k0 + bk + q, p.K - 1)) * ldb + bcol;
-      C2 v = jb.B[off];
-      if constexpr (BCOMB) {
-        const C2 x0 = jb.BX0[off], x1 = jb.BX1[off];
-        v.x = p.bxc[0] * v.x + p.bxc[1] * x0.x + p.bxc[2] * x1.x;
-        v.y = p.bxc[0] * v.y + p.bxc[1] * x0.y + p.bxc[2] * x1.y;
-      }
-      rb[q] = v;
+      rb[q] = jb.B[max(0, min(k0 + bk + q, p.K - 1)) * ldb + bcol];
     }
   };
   auto chunk = [](int row, int c) { return row * (BK / 8) + (c ^ ((row >> 2) & 3)); };

@@ -12,26 +12,15 @@ namespace qcheff {
 
 template <typename T, int CFG> void launch_tile(const GemmParams<T>& p, unsigned blocks, hipStream_t stream) {
   using G = GemmTile<T, CFG>;
-  if constexpr (std::is_same_v<T, float> && CFG == 3) {
-    if (p.nbx > 0)
-      hipLaunchKernelGGL((cgemm_bf16x3_planes_kernel<G::BM, G::BN, G::WM, G::WN, G::NT, true>), dim3(blocks),
-                         dim3(G::NT), 0, stream, p);
-    else
-      hipLaunchKernelGGL((cgemm_bf16x3_planes_kernel<G::BM, G::BN, G::WM, G::WN, G::NT, false>), dim3(blocks),
-                         dim3(G::NT), 0, stream, p);
-  } else if constexpr (std::is_same_v<T, float> && CFG == 2) {
-    if (p.nbx > 0)
-      hipLaunchKernelGGL((cgemm_bf16x3_kernel<G::BM, G::BN, G::WM, G::WN, G::NT, true>), dim3(blocks), dim3(G::NT), 0,
-                         stream, p);
-    else
-      hipLaunchKernelGGL((cgemm_bf16x3_kernel<G::BM, G::BN, G::WM, G::WN, G::NT, false>), dim3(blocks), dim3(G::NT),
-                         0, stream, p);
-  } else if (p.nbx > 0)
-    hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT, G::WPE, true>), dim3(blocks),
-                       dim3(G::NT), 0, stream, p);
+  if constexpr (std::is_same_v<T, float> && CFG == 3)
+    hipLaunchKernelGGL((cgemm_bf16x3_planes_kernel<G::BM, G::BN, G::WM, G::WN, G::NT>), dim3(blocks), dim3(G::NT), 0,
+                       stream, p);
+  else if constexpr (std::is_same_v<T, float> && CFG == 2)
+    hipLaunchKernelGGL((cgemm_bf16x3_kernel<G::BM, G::BN, G::WM, G::WN, G::NT>), dim3(blocks), dim3(G::NT), 0, stream,
+                       p);
   else
-    hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT, G::WPE, false>), dim3(blocks),
-                       dim3(G::NT), 0, stream, p);
+    hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT, G::WPE>), dim3(blocks), dim3(G::NT),
+                       0, stream, p);
 }
 
 // Launch; `active` is the number of items that do work (squaring mode skips

@@ -244,6 +244,25 @@ __global__ __launch_bounds__(256) void phase_kernel(C2* __restrict__ U, int64_t 
   }
 }
 
+// The inner Pade combinations of both polynomials in one elementwise pass:
+// P = w0 A6 + w1 A4 + w2 A2 and Q = v0 A6 + v1 A4 + v2 A2 (the right operands
+// of the W and V products), over n elements of the chunk.
+template <typename C2, typename T>
+__global__ __launch_bounds__(256) void pade_inner_kernel(const C2* __restrict__ A6, const C2* __restrict__ A4,
+                                                         const C2* __restrict__ A2, int64_t n, T w0, T w1, T w2,
+                                                         T v0, T v1, T v2, C2* __restrict__ P, C2* __restrict__ Q) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x) {
+    const C2 a6 = A6[e], a4 = A4[e], a2 = A2[e];
+    C2 pv, qv;
+    pv.x = w0 * a6.x + w1 * a4.x + w2 * a2.x;
+    pv.y = w0 * a6.y + w1 * a4.y + w2 * a2.y;
+    qv.x = v0 * a6.x + v1 * a4.x + v2 * a2.x;
+    qv.y = v0 * a6.y + v1 * a4.y + v2 * a2.y;
+    P[e] = pv;
+    Q[e] = qv;
+  }
+}
+
 // R = aug[:, d:2d] written (cast) to the buffer where the squarings must start
 // so that the last one lands in U: U if s is even (or no squaring), else P1.
 template <typename C2>

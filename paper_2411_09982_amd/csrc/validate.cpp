@@ -2,6 +2,7 @@
 #include "validate.hpp"
 
 #include <cmath>
+#include <cstdint>
 
 #include "../../include/qcheff.h"
 
@@ -93,6 +94,12 @@ Check check_expm(const void* omega, int64_t batch, int64_t d, int dtype, const v
   if (elem_bytes(dtype) == 0) return Check::fail(QCHEFF_EINVAL, "unknown dtype");
   if (batch == 0) return Check::ok();
   if (!omega || !U) return Check::fail(QCHEFF_EINVAL, "omega and U must not be NULL");
+  if (omega != U) {   // the same buffer, or two that do not overlap (U serves as scratch)
+    const size_t bytes = size_t(batch) * size_t(d) * size_t(d) * elem_bytes(dtype);
+    const uintptr_t o = reinterpret_cast<uintptr_t>(omega), u = reinterpret_cast<uintptr_t>(U);
+    if (o < u + bytes && u < o + bytes)
+      return Check::fail(QCHEFF_EINVAL, "U must be omega itself or not overlap it");
+  }
   if (!ws) return Check::fail(QCHEFF_EWORKSPACE, "workspace must not be NULL");
   if (expm_chunk(ws_bytes, batch, d, dtype) < 1)
     return Check::fail(QCHEFF_EWORKSPACE, "workspace smaller than one item needs");

@@ -72,6 +72,10 @@ def test_expm_validation_and_workspace():
     assert e(FAKE, 2, 8, q.C64, FAKE, None, FAKE, one - 1, None) == q.EWORKSPACE
     assert e(None, 2, 8, q.C64, FAKE, None, FAKE, one, None) == q.EINVAL
     assert e(FAKE, -1, 8, q.C64, FAKE, None, FAKE, one, None) == q.EINVAL
+    # U is omega itself or a buffer that does not overlap it
+    for off in (8, 2 * 8 * 8 * 8 - 8):
+        assert e(FAKE, 2, 8, q.C64, ctypes.c_void_p(FAKE.value + off), None, FAKE, 1 << 30, None) == q.EINVAL
+        assert e(ctypes.c_void_p(FAKE.value + off), 2, 8, q.C64, FAKE, None, FAKE, 1 << 30, None) == q.EINVAL
     # per item: 6 d^2 working matrices + the 2 d^2 FP64 augmented system + pivots
     d = 1000
     c64 = q.workspace_bytes(q.FN_EXPM, 1, d, 1, 1, q.C64)
