@@ -56,8 +56,8 @@ DEFAULT_CHUNK = {"c64": 256, "c128": 128, "bf16x3": 256}   # intervals per expm 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="transmon10x_resonator100_d1000")
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128", "bf16x3"],
                     help="c64: FP32 MFMA products; bf16x3: the same complex64 path with the products on BF16 "
