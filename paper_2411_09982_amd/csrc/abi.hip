@@ -346,7 +346,9 @@ struct LuCtx {
 int lu_gemm_update(const LuCtx& c, int64_t r0, int64_t r1, int64_t c0, int64_t c1, int64_t k0, int64_t k1) {
   // A[r0:r1, c0:c1] -= A[r0:r1, k0:k1] * A[k0:k1, c0:c1]
   if (r1 <= r0 || c1 <= c0 || k1 <= k0) return QCHEFF_OK;
-  auto p = gemm_params<double>(int(r1 - r0), int(c1 - c0), int(k1 - k0), int(c.nb), rule_cfg(c.d));
+  // narrow updates (a 32-row leaf block, a 16-column panel) take the small tile
+  const int cfg = (r1 - r0 <= 48 || c1 - c0 <= 48) ? 1 : rule_cfg(c.d);
+  auto p = gemm_params<double>(int(r1 - r0), int(c1 - c0), int(k1 - k0), int(c.nb), cfg);
   p.A = c.aug + r0 * c.ld + k0; p.lda = c.ld; p.sA = c.stride;
   p.B = c.aug + k0 * c.ld + c0; p.ldb = c.ld; p.sB = c.stride;
   p.C = c.aug + r0 * c.ld + c0; p.ldc = c.ld; p.sC = c.stride;
