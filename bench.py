@@ -239,7 +239,7 @@ def cpu_baseline(w, n_int):
     try:
         from threadpoolctl import threadpool_info
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    except Exception:
+    except ImportError:
         cores = os.cpu_count()
     s = w.N // w.M
     u = np.ascontiguousarray(w.u[:, : n_int * s])
@@ -485,6 +485,15 @@ def main():
     if not a.no_cpu_baseline:
         import oracle
         cpu, U_or, _ = cpu_baseline(w, a.cpu_intervals)
+        # the same oracle with its BLAS / LAPACK pinned to one thread, on a shorter prefix
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                one, _, _ = cpu_baseline(w, max(1, a.cpu_intervals // 12))
+            extra["cpu_baseline_1thread"] = dict(value=round(one["value"], 3), unit=one["unit"], cores=1,
+                                                 sample=one["sample"])
+        except ImportError:
+            pass
         # sampled parity of the benchmarked run: interval 0 from the oracle sample
         # (direction of U_0 against the oracle's, and its distance from unitarity)
         extra["infidelity_U0_vs_oracle"] = float(oracle.propagator_infidelity(U_or[0], U_samples[0],
