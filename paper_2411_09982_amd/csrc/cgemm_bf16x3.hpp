@@ -5,9 +5,9 @@
 // numbers, with |m| <= 2^-9 |x| and |l| <= 2^-18 |x|.  A real product keeps the
 // six part products down to order 2^-18 (l*h, h*l, m*m, m*h, h*m, h*h, in rising
 // size); the three it drops (m*l, l*m, l*l) are below 2^-26 of |x||y|.  The part
-// products are exact in FP32, so a sum of products carries the accumulation
-// error of the BF16 instruction instead of that of FP32 MFMA, and runs on
-// 16x16x32 BF16 MFMA (FP32 accumulation) at 2.5 PFLOP/s instead of 157 TFLOP/s.
+// products are exact in FP32; each K step's part products are summed apart from
+// the running sum (cmac3), which is rounded once per step, and the products run
+// on 16x16x32 BF16 MFMA (FP32 accumulation) at 2.5 PFLOP/s instead of 157 TFLOP/s.
 //
 // Same parameters, tile mapping and epilogues as cgemm_kernel<float>.  Tiles sit
 // in LDS as FP32 (k-major, double-buffered: one barrier per K step); each wave
@@ -63,16 +63,42 @@ __device__ __forceinline__ void split_frag(const float2 (&v)[8], u32x4 (&re)[3],
   }
 }
 
-// c += x y for split operands x = (h, m, l), y = (h, m, l): six part products,
-// the smallest first.
-__device__ __forceinline__ f32x4 prod3(const u32x4 (&x)[3], const u32x4 (&y)[3], f32x4 c) {
-  c = mfma16_bf16(x[2], y[0], c);
-  c = mfma16_bf16(x[0], y[2], c);
-  c = mfma16_bf16(x[1], y[1], c);
-  c = mfma16_bf16(x[1], y[0], c);
-  c = mfma16_bf16(x[0], y[1], c);
-  c = mfma16_bf16(x[0], y[0], c);
-  return c;
+// One K step (32 k) of the complex block products of one A block with TN B
+// blocks, Re += Ar Br - Ai Bi and Im += Ar Bi + Ai Br, for split operands
+// (h, m, l) with -Ai given as nai: six part products per real product.  Each
+// part sum of the step goes to a fresh accumulator (the five small part products
+// first, then hi * hi), which is added to the running sum once: the running sum
+// is rounded once per K step instead of once per MFMA, so the accumulation error
+// stays at or below that of the FP32 MFMA kernel.  The 2 TN part sums advance
+// round robin, so that no MFMA waits for the one before it.
+template <int TN>
+__device__ __forceinline__ void cmac3(const u32x4 (&ar)[3], const u32x4 (&ai)[3], const u32x4 (&nai)[3],
+                                      const u32x4 (&br)[TN][3], const u32x4 (&bi)[TN][3], f32x4 (&accr)[TN],
+                                      f32x4 (&acci)[TN]) {
+  f32x4 tr[TN], ti[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) tr[j] = ti[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  constexpr int PX[6] = {2, 0, 1, 1, 0, 0}, PY[6] = {0, 2, 1, 0, 1, 0};   // lo*hi, hi*lo, mid*mid, mid*hi, hi*mid, hi*hi
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      tr[j] = mfma16_bf16(ar[PX[t]], br[j][PY[t]], tr[j]);
+      ti[j] = mfma16_bf16(ar[PX[t]], bi[j][PY[t]], ti[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      tr[j] = mfma16_bf16(nai[PX[t]], bi[j][PY[t]], tr[j]);
+      ti[j] = mfma16_bf16(ai[PX[t]], br[j][PY[t]], ti[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < TN; ++j)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      accr[j][e] += tr[j][e];
+      acci[j][e] += ti[j][e];
+    }
 }
 
 template <int BM, int BN, int WM, int WN, int NT>
@@ -172,14 +198,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void cg
         u32x4 naim[3];
 #pragma unroll
         for (int pl = 0; pl < 3; ++pl) naim[pl] = aim[pl] ^ 0x80008000u;   // -Ai: flip the BF16 sign bits
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          // Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br
-          accr[i][j] = prod3(are, bre[j], accr[i][j]);
-          accr[i][j] = prod3(naim, bim[j], accr[i][j]);
-          acci[i][j] = prod3(are, bim[j], acci[i][j]);
-          acci[i][j] = prod3(aim, bre[j], acci[i][j]);
-        }
+        cmac3<TN>(are, aim, naim, bre, bim, accr[i], acci[i]);
         if (i + 1 < TM) {
           split_frag(vn, are, aim);
           // 24 TN MFMAs against about 90 VALU of the split: one MFMA, then two VALU
@@ -306,13 +325,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void cg
           aim[pl] = As[3 + pl][ca];
           naim[pl] = aim[pl] ^ 0x80008000u;   // -Ai: flip the BF16 sign bits
         }
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          accr[i][j] = prod3(are, bre[j], accr[i][j]);
-          accr[i][j] = prod3(naim, bim[j], accr[i][j]);
-          acci[i][j] = prod3(are, bim[j], acci[i][j]);
-          acci[i][j] = prod3(aim, bre[j], acci[i][j]);
-        }
+        cmac3<TN>(are, aim, naim, bre, bim, accr[i], acci[i]);
       }
     }
     if (kt + 1 < nk) {

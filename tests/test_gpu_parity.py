@@ -115,6 +115,20 @@ def test_generators_parity(d, K, order, dtype):
         assert np.abs(host(om2) - ref2).max() <= 2 * tol
 
 
+def test_generators_parity_long_chunks():
+    # d = 730 fills 2048 blocks with one chunk of intervals, and K = 8 (44 coefficients
+    # per interval) caps a chunk at 139 intervals: 200 intervals run as 139 + 61
+    d, K, M = 730, 8, 200
+    say(f"generators d={d} K={K} M={M}")
+    w = wl.random_system(d, K, M * 5, M, 2, config_id=7, drift_scale=20.0, drive_scale=3.0)
+    c1, c2 = oracle.interval_coefficients(w.u, w.dt_sample, w.M, 2)
+    ref = oracle.generators(w.H0, w.Hk, c1, c2, w.dt_interval, 2)
+    om, _ = q.magnus_generators(gpu(w.H0), gpu(w.Hk), gpu(c1), gpu(c2), w.dt_interval, 2, torch.complex64)
+    torch.cuda.synchronize()
+    err = np.abs(host(om) - ref).max()
+    assert err <= 1.2e-7 * np.abs(ref).max(), err
+
+
 # ------------------------------------------------------------- exponential
 
 EXPM_DIMS = [1, 2, 3, 7, 8, 16, 17, 31, 32, 33, 64, 100, 128, 257]
