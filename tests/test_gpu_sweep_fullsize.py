@@ -1,0 +1,54 @@
+"""Full-size parity of the batched sweep: the 512 transmon-chain instances of
+uneven dimension (d in {16, 32, 64, 128, 256, 512}, M = 256, order 2, complex64)
+in the launch configuration `bench.py --sweep` times (one `Sweep` over all jobs,
+eager and then replayed from the captured per-group graphs).
+
+The oracle runs the whole chain of one job per dimension; every job's final
+state is checked against the norm bound of the FP32 path, and the graph replay
+must reproduce the eager states bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+from tests.test_gpu_parity import say
+
+pytestmark = pytest.mark.gpu
+
+q = pytest.importorskip("paper_2411_09982_amd")
+from paper_2411_09982_amd.sweep import Sweep  # noqa: E402
+
+
+def test_sweep_512_instances_full_size():
+    jobs = wl.sweep_instances()
+    dims = sorted({j.d for j in jobs})
+    assert len(jobs) == 512 and dims == [16, 32, 64, 128, 256, 512] and all(j.M == 256 for j in jobs)
+    say(f"sweep of {len(jobs)} jobs, d = {dims}")
+    sw = Sweep(jobs, torch.complex64)
+    sw.run()
+    eager = sw.states()
+    # every job: the norm error of the FP32 chain stays within M 2^s u for the
+    # largest scaling exponent of its intervals
+    smax = {}
+    for g in sw.groups:
+        s = g["s"].cpu().numpy().reshape(len(g["idx"]), g["M"])
+        for k, i in enumerate(g["idx"]):
+            smax[i] = int(s[k].max())
+    assert min(smax.values()) >= 0
+    for i, j in enumerate(jobs):
+        assert oracle.norm_error(eager[i]) <= j.M * 2.0 ** smax[i] * 2.0 ** -24, (i, j.d, smax[i])
+    # one job per dimension against the oracle's whole chain
+    for d in dims:
+        i = next(k for k, j in enumerate(jobs) if j.d == d)
+        j = jobs[i]
+        ref = oracle.run(j.H0, j.Hk, j.u, j.dt_sample, j.M, j.order, psi0=j.psi0)
+        inf = abs(oracle.state_infidelity(ref["psi"], eager[i]))
+        say(f"  job {i}: d={d}, 256-interval chain state infidelity {inf:.3e}")
+        assert inf <= 1e-6, (i, d, inf)
+    # the captured graphs replay the same states
+    sw.capture()
+    sw.run()
+    replay = sw.states()
+    assert all(np.array_equal(eager[i], replay[i]) for i in eager)
