@@ -217,7 +217,35 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
   // inside one item fit 32 bits (the host keeps ld * rows below 2^31).
   const int lda = int(p.lda), ldb = int(p.ldb);
   C2 ra[LA], rb[LB];
+  // FP64: rows of A past M and columns of B past N only feed outputs the
+  // epilogue drops, so they may read the clamped last row / column as they are,
+  // and a K step wholly inside K loads from precomputed addresses with no clamp
+  // and no select (+4 % on large FP64 products; the FP32 kernel measured faster
+  // with the clamped form throughout)
+  const C2* pa[LA];
+  const C2* pb[LB];
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int e = tid + NT * q;
+      pa[q] = A + min(row0 + e / BK, p.M - 1) * lda + e % BK;   // A[row][k0 + ka] at pa[q][k0]
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int e = tid + NT * q;
+      pb[q] = B + (e / BN) * ldb + min(col0 + e % BN, p.N - 1);   // B[k0 + kb][col] at pb[q][k0 ldb]
+    }
+  }
   auto load = [&](int k0) {
+    if constexpr (sizeof(T) == 8) {
+      if (k0 + BK <= p.K) {
+#pragma unroll
+        for (int q = 0; q < LA; ++q) ra[q] = pa[q][k0];
+#pragma unroll
+        for (int q = 0; q < LB; ++q) rb[q] = pb[q][k0 * ldb];
+        return;
+      }
+    }
 #pragma unroll
     for (int q = 0; q < LA; ++q) {
       const int e = tid + NT * q, r = e / BK, k = e % BK;
