@@ -1,7 +1,6 @@
 // Batched complex GEMM on MFMA (gfx950), FP32 or FP64, interleaved complex storage.
 //
 //   C_b = alpha * A_b B_b + beta * C_b + sum_i xc[i] X_{i,b} + gamma * I      (EPI_STD)
-//   (B_b may be a linear combination of up to three matrices, formed as it loads)
 //   aug_b[:, :N] = V_b - A_b B_b,  aug_b[:, off:off+N] = V_b + A_b B_b (FP64)  (EPI_AUG)
 //
 // A complex product is four real MFMA products on planar operands:
@@ -10,7 +9,9 @@
 // sub-tile built from 16x16x4 MFMA instructions.  K advances BK at a time
 // through double-buffered LDS; the next tile is fetched into registers while
 // the current one is consumed.  Any M, N, K, leading dimension and offset is
-// accepted: out-of-range loads read zero and out-of-range stores are skipped.
+// accepted: k past K reads as zero, rows of A past M and columns of B past N
+// read a clamped valid element (they only feed outputs that are not stored),
+// and out-of-range stores are skipped.
 #pragma once
 
 #include "common.hpp"
