@@ -64,8 +64,8 @@ __global__ __launch_bounds__(1024) void lu_panel_reg_kernel(double2* aug, int64_
   int* piv = piv_all + int64_t(b) * d;
   const int nrows = d - k0, nc = k1 - k0;
   const bool own = tid < nrows;
-  __shared__ double2 sbuf[2][NB];
-  __shared__ double2 prow[NB];
+  __shared__ double2 prow[NB];   // the pivot row of the current column
+  __shared__ double2 orow[NB];   // the row it displaces
   __shared__ double wv[T / 64];
   __shared__ int wi[T / 64];
   double2 r[NB];
@@ -96,30 +96,29 @@ __global__ __launch_bounds__(1024) void lu_panel_reg_kernel(double2* aug, int64_
     for (int w = 1; w < T / 64; ++w) argmax_combine(v, idx, wv[w], wi[w]);
     const int p = (idx >= j && idx < nrows) ? idx : j;
     if (tid == 0) piv[k0 + j] = k0 + p;
-    if (p != j) {
-      if (tid == p) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) sbuf[0][c] = r[c];
-      }
-      if (tid == j) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) sbuf[1][c] = r[c];
-      }
-      __syncthreads();
-      if (tid == p) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) r[c] = sbuf[1][c];
-      }
-      if (tid == j) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) r[c] = sbuf[0][c];
-      }
-    }
-    if (tid == j) {
+    // one exchange through LDS: the pivot row is published (it becomes row j
+    // and drives the elimination), row j goes to the pivot's owner.  Two
+    // barriers per column: every read of wv, prow and orow of this column
+    // happens before the next column's first barrier, every write after it.
+    if (tid == p) {
 #pragma unroll
       for (int c = 0; c < NB; ++c) prow[c] = r[c];
     }
+    if (p != j && tid == j) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) orow[c] = r[c];
+    }
     __syncthreads();
+    if (p != j) {
+      if (tid == j) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) r[c] = prow[c];
+      }
+      if (tid == p) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) r[c] = orow[c];
+      }
+    }
     if (own && tid > j) {
       const double2 l = cmul(r[j], crecip(prow[j]));
       r[j] = l;
@@ -130,7 +129,6 @@ __global__ __launch_bounds__(1024) void lu_panel_reg_kernel(double2* aug, int64_
         r[c].y -= t.y;
       }
     }
-    __syncthreads();
   });
 
   if (own) {
