@@ -35,6 +35,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cgemm_f32_traffic_transmon_resona
 GEMM_SOURCE = os.path.join(ROOT, "paper_2411_09982_amd", "csrc", "cgemm.hpp")
 
 
+TRAFFIC_WORKLOAD = "transmon10x_resonator100_d1000"   # the job the committed counters were taken on
+
+
 def measured_traffic():
     """HBM bytes per launch of the FP32 GEMM kernel from the committed rocprofv3 --pmc
     summary, or None when the kernel source has changed since it was measured."""
@@ -430,11 +433,14 @@ def main():
     executed = BF16X3_PARTS if a.dtype == "bf16x3" else 1    # MFMA flops per algorithmic flop
     achieved = executed * k["flops"] / (k["ms"] * 1e-3) / 1e12 if k["ms"] > 0 else 0.0
     peak = MFMA_PEAK_TFLOPS[a.dtype]
+    # HBM bytes per launch as counted for this exact job and launch configuration
+    traffic = (measured_traffic() if a.dtype == "c64" and a.workload == TRAFFIC_WORKLOAD
+               and job.chunk == DEFAULT_CHUNK["c64"] and job.lanes == 1 else None)
     roof = dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
-                frac=round(achieved / peak, 4), traffic=measured_traffic() if a.dtype == "c64" else None,
+                frac=round(achieved / peak, 4), traffic=traffic,
                 kernel={"c64": "cgemm_kernel<float,...> (Pade products, squarings)",
-                        "bf16x3": "cgemm_bf16x3_kernel (Pade products, squarings; BF16 MFMA flops executed, "
-                                  "6 per algorithmic flop)",
+                        "bf16x3": "cgemm_bf16x3_planes_kernel (Pade products, squarings; BF16 MFMA flops "
+                                  "executed, 6 per algorithmic flop)",
                         "c128": "cgemm_kernel<double,...> (Pade products, squarings, LU updates)"}[a.dtype],
                 launches=k["launches"], avg_launch_ms=round(k["ms"] / max(k["launches"], 1), 4),
                 flops_per_launch=executed * k["flops"] / max(k["launches"], 1))
