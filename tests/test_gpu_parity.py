@@ -1,9 +1,11 @@
 """GPU parity: every C-ABI entry point against the CPU oracle, element by element.
 
-Tolerances (written here, derived in the design doc):
+Tolerances:
   FP64 path (QCHEFF_C128): propagator / state infidelity <= 1e-12 and
-      max-abs error <= 1e-10 per U_n;
-  FP32 path (QCHEFF_C64, FP64 norm / scaling / Pade solve): infidelity <= 1e-6;
+      max-abs error <= 1e-10 per U_n (a few hundred roundings of 2^-53 per entry);
+  FP32 path (QCHEFF_C64, FP64 norm / scaling / Pade solve): infidelity <= 1e-6,
+      or 4 2^s 2^-24 per U_n where s squarings double the radial error the FP32
+      rounding of R leaves (inf_tol below);
   coefficients: within a few ulps of the sum of absolute terms (compensated sums).
 """
 import math
