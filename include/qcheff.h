@@ -47,7 +47,7 @@ extern "C" {
 #define QCHEFF_EINVAL       -1  /* bad shape, pointer, order, mode or flag      */
 #define QCHEFF_EWORKSPACE   -2  /* workspace missing or too small               */
 #define QCHEFF_EDEVICE      -3  /* a HIP call or kernel launch failed           */
-#define QCHEFF_EUNSUPPORTED -5  /* valid request this build does not implement */
+#define QCHEFF_EUNSUPPORTED -5  /* valid request the library does not implement */
 
 /* element types */
 #define QCHEFF_C128 1           /* complex double; every step in FP64           */
@@ -128,7 +128,7 @@ int qcheff_magnus_coeffs(const double* u, int64_t K, int64_t N, double dt_sample
  *
  *   H0         [d][d] Hermitian, device, op_dtype.
  *   Hk         [K][d][d] Hermitian, device, op_dtype.  Hermiticity is not checked.
- *   op_dtype   QCHEFF_C128 (this build accepts C128 operators only).
+ *   op_dtype   QCHEFF_C128 (the library accepts C128 operators only).
  *   c1, c2     as written by qcheff_magnus_coeffs (device); c2 may be NULL for order 1.
  *   M          intervals to form (>= 0).  A caller that streams intervals in
  *              chunks passes c1/c2 offset to the chunk and the chunk's M.

@@ -196,7 +196,7 @@ def spin_chain(n_spins: int = 10, n_samples: int = 10_000, M: int = 200, order: 
     controls H_x = sum_j sx_j, H_y = sum_j sy_j with u_x = A env cos(2 pi f t),
     u_y = A env sin(2 pi f t), f ~ U[0, 10] GHz (seeded), Gaussian env sigma = T/5,
     T = 25 ns.  w = 2pi*5, J = 2pi*0.05, g = 2pi*0.02, A = 2pi*0.05 GHz (the paper
-    publishes symbols only; these values are this build's choice).  psi0 = |0...0>.
+    publishes symbols only; these values are chosen here).  psi0 = |0...0>.
     """
     g_rng = rng(config_id)
     w, J, gnn, amp, t_total = TWO_PI * 5.0, TWO_PI * 0.05, TWO_PI * 0.02, TWO_PI * 0.05, 25.0
