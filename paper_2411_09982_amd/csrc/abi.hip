@@ -31,21 +31,53 @@ struct TimedLaunch {
   hipEvent_t a, b;
 };
 std::atomic<int> g_timing{0};
-std::mutex g_timing_mu;
+std::mutex g_timing_mu;               // guards g_timed and g_events
 std::vector<TimedLaunch> g_timed;
+// Events come from a pool and go back to it once read: creating two events per
+// launch costs more host time than some of the launches they time.
+std::vector<hipEvent_t> g_events;
+
+hipError_t take_event(hipEvent_t* e) {
+  {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (!g_events.empty()) {
+      *e = g_events.back();
+      g_events.pop_back();
+      return hipSuccess;
+    }
+  }
+  return hipEventCreate(e);
+}
+
+void give_events_locked(const TimedLaunch& t) {
+  g_events.push_back(t.a);
+  g_events.push_back(t.b);
+}
 }  // namespace
 
 void LaunchTimer::begin(hipStream_t st) {
   on = g_timing.load(std::memory_order_relaxed) != 0;
   if (!on) return;
-  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess || hipEventRecord(a, st) != hipSuccess)
+  if (take_event(&a) != hipSuccess) {
     on = false;
+    return;
+  }
+  if (take_event(&b) != hipSuccess || hipEventRecord(a, st) != hipSuccess) {
+    on = false;
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_events.push_back(a);
+    if (b) g_events.push_back(b);
+  }
 }
 
 void LaunchTimer::end(hipStream_t st, int kernel, double flops, double bytes) {
   if (!on) return;
-  if (hipEventRecord(b, st) != hipSuccess) return;
   std::lock_guard<std::mutex> lk(g_timing_mu);
+  if (hipEventRecord(b, st) != hipSuccess) {
+    g_events.push_back(a);
+    g_events.push_back(b);
+    return;
+  }
   g_timed.push_back({kernel, flops, bytes, a, b});
 }
 
@@ -822,10 +854,7 @@ const char* qcheff_last_error(void) { return g_last_error.c_str(); }
 
 int qcheff_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_timing_mu);
-  for (auto& t : g_timed) {
-    hipEventDestroy(t.a);
-    hipEventDestroy(t.b);
-  }
+  for (auto& t : g_timed) give_events_locked(t);
   g_timed.clear();
   g_timing.store(on ? 1 : 0);
   return QCHEFF_OK;
@@ -849,8 +878,7 @@ int qcheff_timing_read(int kernel, int64_t* launches, double* total_ms, double* 
     fl += t.flops;
     by += t.bytes;
     ++n;
-    hipEventDestroy(t.a);
-    hipEventDestroy(t.b);
+    give_events_locked(t);
   }
   g_timed.swap(keep);
   *launches = n;
