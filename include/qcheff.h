@@ -47,6 +47,9 @@ extern "C" {
 #define QCHEFF_EINVAL       -1  /* bad shape, pointer, order, mode or flag      */
 #define QCHEFF_EWORKSPACE   -2  /* workspace missing or too small               */
 #define QCHEFF_EDEVICE      -3  /* a HIP call or kernel launch failed           */
+#define QCHEFF_ENONFINITE   -4  /* reported by qcheff_sync_status: a non-finite
+                                   norm or generator, or a zero pivot, since the
+                                   last call of it                              */
 #define QCHEFF_EUNSUPPORTED -5  /* valid request the library does not implement */
 
 /* element types */
@@ -245,6 +248,19 @@ size_t qcheff_workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int o
 
 /* Message for the calling thread's last non-OK status (never NULL). */
 const char* qcheff_last_error(void);
+
+/*
+ * qcheff_sync_status - waits for `stream`, then reports and clears the
+ * conditions the library's kernels (and host-side checks) have flagged on the
+ * current device since the previous call: a non-finite norm of a generator
+ * (the scaling step of the exponential, Sec. 4.1, or the Taylor action), or a
+ * zero pivot in the LU of a Pade denominator.  The affected results are NaN
+ * (qcheff_expm_batched also marks them with s_out = -1); this call is the one
+ * place to learn about it without inspecting them.  The flags are per device
+ * and shared by every stream and thread of the process.
+ * Returns QCHEFF_OK, QCHEFF_ENONFINITE or QCHEFF_EDEVICE.
+ */
+int qcheff_sync_status(void* stream);
 
 /*
  * Kernel timing (instrumentation for throughput and roofline measurements).

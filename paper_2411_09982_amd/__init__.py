@@ -12,6 +12,7 @@ Functions (same names as the C entry points, minus the ``qcheff_`` prefix):
   magnus_generators(H0, Hk, c1, c2, dt_interval, order, out_dtype) -> omega
   expm_batched(omega)                                   -> U, s
   propagate(U, mode, x)                                 -> x (in place)
+  sync_status(stream)                                   -> OK or ENONFINITE
 and ``evolve(...)``, the four calls in sequence (the paper's evolve()), and
 ``evolve_state(...)``, the state-only path through qcheff_propagate_action.
 """
@@ -27,7 +28,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqcheff_magnus.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "qcheff.h")
 
-OK, EINVAL, EWORKSPACE, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -5
+OK, EINVAL, EWORKSPACE, EDEVICE, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 C128, C64, C64_BF16X3 = 1, 2, 3
 STATE, PRODUCT = 1, 2
 REUSE_BASIS = 1
@@ -74,6 +75,8 @@ def lib() -> ctypes.CDLL:
     L.qcheff_timing_read.restype = i32
     L.qcheff_last_error.argtypes = []
     L.qcheff_last_error.restype = ctypes.c_char_p
+    L.qcheff_sync_status.argtypes = [vp]
+    L.qcheff_sync_status.restype = i32
     _lib = L
     return L
 
@@ -87,6 +90,16 @@ def header_symbols() -> list[str]:
 def _check(fn: str, status: int) -> None:
     if status != OK:
         raise QcheffError(fn, status, lib().qcheff_last_error().decode())
+
+
+def sync_status(stream=None) -> int:
+    """qcheff_sync_status: waits for the stream; OK, or ENONFINITE if a generator
+    norm was not finite or a Pade denominator had a zero pivot since the last call
+    (the flags are then cleared).  Raises only for a device error."""
+    st = lib().qcheff_sync_status(_stream(stream))
+    if st not in (OK, ENONFINITE):
+        _check("qcheff_sync_status", st)
+    return st
 
 
 def _ptr(t):

@@ -31,6 +31,7 @@ struct TimedLaunch {
   hipEvent_t a, b;
 };
 std::atomic<int> g_timing{0};
+std::atomic<unsigned> g_host_status{0};   // conditions found on the host, reported with the device's
 std::mutex g_timing_mu;               // guards g_timed and g_events
 std::vector<TimedLaunch> g_timed;
 // Events come from a pool and go back to it once read: creating two events per
@@ -674,6 +675,7 @@ int run_action(const void* Ov, int64_t M, int64_t d, void* x, void* traj, double
     int64_t s = 1;
     if (!(nu <= 1.7976931348623157e308) || !std::isfinite(m_n.x) || !std::isfinite(m_n.y)) {
       m = -1;   // non-finite generator: the state becomes NaN
+      g_host_status.fetch_or(STATUS_NONFINITE);
     } else if (nu > 0.0) {
       action_params(nu, tol, &m, &s);
       if (m == 0 || double(m) * double(s) > kMaxActionTerms)
@@ -851,6 +853,21 @@ size_t qcheff_workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int o
 }
 
 const char* qcheff_last_error(void) { return g_last_error.c_str(); }
+
+int qcheff_sync_status(void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  QC_HIP(hipStreamSynchronize(st));
+  unsigned w = 0;
+  QC_HIP(hipMemcpyFromSymbol(&w, HIP_SYMBOL(status_word), sizeof(w), 0, hipMemcpyDeviceToHost));
+  if (w) {
+    const unsigned zero = 0;
+    QC_HIP(hipMemcpyToSymbol(HIP_SYMBOL(status_word), &zero, sizeof(zero), 0, hipMemcpyHostToDevice));
+  }
+  w |= g_host_status.exchange(0);
+  if (w & STATUS_NONFINITE) return fail(QCHEFF_ENONFINITE, "a generator or its norm was not finite");
+  if (w & STATUS_ZERO_PIVOT) return fail(QCHEFF_ENONFINITE, "a Pade denominator had a zero pivot");
+  return QCHEFF_OK;
+}
 
 int qcheff_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_timing_mu);

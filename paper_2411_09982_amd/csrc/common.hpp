@@ -51,4 +51,10 @@ template <typename C2> __device__ __forceinline__ C2 czero();
 template <> __device__ __forceinline__ float2 czero<float2>() { return make_float2(0.f, 0.f); }
 template <> __device__ __forceinline__ double2 czero<double2>() { return make_double2(0.0, 0.0); }
 
+// Sticky status of the kernels on this device, read and cleared by
+// qcheff_sync_status: bit 0 a non-finite norm, bit 1 a zero pivot.
+__device__ unsigned status_word;
+enum : unsigned { STATUS_NONFINITE = 1u, STATUS_ZERO_PIVOT = 2u };
+__device__ __forceinline__ void flag_status(unsigned bits) { atomicOr(&status_word, bits); }
+
 }  // namespace qcheff

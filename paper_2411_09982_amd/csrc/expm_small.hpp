@@ -151,6 +151,7 @@ __global__ __launch_bounds__(256) void expm_small_kernel(const typename Cx<T>::t
       int s;
       if (!(nrm <= 1.7976931348623157e308)) {
         s = -1;
+        flag_status(STATUS_NONFINITE);
       } else {
         s = 0;
         while (nrm > ldexp(theta, s)) ++s;

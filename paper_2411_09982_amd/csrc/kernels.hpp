@@ -212,6 +212,7 @@ __global__ __launch_bounds__(256) void scale_kernel(const C2* __restrict__ omega
     s_ws[b] = s;
     if (s_out) s_out[b] = s;
     atomicMax(smax, s);
+    if (s == -1) flag_status(STATUS_NONFINITE);
   }
   const double f = (s >= 0) ? ldexp(1.0, -s) : __longlong_as_double(0x7ff8000000000000LL);
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < dd; e += int64_t(gridDim.x) * blockDim.x) {

@@ -95,7 +95,10 @@ __global__ __launch_bounds__(1024) void lu_panel_reg_kernel(double2* aug, int64_
 #pragma unroll
     for (int w = 1; w < T / 64; ++w) argmax_combine(v, idx, wv[w], wi[w]);
     const int p = (idx >= j && idx < nrows) ? idx : j;
-    if (tid == 0) piv[k0 + j] = k0 + p;
+    if (tid == 0) {
+      piv[k0 + j] = k0 + p;
+      if (!(v > 0.0)) flag_status(STATUS_ZERO_PIVOT);   // v is the largest |re| + |im| (NaN counts as inf)
+    }
     // one exchange through LDS: the pivot row is published (it becomes row j
     // and drives the elimination), row j goes to the pivot's owner.  Two
     // barriers per column: every read of wv, prow and orow of this column
@@ -170,7 +173,10 @@ __global__ __launch_bounds__(256) void lu_panel_kernel(double2* aug, int64_t ld,
       __syncthreads();
     }
     const int pr = (sidx[0] >= j && sidx[0] < d) ? sidx[0] : j;
-    if (tid == 0) piv[j] = pr;
+    if (tid == 0) {
+      piv[j] = pr;
+      if (!(smax[0] > 0.0)) flag_status(STATUS_ZERO_PIVOT);
+    }
     if (pr != j) {
       for (int c = k0 + tid; c < k1; c += 256) {
         const double2 t = A[int64_t(j) * ld + c];

@@ -16,7 +16,7 @@ def test_exports_every_header_symbol():
     assert set(names) == {"qcheff_magnus_coeffs", "qcheff_magnus_generators", "qcheff_expm_batched",
                           "qcheff_propagate", "qcheff_workspace_bytes", "qcheff_last_error",
                           "qcheff_timing_enable", "qcheff_timing_read", "qcheff_propagate_batched",
-                          "qcheff_propagate_action"}
+                          "qcheff_propagate_action", "qcheff_sync_status"}
     L = q.lib()
     for n in names:
         assert hasattr(L, n), n

@@ -359,3 +359,24 @@ def test_propagate_batched_parity(B, M, d, dtype):
     for b in range(B):
         ref = oracle.propagate_state(Uref[b], psi0[b])
         assert np.abs(host(x)[b] - ref).max() <= 1e-13 * M * math.sqrt(d)
+
+
+def test_sync_status_reports_nonfinite_generators():
+    # a NaN generator: the exponential marks it (s = -1, U NaN) and the device
+    # status word reports it once; a zero column pivot is reported the same way
+    q.sync_status()                                   # clear anything earlier tests left
+    for d in (8, 48):
+        om = torch.from_numpy(wl.random_skew_hermitian_batch(3, d, 2.0, config_id=d)).to(DEV)
+        om[1, 0, 0] = float("nan")
+        U, s = q.expm_batched(om, skew_hermitian=True)
+        assert s.cpu().tolist()[1] == -1 and torch.isnan(U[1]).all()
+        assert q.sync_status() == q.ENONFINITE
+        assert q.sync_status() == q.OK
+        U, s = q.expm_batched(om[::2].contiguous(), skew_hermitian=True)
+        assert q.sync_status() == q.OK
+    # the state-only path flags a non-finite generator from the host
+    om = torch.from_numpy(wl.random_skew_hermitian_batch(2, 40, 2.0, config_id=3)).to(DEV)
+    om[0, 1, 2] = float("inf")
+    x = torch.from_numpy(wl.random_state(40, 4)).to(DEV)
+    q.propagate_action(om, x)
+    assert q.sync_status() == q.ENONFINITE and q.sync_status() == q.OK
