@@ -219,7 +219,11 @@ int qcheff_propagate_batched(const void* U, int64_t B, int64_t M, int64_t d, int
  * pays off when d is large and ||Omega_n|| moderate, e.g. many short intervals).
  *
  *   omega      [M][d][d], device, dtype (QCHEFF_C128 or QCHEFF_C64): the
- *              generators as qcheff_magnus_generators writes them.
+ *              generators as qcheff_magnus_generators writes them, which are
+ *              skew-Hermitian (Omega_ji = -conj(Omega_ij)) for Hermitian H0,
+ *              H_k.  For d >= 2048 the products read the upper triangle (and
+ *              the 64 x 64 diagonal tiles) only and take the lower triangle as
+ *              its mirror; the shift and the norms read the whole matrix.
  *   x          [d] complex128, device, in: psi_0, out: psi_M (FP64 state,
  *              products accumulate in FP64).
  *   traj       optional [M+1][d] complex128: psi_0 ... psi_M.

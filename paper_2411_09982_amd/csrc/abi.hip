@@ -231,6 +231,16 @@ int bf16x3_cfg() {
   return (v && std::strcmp(v, "fragments") == 0) ? 2 : 3;
 }
 
+// Taylor-term kernel: 0 reads Omega whole (a wave per row), 1 reads its upper
+// triangle by tiles and finishes the output blocks in a second launch.  Below
+// d = 2048 the tile grid (nb (nb + 1) / 2 workgroups) does not fill the chip.
+int action_mode(int64_t d) {
+  const char* v = std::getenv("QCHEFF_ACTION_KERNEL");
+  if (v && std::strcmp(v, "rows") == 0) return 0;
+  if (v && std::strcmp(v, "tiles") == 0) return 1;
+  return d >= 2048 ? 1 : 0;
+}
+
 // ------------------------------------------------------------------- coeffs
 int run_coeffs(const double* u, int64_t K, int64_t N, double dt, int64_t M, int order, double* c1,
                double* c2, hipStream_t st) {
@@ -647,6 +657,9 @@ int run_action(const void* Ov, int64_t M, int64_t d, void* x, void* traj, double
   double2* Y = cv.take<double2>(size_t(d) * 16);
   double2* mu = cv.take<double2>(size_t(M) * 16);
   unsigned long long* norms = cv.take<unsigned long long>(size_t(M) * 16);
+  const int nb = int((d + kActTile - 1) / kActTile);
+  double2* P = cv.take<double2>(size_t(nb) * nb * kActTile * 16);
+  const int mode = action_mode(d);
   double2* F = static_cast<double2*>(x);
   double2* t = static_cast<double2*>(traj);
   if (t) QC_HIP(hipMemcpyAsync(t, F, size_t(d) * 16, hipMemcpyDeviceToDevice, st));
@@ -697,10 +710,22 @@ int run_action(const void* Ov, int64_t M, int64_t d, void* x, void* traj, double
         for (int j = 1; j <= m; ++j) {
           LaunchTimer tm;
           tm.begin(st);
-          hipLaunchKernelGGL(action_term_kernel<C2>, dim3(nblocks(d, 4)), dim3(256), 0, st, Om + n * dd, int(d), cur,
-                             nxt, F, 1.0 / (double(s) * double(j)), m_n, j == m ? 1 : 0, eta);
-          // one complex multiply-add per matrix element; the matrix is read once
-          tm.end(st, KERNEL_ACTION, 8.0 * double(dd), double(dd) * sizeof(C2) + 4.0 * 16.0 * double(d));
+          const double coef = 1.0 / (double(s) * double(j));
+          const int lst = j == m ? 1 : 0;
+          if (mode == 0) {
+            hipLaunchKernelGGL(action_term_kernel<C2>, dim3(nblocks(d, 4)), dim3(256), 0, st, Om + n * dd, int(d),
+                               cur, nxt, F, coef, m_n, lst, eta);
+          } else {
+            const unsigned tiles = unsigned(nb) * unsigned(nb + 1) / 2;
+            hipLaunchKernelGGL(action_tile_kernel<C2>, dim3(tiles), dim3(256), 0, st, Om + n * dd, int(d), nb, cur,
+                               P);
+            hipLaunchKernelGGL(action_finish_kernel, dim3(4 * unsigned(nb)), dim3(256), 0, st, int(d), nb, cur, nxt,
+                               F, P, coef, m_n, lst, eta);
+          }
+          // one complex multiply-add per matrix element; the whole matrix, or
+          // its upper triangle with the diagonal, is read once
+          const double elems = mode == 0 ? double(dd) : 0.5 * double(d) * double(d + 1);
+          tm.end(st, KERNEL_ACTION, 8.0 * double(dd), elems * sizeof(C2) + 4.0 * 16.0 * double(d));
           std::swap(cur, nxt);
         }
       }

@@ -189,6 +189,184 @@ __global__ __launch_bounds__(256) void action_term_kernel(const C2* __restrict__
   }
 }
 
+// ------------------------------------------------ half-read Taylor term
+//
+// Omega is skew-Hermitian (Omega_ji = -conj(Omega_ij), exactly so for the
+// generators of Hermitian H0, H_k), so a product needs only its upper triangle:
+// a 64 x 64 tile (I, J), I < J, gives its own rows' share y_I += Omega_IJ x_J
+// and the mirrored tile's share y_J += -Omega_IJ^dag x_I; diagonal tiles are read
+// whole.  Shares land in P[K][L][0..63] (K the output block, L the partner
+// tile), so every output block has exactly nb shares, summed in a fixed order
+// whatever order the tiles finish in (the result does not depend on
+// scheduling).  HBM traffic per product: d (d + 64) / 2 elements of
+// Omega instead of d^2.
+constexpr int kActTile = 64;
+
+// Tile t of the upper triangle, enumerated column by column: t = J (J + 1) / 2 + I.
+__device__ __forceinline__ void action_tile_of(int t, int& I, int& J) {
+  int j = int((sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
+  while (j * (j + 1) / 2 > t) --j;
+  while ((j + 1) * (j + 2) / 2 <= t) ++j;
+  J = j;
+  I = t - j * (j + 1) / 2;
+}
+
+// Finish 16 rows of output block K = blockIdx.x / 4: sum the nb shares in a
+// fixed order (sixteen strided partial sums, four independent loads in flight
+// per thread, combined in index order) and apply the term update of
+// action_term_kernel.  Grid 4 nb, 256 threads.
+__global__ __launch_bounds__(256) void action_finish_kernel(int d, int nb, const double2* __restrict__ x,
+                                                            double2* __restrict__ y, double2* __restrict__ F,
+                                                            const double2* __restrict__ P, double coef, double2 mu,
+                                                            int last, double2 eta) {
+  __shared__ double2 part[16][17];
+  const int K = blockIdx.x >> 2, sub = blockIdx.x & 3;
+  const int t = threadIdx.x & 15, p = threadIdx.x >> 4;
+  const double2* src = P + int64_t(K) * nb * kActTile + 16 * sub + t;
+  double sr = 0.0, si = 0.0;
+  int L = p;
+  for (; L + 48 < nb; L += 64) {
+    double2 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = src[int64_t(L + 16 * q) * kActTile];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sr += v[q].x;
+      si += v[q].y;
+    }
+  }
+  for (; L < nb; L += 16) {
+    const double2 v = src[int64_t(L) * kActTile];
+    sr += v.x;
+    si += v.y;
+  }
+  part[p][t] = make_double2(sr, si);
+  __syncthreads();
+  const int row = K * kActTile + 16 * sub + t;
+  if (p == 0 && row < d) {
+    sr = 0.0;
+    si = 0.0;
+#pragma unroll
+    for (int g = 0; g < 16; ++g) {
+      sr += part[g][t].x;
+      si += part[g][t].y;
+    }
+    const double2 xr = x[row];
+    sr -= mu.x * xr.x - mu.y * xr.y;
+    si -= mu.x * xr.y + mu.y * xr.x;
+    const double2 tv = make_double2(coef * sr, coef * si);
+    double2 f = F[row];
+    f.x += tv.x;
+    f.y += tv.y;
+    if (last) {
+      f = make_double2(eta.x * f.x - eta.y * f.y, eta.x * f.y + eta.y * f.x);
+      y[row] = f;
+    } else {
+      y[row] = tv;
+    }
+    F[row] = f;
+  }
+}
+
+// One tile per workgroup (grid nb (nb + 1) / 2), writing its shares; the output
+// blocks are finished by action_finish_kernel in a launch of its own (a
+// last-workgroup-finishes variant needs device-wide fences that cost more than
+// the launch).  A thread holds two adjacent columns of eight rows (rows rg,
+// rg + 8, ...), so that a half-wave reads a whole 64-element row segment.
+template <typename C2>
+__global__ __launch_bounds__(256) void action_tile_kernel(const C2* __restrict__ A, int d, int nb,
+                                                          const double2* __restrict__ x, double2* __restrict__ P) {
+  int I, J;
+  action_tile_of(int(blockIdx.x), I, J);
+  const int tid = threadIdx.x, cp = tid & 31, rg = tid >> 5;
+  const int r0 = I * kActTile, c0 = J * kActTile;
+  const bool offdiag = I != J;
+  __shared__ double2 xs[2][kActTile];
+  __shared__ double2 rowp[kActTile][33];
+  __shared__ double2 colp[8][kActTile];
+  if (tid < 64) xs[0][tid] = r0 + tid < d ? x[r0 + tid] : make_double2(0.0, 0.0);
+  else if (tid < 128) xs[1][tid - 64] = c0 + tid - 64 < d ? x[c0 + tid - 64] : make_double2(0.0, 0.0);
+  double ar[8][2], ai[8][2];
+  const bool full = r0 + kActTile <= d && c0 + kActTile <= d;
+  if (sizeof(C2) == 8 && full && (d & 1) == 0) {
+    // complex64, even d: the two elements are one aligned 16-byte load
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float4 u = *reinterpret_cast<const float4*>(A + int64_t(r0 + rg + 8 * k) * d + c0 + 2 * cp);
+      ar[k][0] = u.x;
+      ai[k][0] = u.y;
+      ar[k][1] = u.z;
+      ai[k][1] = u.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int row = r0 + rg + 8 * k;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int col = c0 + 2 * cp + e;
+        C2 v;
+        v.x = 0;
+        v.y = 0;
+        if (full || (row < d && col < d)) v = A[int64_t(row) * d + col];
+        ar[k][e] = double(v.x);
+        ai[k][e] = double(v.y);
+      }
+    }
+  }
+  __syncthreads();
+  double2 xc[2] = {xs[1][2 * cp], xs[1][2 * cp + 1]};
+  double csr[2] = {0.0, 0.0}, csi[2] = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      sr += ar[k][e] * xc[e].x - ai[k][e] * xc[e].y;
+      si += ar[k][e] * xc[e].y + ai[k][e] * xc[e].x;
+    }
+    rowp[rg + 8 * k][cp] = make_double2(sr, si);
+    if (offdiag) {
+      // -conj(a) x_I[row]
+      const double2 xr = xs[0][rg + 8 * k];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        csr[e] += -ar[k][e] * xr.x - ai[k][e] * xr.y;
+        csi[e] += ai[k][e] * xr.x - ar[k][e] * xr.y;
+      }
+    }
+  }
+  if (offdiag) {
+    colp[rg][2 * cp] = make_double2(csr[0], csi[0]);
+    colp[rg][2 * cp + 1] = make_double2(csr[1], csi[1]);
+  }
+  __syncthreads();
+  {
+    // row shares: four threads per row, eight entries each, then two butterfly steps
+    const int row = tid >> 2, qq = tid & 3;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      sr += rowp[row][8 * qq + i].x;
+      si += rowp[row][8 * qq + i].y;
+    }
+    sr += __shfl_xor(sr, 1);
+    si += __shfl_xor(si, 1);
+    sr += __shfl_xor(sr, 2);
+    si += __shfl_xor(si, 2);
+    if (qq == 0) P[(int64_t(I) * nb + J) * kActTile + row] = make_double2(sr, si);
+  }
+  if (offdiag && tid < 64) {
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      sr += colp[g][tid].x;
+      si += colp[g][tid].y;
+    }
+    P[(int64_t(J) * nb + I) * kActTile + tid] = make_double2(sr, si);
+  }
+}
+
 // x <- eta x (a step with no Taylor term: Omega = mu I exactly, or a
 // non-finite generator, eta = NaN).
 __global__ __launch_bounds__(256) void scale_state_kernel(double2* __restrict__ x, int d, double2 eta) {

@@ -143,8 +143,11 @@ Check check_propagate_batched(const void* U, int64_t B, int64_t M, int64_t d, in
 
 size_t action_ws_bytes(int64_t M, int64_t d) {
   if (M < 0 || d < 1) return 0;
-  // two term vectors, the per-interval shift and the two norms per interval
-  return 2 * align256(size_t(d) * 16) + align256(size_t(M) * 16) + align256(size_t(M) * 16);
+  // two term vectors, the per-interval shift and the two norms per interval;
+  // the 64-row shares of the tiled product ([nb][nb][64] complex128)
+  const size_t nb = size_t((d + 63) / 64);
+  return 2 * align256(size_t(d) * 16) + align256(size_t(M) * 16) + align256(size_t(M) * 16) +
+         align256(nb * nb * 64 * 16);
 }
 
 Check check_action(const void* omega, int64_t M, int64_t d, int dtype, const void* x, double tol, const void* ws,

@@ -118,9 +118,10 @@ def test_propagate_action_validation():
     L = q.lib()
     a = L.qcheff_propagate_action
     need = q.workspace_bytes(q.FN_ACTION, 3, 10, 1, 1, q.C64)
-    # two term vectors, the shifts and the norms, each on a 256-byte boundary
-    assert need == 2 * 256 + 256 + 256
-    assert q.workspace_bytes(q.FN_ACTION, 1000, 4096, 1, 1, q.C128) == 2 * 65536 + 2 * 16128
+    # two term vectors, the shifts, the norms and the tile shares, each on a
+    # 256-byte boundary
+    assert need == 2 * 256 + 256 + 256 + 1024
+    assert q.workspace_bytes(q.FN_ACTION, 1000, 4096, 1, 1, q.C128) == 2 * 65536 + 2 * 16128 + 64 * 64 * 64 * 16
     assert q.workspace_bytes(q.FN_ACTION, 3, 10, 1, 1, 9) == 0
     assert a(FAKE, -1, 10, q.C64, FAKE, None, 0.0, FAKE, need, None) == q.EINVAL
     assert a(FAKE, 3, 0, q.C64, FAKE, None, 0.0, FAKE, need, None) == q.EINVAL

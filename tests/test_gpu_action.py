@@ -20,12 +20,19 @@ def _oracle_chain(Om, psi0):
     return oracle.propagate_state(U, psi0, trajectory=True)
 
 
+# the Taylor-term kernels: the whole matrix by rows, or its upper triangle by
+# 64 x 64 tiles; below d = 2048 the library picks "rows" by itself
+KERNELS = ["rows", "tiles"]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 @pytest.mark.parametrize("d", [1, 3, 17, 64, 130, 300])
-def test_action_parity(d, dtype):
+def test_action_parity(d, dtype, kernel, monkeypatch):
     # norms from 0 (a pure phase after the shift) to one needing many steps; one
     # generator with a large mean diagonal (the shift takes it out)
-    say(f"action d={d} {dtype}")
+    monkeypatch.setenv("QCHEFF_ACTION_KERNEL", kernel)
+    say(f"action d={d} {dtype} {kernel}")
     norms = [0.0, 0.3, 5.0, 60.0, 400.0]
     Om = wl.random_skew_hermitian_batch(len(norms), d, norms, config_id=600 + d)
     Om[2] += -1j * 37.0 * np.eye(d)
@@ -80,3 +87,24 @@ def test_evolve_state_matches_propagator_path(dtype):
     else:
         assert abs(float(oracle.state_infidelity(ref, a))) <= 1e-6
         assert oracle.norm_error(a) <= w.M * 2.0 ** -24 * 8
+
+
+@pytest.mark.parametrize("kernel", ["rows", "tiles"])
+def test_action_tiles_large_ragged(kernel, monkeypatch):
+    # d = 2100: 33 tile rows with a ragged last one, the size range where the
+    # library reads the upper triangle by itself; against the oracle, and a
+    # second run bit-identical (the shares of a block are summed in a fixed order)
+    monkeypatch.setenv("QCHEFF_ACTION_KERNEL", kernel)
+    d = 2100
+    say(f"action d={d} {kernel}")
+    Om = wl.random_skew_hermitian_batch(2, d, [3.0, 40.0], config_id=2100)
+    psi0 = wl.random_state(d, 21)
+    ref, _ = _oracle_chain(Om, psi0)
+    out = []
+    for _ in range(2):
+        x = gpu(psi0)
+        q.propagate_action(gpu(Om), x)
+        torch.cuda.synchronize()
+        out.append(host(x))
+    assert np.abs(out[0] - ref).max() <= 1e-12
+    assert np.array_equal(out[0], out[1])
