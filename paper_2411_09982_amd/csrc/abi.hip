@@ -668,8 +668,18 @@ int run_action(const void* Ov, int64_t M, int64_t d, void* x, void* traj, double
   hipLaunchKernelGGL(fill_u32_kernel, dim3(nblocks(4 * M, 256)), dim3(256), 0, st,
                      reinterpret_cast<uint32_t*>(norms), 4 * M, 0u);
   hipLaunchKernelGGL(trace_mean_kernel<C2>, dim3(unsigned(M)), dim3(256), 0, st, Om, int(d), mu);
-  hipLaunchKernelGGL(shifted_norms_kernel<C2>, dim3(nblocks(d, 256), unsigned(M), 2), dim3(256), 0, st, Om, int(d),
-                     mu, norms);
+  // the tiled product already takes Omega as skew-Hermitian: then one row pass
+  // gives both norms; otherwise columns and rows.  Items in slices of the
+  // grid's y limit.
+  for (int64_t b0 = 0; b0 < M; b0 += 65535) {
+    const unsigned nbt = unsigned(std::min<int64_t>(65535, M - b0));
+    if (mode == 1)
+      hipLaunchKernelGGL(shifted_rownorm_kernel<C2>, dim3(nblocks(d, 4), nbt), dim3(256), 0, st, Om, int(d), b0, mu,
+                         norms);
+    else
+      hipLaunchKernelGGL(shifted_norms_kernel<C2>, dim3(nblocks(d, 256), nbt, 2), dim3(256), 0, st, Om, int(d), b0,
+                         mu, norms);
+  }
   QC_HIP(hipGetLastError());
   // the host sizes every interval's launches from the shift and the norms
   std::vector<double2> mu_h(static_cast<size_t>(M));
@@ -682,6 +692,7 @@ int run_action(const void* Ov, int64_t M, int64_t d, void* x, void* traj, double
     double n1, ninf;
     std::memcpy(&n1, &nb_h[2 * n], 8);
     std::memcpy(&ninf, &nb_h[2 * n + 1], 8);
+    if (mode == 1) n1 = ninf;                 // equal for a skew-Hermitian matrix
     const double nu = std::sqrt(n1 * ninf);   // ||.||_2 <= sqrt(||.||_1 ||.||_inf)
     const double2 m_n = mu_h[n];
     int m = 0;

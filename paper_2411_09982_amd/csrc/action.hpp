@@ -53,16 +53,16 @@ __device__ __forceinline__ void nan_max(double& a, double o) {
   if (o > a || o != o) a = o;   // NaN wins
 }
 
-// norms[2 b] = max column sum, norms[2 b + 1] = max row sum of |Omega_b - mu_b I|,
-// as IEEE bits under an atomic max (monotone for non-negative values, NaN the
-// largest pattern).  Grid (ceil(d / 256), batch, 2): z = 0 columns, z = 1 rows
-// (a wave per row, so that the reads are coalesced).
+// norms[2 b] = max column sum, norms[2 b + 1] = max row sum of |Omega_b - mu_b I|
+// for b = b0 + blockIdx.y, as IEEE bits under an atomic max (monotone for
+// non-negative values, NaN the largest pattern).  Grid (ceil(d / 256), items,
+// 2): z = 0 columns, z = 1 rows (a wave per row, so that the reads are coalesced).
 template <typename C2>
-__global__ __launch_bounds__(256) void shifted_norms_kernel(const C2* __restrict__ X, int d,
+__global__ __launch_bounds__(256) void shifted_norms_kernel(const C2* __restrict__ X, int d, int64_t b0,
                                                             const double2* __restrict__ mu,
                                                             unsigned long long* __restrict__ norms) {
-  const int b = blockIdx.y;
-  const C2* A = X + int64_t(b) * d * d;
+  const int64_t b = b0 + blockIdx.y;
+  const C2* A = X + b * d * d;
   const double2 m = mu[b];
   double best = 0.0;
   if (blockIdx.z == 0) {
@@ -96,6 +96,47 @@ __global__ __launch_bounds__(256) void shifted_norms_kernel(const C2* __restrict
     __syncthreads();
   }
   if (threadIdx.x == 0) atomicMax(norms + 2 * b + blockIdx.z, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+// norms[2 (b0 + b) + 1] = max row sum of |Omega - mu I| for item b0 + b
+// (IEEE bits, atomic max).  A wave per row, eight loads in flight per lane;
+// grid (ceil(d / 4), items).  For a skew-Hermitian matrix the max row sum is
+// also the max column sum, so this one pass gives the 1-norm as well.
+template <typename C2>
+__global__ __launch_bounds__(256) void shifted_rownorm_kernel(const C2* __restrict__ X, int d, int64_t b0,
+                                                              const double2* __restrict__ mu,
+                                                              unsigned long long* __restrict__ norms) {
+  const int64_t b = b0 + blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + wave;
+  const double2 m = mu[b];
+  double sum = 0.0;
+  if (r < d) {
+    const C2* ar = X + b * d * d + int64_t(r) * d;
+    int c = lane;
+    for (; c + 448 < d; c += 512) {
+      C2 u[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) u[q] = ar[c + 64 * q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sum += shifted_abs(double(u[q].x), double(u[q].y), r == c + 64 * q, m);
+    }
+    for (; c < d; c += 64) {
+      const C2 u = ar[c];
+      sum += shifted_abs(double(u.x), double(u.y), r == c, m);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+  __shared__ double red[4];
+  if (lane == 0) red[wave] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double best = red[0];
+    nan_max(best, red[1]);
+    nan_max(best, red[2]);
+    nan_max(best, red[3]);
+    atomicMax(norms + 2 * b + 1, (unsigned long long)__double_as_longlong(best));
+  }
 }
 
 // One Taylor term: y = coef (A - mu I) x, F += y; on the last term of a step
@@ -282,10 +323,8 @@ __global__ __launch_bounds__(256) void action_tile_kernel(const C2* __restrict__
   const int r0 = I * kActTile, c0 = J * kActTile;
   const bool offdiag = I != J;
   __shared__ double2 xs[2][kActTile];
-  __shared__ double2 rowp[kActTile][33];
-  __shared__ double2 colp[8][kActTile];
-  if (tid < 64) xs[0][tid] = r0 + tid < d ? x[r0 + tid] : make_double2(0.0, 0.0);
-  else if (tid < 128) xs[1][tid - 64] = c0 + tid - 64 < d ? x[c0 + tid - 64] : make_double2(0.0, 0.0);
+  __shared__ double2 colp[4][kActTile];
+  // the tile's loads go out first; x comes from L2 meanwhile
   double ar[8][2], ai[8][2];
   const bool full = r0 + kActTile <= d && c0 + kActTile <= d;
   if (sizeof(C2) == 8 && full && (d & 1) == 0) {
@@ -314,18 +353,21 @@ __global__ __launch_bounds__(256) void action_tile_kernel(const C2* __restrict__
       }
     }
   }
+  if (tid < 64) xs[0][tid] = r0 + tid < d ? x[r0 + tid] : make_double2(0.0, 0.0);
+  else if (tid < 128) xs[1][tid - 64] = c0 + tid - 64 < d ? x[c0 + tid - 64] : make_double2(0.0, 0.0);
   __syncthreads();
-  double2 xc[2] = {xs[1][2 * cp], xs[1][2 * cp + 1]};
+  const double2 xc[2] = {xs[1][2 * cp], xs[1][2 * cp + 1]};
+  double vr[8], vi[8];
   double csr[2] = {0.0, 0.0}, csi[2] = {0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    double sr = 0.0, si = 0.0;
+    vr[k] = 0.0;
+    vi[k] = 0.0;
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      sr += ar[k][e] * xc[e].x - ai[k][e] * xc[e].y;
-      si += ar[k][e] * xc[e].y + ai[k][e] * xc[e].x;
+      vr[k] += ar[k][e] * xc[e].x - ai[k][e] * xc[e].y;
+      vi[k] += ar[k][e] * xc[e].y + ai[k][e] * xc[e].x;
     }
-    rowp[rg + 8 * k][cp] = make_double2(sr, si);
     if (offdiag) {
       // -conj(a) x_I[row]
       const double2 xr = xs[0][rg + 8 * k];
@@ -336,34 +378,63 @@ __global__ __launch_bounds__(256) void action_tile_kernel(const C2* __restrict__
       }
     }
   }
-  if (offdiag) {
-    colp[rg][2 * cp] = make_double2(csr[0], csi[0]);
-    colp[rg][2 * cp + 1] = make_double2(csr[1], csi[1]);
-  }
-  __syncthreads();
+  // Row shares: the 32 lanes of a half-wave hold the same eight rows.  Recursive
+  // halving over lane bits 4, 3, 2 (each lane keeps half of its rows and adds
+  // its partner's half), then bits 1 and 0: lane 4 i of the half-wave ends with
+  // the sum for row rg + 8 (4 b4 + 2 b3 + b2).
+  const int lane = tid & 63;
   {
-    // row shares: four threads per row, eight entries each, then two butterfly steps
-    const int row = tid >> 2, qq = tid & 3;
-    double sr = 0.0, si = 0.0;
+    const bool b = lane & 16;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      sr += rowp[row][8 * qq + i].x;
-      si += rowp[row][8 * qq + i].y;
+    for (int i = 0; i < 4; ++i) {
+      const double sr = b ? vr[i] : vr[4 + i], si = b ? vi[i] : vi[4 + i];
+      const double kr = b ? vr[4 + i] : vr[i], ki = b ? vi[4 + i] : vi[i];
+      vr[i] = kr + __shfl_xor(sr, 16);
+      vi[i] = ki + __shfl_xor(si, 16);
     }
-    sr += __shfl_xor(sr, 1);
-    si += __shfl_xor(si, 1);
-    sr += __shfl_xor(sr, 2);
-    si += __shfl_xor(si, 2);
-    if (qq == 0) P[(int64_t(I) * nb + J) * kActTile + row] = make_double2(sr, si);
   }
-  if (offdiag && tid < 64) {
-    double sr = 0.0, si = 0.0;
+  {
+    const bool b = lane & 8;
 #pragma unroll
-    for (int g = 0; g < 8; ++g) {
-      sr += colp[g][tid].x;
-      si += colp[g][tid].y;
+    for (int i = 0; i < 2; ++i) {
+      const double sr = b ? vr[i] : vr[2 + i], si = b ? vi[i] : vi[2 + i];
+      const double kr = b ? vr[2 + i] : vr[i], ki = b ? vi[2 + i] : vi[i];
+      vr[i] = kr + __shfl_xor(sr, 8);
+      vi[i] = ki + __shfl_xor(si, 8);
     }
-    P[(int64_t(J) * nb + I) * kActTile + tid] = make_double2(sr, si);
+  }
+  {
+    const bool b = lane & 4;
+    const double sr = b ? vr[0] : vr[1], si = b ? vi[0] : vi[1];
+    const double kr = b ? vr[1] : vr[0], ki = b ? vi[1] : vi[0];
+    vr[0] = kr + __shfl_xor(sr, 4);
+    vi[0] = ki + __shfl_xor(si, 4);
+  }
+  vr[0] += __shfl_xor(vr[0], 2);
+  vi[0] += __shfl_xor(vi[0], 2);
+  vr[0] += __shfl_xor(vr[0], 1);
+  vi[0] += __shfl_xor(vi[0], 1);
+  if ((lane & 3) == 0) {
+    const int k = ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+    P[(int64_t(I) * nb + J) * kActTile + rg + 8 * k] = make_double2(vr[0], vi[0]);
+  }
+  if (offdiag) {
+    // column shares: the two half-waves of a wave, then the four waves in LDS
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      csr[e] += __shfl_xor(csr[e], 32);
+      csi[e] += __shfl_xor(csi[e], 32);
+    }
+    if (lane < 32) {
+      colp[tid >> 6][2 * cp] = make_double2(csr[0], csi[0]);
+      colp[tid >> 6][2 * cp + 1] = make_double2(csr[1], csi[1]);
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const double sr = ((colp[0][tid].x + colp[1][tid].x) + colp[2][tid].x) + colp[3][tid].x;
+      const double si = ((colp[0][tid].y + colp[1][tid].y) + colp[2][tid].y) + colp[3][tid].y;
+      P[(int64_t(J) * nb + I) * kActTile + tid] = make_double2(sr, si);
+    }
   }
 }
 
