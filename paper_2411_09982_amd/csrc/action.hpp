@@ -264,6 +264,14 @@ __global__ __launch_bounds__(256) void action_finish_kernel(int d, int nb, const
   const int K = blockIdx.x >> 2, sub = blockIdx.x & 3;
   const int t = threadIdx.x & 15, p = threadIdx.x >> 4;
   const double2* src = P + int64_t(K) * nb * kActTile + 16 * sub + t;
+  const int row = K * kActTile + 16 * sub + t;
+  // the state rows go out with the shares (one round trip, not two)
+  const bool upd = p == 0 && row < d;
+  double2 xr = make_double2(0.0, 0.0), f = make_double2(0.0, 0.0);
+  if (upd) {
+    xr = x[row];
+    f = F[row];
+  }
   double sr = 0.0, si = 0.0;
   int L = p;
   for (; L + 48 < nb; L += 64) {
@@ -283,8 +291,7 @@ __global__ __launch_bounds__(256) void action_finish_kernel(int d, int nb, const
   }
   part[p][t] = make_double2(sr, si);
   __syncthreads();
-  const int row = K * kActTile + 16 * sub + t;
-  if (p == 0 && row < d) {
+  if (upd) {
     sr = 0.0;
     si = 0.0;
 #pragma unroll
@@ -292,11 +299,9 @@ __global__ __launch_bounds__(256) void action_finish_kernel(int d, int nb, const
       sr += part[g][t].x;
       si += part[g][t].y;
     }
-    const double2 xr = x[row];
     sr -= mu.x * xr.x - mu.y * xr.y;
     si -= mu.x * xr.y + mu.y * xr.x;
     const double2 tv = make_double2(coef * sr, coef * si);
-    double2 f = F[row];
     f.x += tv.x;
     f.y += tv.y;
     if (last) {
@@ -324,18 +329,20 @@ __global__ __launch_bounds__(256) void action_tile_kernel(const C2* __restrict__
   const bool offdiag = I != J;
   __shared__ double2 xs[2][kActTile];
   __shared__ double2 colp[4][kActTile];
-  // the tile's loads go out first; x comes from L2 meanwhile
-  double ar[8][2], ai[8][2];
+  // the tile's loads go out first (kept in the storage type until the
+  // arithmetic); x comes from L2 meanwhile
+  using R = decltype(C2::x);
+  R rar[8][2], rai[8][2];
   const bool full = r0 + kActTile <= d && c0 + kActTile <= d;
   if (sizeof(C2) == 8 && full && (d & 1) == 0) {
     // complex64, even d: the two elements are one aligned 16-byte load
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const float4 u = *reinterpret_cast<const float4*>(A + int64_t(r0 + rg + 8 * k) * d + c0 + 2 * cp);
-      ar[k][0] = u.x;
-      ai[k][0] = u.y;
-      ar[k][1] = u.z;
-      ai[k][1] = u.w;
+      rar[k][0] = u.x;
+      rai[k][0] = u.y;
+      rar[k][1] = u.z;
+      rai[k][1] = u.w;
     }
   } else {
 #pragma unroll
@@ -348,14 +355,22 @@ __global__ __launch_bounds__(256) void action_tile_kernel(const C2* __restrict__
         v.x = 0;
         v.y = 0;
         if (full || (row < d && col < d)) v = A[int64_t(row) * d + col];
-        ar[k][e] = double(v.x);
-        ai[k][e] = double(v.y);
+        rar[k][e] = v.x;
+        rai[k][e] = v.y;
       }
     }
   }
   if (tid < 64) xs[0][tid] = r0 + tid < d ? x[r0 + tid] : make_double2(0.0, 0.0);
   else if (tid < 128) xs[1][tid - 64] = c0 + tid - 64 < d ? x[c0 + tid - 64] : make_double2(0.0, 0.0);
   __syncthreads();
+  double ar[8][2], ai[8][2];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      ar[k][e] = double(rar[k][e]);
+      ai[k][e] = double(rai[k][e]);
+    }
   const double2 xc[2] = {xs[1][2 * cp], xs[1][2 * cp + 1]};
   double vr[8], vi[8];
   double csr[2] = {0.0, 0.0}, csi[2] = {0.0, 0.0};
