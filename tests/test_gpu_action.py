@@ -108,3 +108,19 @@ def test_action_tiles_large_ragged(kernel, monkeypatch):
         out.append(host(x))
     assert np.abs(out[0] - ref).max() <= 1e-12
     assert np.array_equal(out[0], out[1])
+
+
+def test_action_more_intervals_than_grid_rows():
+    # M = 70000 generators (d = 3): the shift and norm launches take the items in
+    # slices of the grid's 65535-row limit; the chain against the oracle's
+    M, d = 70000, 3
+    say(f"action M={M} d={d}")
+    g = np.random.default_rng(70000)
+    A = g.standard_normal((M, d, d)) + 1j * g.standard_normal((M, d, d))
+    Om = 0.15 * (A - np.conj(np.swapaxes(A, -1, -2)))    # exactly skew-Hermitian
+    psi0 = wl.random_state(d, 7)
+    ref = oracle.propagate_state(oracle.expm_skew_hermitian(Om), psi0)
+    x = gpu(psi0)
+    q.propagate_action(gpu(Om), x)
+    torch.cuda.synchronize()
+    assert np.abs(host(x) - ref).max() <= 1e-9
