@@ -231,7 +231,9 @@ def propagate_batched(U, x, stream=None):
 
 def propagate_action(omega, x, traj=None, tol: float = 0.0, ws=None, stream=None):
     """psi <- exp(omega[M-1]) ... exp(omega[0]) psi by the truncated Taylor action
-    (qcheff_propagate_action); omega [M][d][d] generators, x [d] complex128 in place."""
+    (qcheff_propagate_action); omega [M][d][d] generators, x [d] complex128 in place.
+    The generators are taken as skew-Hermitian: from d = 2048 the products read
+    only their upper triangle (QCHEFF_ACTION_KERNEL=rows|tiles overrides)."""
     _dev(omega, "omega")
     _dev(x, "x")
     M, d = omega.shape[0], omega.shape[-1]
