@@ -7,11 +7,13 @@ One step = one pass of the whole path over one job, inputs resident in HBM:
   chunk's exponentials on a second stream).
 Metric: interval propagators per second (M / step time).
 
-Prints ONE JSON line.  Default workload: transmon (10 levels) x resonator
-(100 levels), d = 1000, two drives, 1e5 samples, M = 1000 intervals, second
-order, complex64 products on MFMA with FP64 norm / scaling / Pade solve.
+Prints ONE JSON line.  Default workload: the 10-spin chain of Sec. 4.3, d = 1024,
+two global controls, 1e4 samples, M = 200 intervals, second order, complex64
+products on MFMA with FP64 norm / scaling / Pade solve and an FP64-Gram unitary
+refinement of every propagator.  The transmon x resonator job (d = 1000,
+M = 1000) runs as a second figure in `extra` (--workload picks the headline job).
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME] [--dtype c64|c128]
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--dtype c64|c128|bf16x3]
 """
 from __future__ import annotations
 
@@ -31,19 +33,21 @@ MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6, "bf16x3": 2500.0}
 # BF16 MFMA flops executed per algorithmic flop of a split-BF16 product: each real
 # product is six BF16 part products
 BF16X3_PARTS = 6
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cgemm_f32_traffic_transmon_resonator_d1000.md")
 GEMM_SOURCE = os.path.join(ROOT, "paper_2411_09982_amd", "csrc", "cgemm.hpp")
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
 
 
-TRAFFIC_WORKLOAD = "transmon10x_resonator100_d1000"   # the job the committed counters were taken on
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"cgemm_f32_traffic_{workload}.md")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the FP32 GEMM kernel from the committed rocprofv3 --pmc
-    summary, or None when the kernel source has changed since it was measured."""
+def measured_traffic(workload):
+    """HBM bytes per launch of the FP32 GEMM kernel on `workload` from the committed
+    rocprofv3 --pmc summary, or None when there is none or the kernel source has
+    changed since it was measured."""
     import hashlib
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(traffic_file(workload)).read()
     except OSError:
         return None
     sha = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
@@ -61,7 +65,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="transmon10x_resonator100_d1000")
+    ap.add_argument("--workload", default="spin_chain_10_d1024")
+    ap.add_argument("--second-workload", default="transmon10x_resonator100_d1000",
+                    help="a second job timed after the headline one and reported in extra ('' for none)")
+    ap.add_argument("--no-refine", action="store_true",
+                    help="FP32-product tiers without the unitary refinement of the propagators")
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128", "bf16x3"],
                     help="c64: FP32 MFMA products; bf16x3: the same complex64 path with the products on BF16 "
                          "MFMA (three-way split operands); c128: FP64 throughout")
@@ -117,10 +125,12 @@ def build_workload(name):
 class Job:
     """Device-resident inputs and preallocated buffers for one workload."""
 
-    def __init__(self, w, dtype_name, chunk, lanes=1):
+    def __init__(self, w, dtype_name, chunk, lanes=1, refine=True):
         import torch
         import paper_2411_09982_amd as q
         self.q, self.torch, self.w = q, torch, w
+        # the FP32-product tiers refine each propagator to unitarity after its squarings
+        self.refine = bool(refine) and dtype_name != "c128"
         dev = "cuda:0"
         self.dtype = torch.complex128 if dtype_name == "c128" else torch.complex64
         self.bf16x3 = dtype_name == "bf16x3"
@@ -166,7 +176,7 @@ class Job:
                 c1 = min(w.M, c0 + self.chunk)
                 U = self.omega[c0:c1]
                 q.expm_batched(U, U=U, s_out=self.s[c0:c1], ws=self.exp_ws[0], skew_hermitian=True,
-                               bf16x3=self.bf16x3)
+                               bf16x3=self.bf16x3, unitary_refine=self.refine)
                 ev = torch.cuda.Event()
                 ev.record(main)
                 self.side.wait_event(ev)
@@ -184,7 +194,7 @@ class Job:
             st.wait_event(ready)
             U = self.omega[c0:c1]
             q.expm_batched(U, U=U, s_out=self.s[c0:c1], ws=self.exp_ws[lane], skew_hermitian=True,
-                           bf16x3=self.bf16x3, stream=st)
+                           bf16x3=self.bf16x3, unitary_refine=self.refine, stream=st)
             ev = torch.cuda.Event()
             ev.record(st)
             return ev
@@ -403,6 +413,56 @@ def action(a):
                           data="synthetic", **out)), flush=True)
 
 
+def golden_state(workload):
+    """psi_M of the oracle's whole chain for `workload` (tests/golden/), or None."""
+    path = os.path.join(GOLDEN_DIR, f"{workload}_chain.npz")
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as g:
+        return g["psi_at"][-1]
+
+
+def state_errors(ref, psi):
+    """The final-state error of Sec. 4.3, 1 - |<ref|psi>|^2 (unnormalised), its
+    direction part (norms divided out) and the norm error."""
+    ov = abs(np.vdot(ref, psi)) ** 2
+    return dict(state_error=float(1.0 - ov),
+                direction_error=float(1.0 - ov / (np.vdot(ref, ref).real * np.vdot(psi, psi).real)),
+                norm_minus_1=float(np.linalg.norm(psi) - 1.0))
+
+
+def gemm_rates(kern, steps):
+    return dict(
+        fp32_gemm=dict(launches=kern["f32"]["launches"], ms_per_step=round(kern["f32"]["ms"] / steps, 2),
+                       tflops=round(kern["f32"]["flops"] / max(kern["f32"]["ms"], 1e-9) * 1e-9, 2)),
+        fp64_gemm=dict(launches=kern["f64"]["launches"], ms_per_step=round(kern["f64"]["ms"] / steps, 2),
+                       tflops=round(kern["f64"]["flops"] / max(kern["f64"]["ms"], 1e-9) * 1e-9, 2)),
+        bf16x3_gemm=dict(launches=kern["bf16x3"]["launches"], ms_per_step=round(kern["bf16x3"]["ms"] / steps, 2),
+                         algorithmic_tflops=round(kern["bf16x3"]["flops"] / max(kern["bf16x3"]["ms"], 1e-9) * 1e-9,
+                                                  2)))
+
+
+def job_figure(w, dtype_name, steps, warmup, refine=True, roofline=True):
+    """Time `steps` steps of one job; its rate, GEMM rates and final-state errors."""
+    import torch
+    job = Job(w, dtype_name, DEFAULT_CHUNK[dtype_name], refine=refine)
+    elapsed, times, kern = timed(job, steps, warmup, roofline=roofline)
+    out = dict(value=round(w.M * steps / elapsed, 2), ms_per_step=round(1000 * elapsed / steps, 2))
+    if roofline:
+        out.update(gemm_rates(kern, steps))
+    ref = golden_state(w_name(w))
+    if ref is not None:
+        out.update(state_errors(ref, job.psi.cpu().numpy()))
+    del job
+    torch.cuda.empty_cache()
+    return out
+
+
+def w_name(w):
+    return {"spin_chain_10": "spin_chain_10_d1024",
+            "transmon10x_resonator100": "transmon10x_resonator100_d1000"}.get(w.name, w.name)
+
+
 def main():
     a = parse()
     if a.action:
@@ -426,7 +486,8 @@ def main():
     q.lib()
     w = build_workload(a.workload)
     chunk = a.chunk or DEFAULT_CHUNK[a.dtype]
-    job = Job(w, a.dtype, chunk, a.lanes)
+    refine = not a.no_refine
+    job = Job(w, a.dtype, chunk, a.lanes, refine=refine)
     elapsed, times, kern = timed(job, a.steps, a.warmup)
     s_hist = job.s.cpu().numpy().tolist()
     value = w.M * a.steps / elapsed
@@ -438,13 +499,13 @@ def main():
     achieved = executed * k["flops"] / (k["ms"] * 1e-3) / 1e12 if k["ms"] > 0 else 0.0
     peak = MFMA_PEAK_TFLOPS[a.dtype]
     # HBM bytes per launch as counted for this exact job and launch configuration
-    traffic = (measured_traffic() if a.dtype == "c64" and a.workload == TRAFFIC_WORKLOAD
-               and job.chunk == DEFAULT_CHUNK["c64"] and job.lanes == 1 else None)
+    traffic = (measured_traffic(a.workload) if a.dtype == "c64" and job.chunk == min(DEFAULT_CHUNK["c64"], w.M)
+               and job.lanes == 1 and refine else None)
     roof = dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
                 frac=round(achieved / peak, 4), traffic=traffic,
-                kernel={"c64": "cgemm_kernel<float,...> (Pade products, squarings)",
-                        "bf16x3": "cgemm_bf16x3_planes_kernel (Pade products, squarings; BF16 MFMA flops "
-                                  "executed, 6 per algorithmic flop)",
+                kernel={"c64": "cgemm_kernel<float,...> (Pade products, squarings, unitary refinement)",
+                        "bf16x3": "cgemm_bf16x3_planes_kernel (Pade products, squarings, unitary refinement; "
+                                  "BF16 MFMA flops executed, 6 per algorithmic flop)",
                         "c128": "cgemm_kernel<double,...> (Pade products, squarings, LU updates)"}[a.dtype],
                 launches=k["launches"], avg_launch_ms=round(k["ms"] / max(k["launches"], 1), 4),
                 flops_per_launch=executed * k["flops"] / max(k["launches"], 1))
@@ -459,37 +520,37 @@ def main():
         step_ms_p50=round(1000 * float(np.percentile(times, 50)), 2),
         step_ms_p99=round(1000 * float(np.percentile(times, 99)), 2),
         s_hist={str(v): s_hist.count(v) for v in sorted(set(s_hist))},
-        fp64_gemm=dict(launches=kern["f64"]["launches"], ms_per_step=round(kern["f64"]["ms"] / a.steps, 2),
-                       tflops=round(kern["f64"]["flops"] / max(kern["f64"]["ms"], 1e-9) * 1e-9, 2)),
-        fp32_gemm=dict(launches=kern["f32"]["launches"], ms_per_step=round(kern["f32"]["ms"] / a.steps, 2)),
-        bf16x3_gemm=dict(launches=kern["bf16x3"]["launches"], ms_per_step=round(kern["bf16x3"]["ms"] / a.steps, 2),
-                         algorithmic_tflops=round(kern["bf16x3"]["flops"] / max(kern["bf16x3"]["ms"], 1e-9) * 1e-9,
-                                                  2)),
         chunk=job.chunk,
         lanes=job.lanes,
+        unitary_refine=job.refine,
     )
+    extra.update(gemm_rates(kern, a.steps))
     psi_mixed = job.psi.cpu().numpy()
     U_samples = {n: job.omega[n].cpu().numpy().astype(np.complex128) for n in (0, w.M // 2, w.M - 1)}
     del job
     torch.cuda.empty_cache()
+    ref = golden_state(a.workload)
+    if ref is not None:
+        # the whole chain against the oracle's (tests/golden/), in Sec. 4.3's error
+        extra["final_state_vs_oracle"] = state_errors(ref, psi_mixed)
 
     if a.dtype in ("c64", "bf16x3") and not a.no_fp64_compare:
-        job64 = Job(w, "c128", DEFAULT_CHUNK["c128"])
-        el64, _, _ = timed(job64, 1, 1, roofline=False)
-        v64 = w.M / el64
-        psi64 = job64.psi.cpu().numpy()
-        extra["fp64_plain"] = dict(value=round(v64, 2), ms_per_step=round(1000 * el64, 1),
-                                   mixed_speedup=round(value / v64, 3),
-                                   # direction (norms divided out) and norm separately: the
-                                   # FP32 squarings leave a small radial error that accumulates
-                                   # coherently along the chain
-                                   state_infidelity_fp32_vs_fp64=float(
-                                       1 - abs(np.vdot(psi64, psi_mixed)) ** 2
-                                       / (np.vdot(psi64, psi64).real * np.vdot(psi_mixed, psi_mixed).real)),
-                                   state_norm_fp32_minus_1=float(np.linalg.norm(psi_mixed) - 1),
-                                   state_norm_fp64_minus_1=float(np.linalg.norm(psi64) - 1))
-        del job64
-        torch.cuda.empty_cache()
+        f64 = job_figure(w, "c128", 1, 1, roofline=False)
+        f64["mixed_speedup"] = round(value / f64["value"], 3)
+        extra["fp64_plain"] = f64
+        if refine:
+            # the same tier without the unitary refinement: what it costs and buys
+            unref = job_figure(w, a.dtype, 2, 1, refine=False, roofline=False)
+            extra["fp32_unrefined"] = unref
+
+    if a.second_workload and a.second_workload != a.workload:
+        w2 = build_workload(a.second_workload)
+        second = dict(workload=w2.name, d=w2.d, M=w2.M, order=w2.order)
+        second[a.dtype] = job_figure(w2, a.dtype, 2, 1, refine=refine)
+        if a.dtype != "c128":
+            second["c128"] = job_figure(w2, "c128", 1, 1, roofline=False)
+            second["mixed_speedup"] = round(second[a.dtype]["value"] / second["c128"]["value"], 3)
+        extra["second_workload"] = second
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -504,11 +565,12 @@ def main():
                                                  sample=one["sample"])
         except ImportError:
             pass
-        # sampled parity of the benchmarked run: interval 0 from the oracle sample
-        # (direction of U_0 against the oracle's, and its distance from unitarity)
-        extra["infidelity_U0_vs_oracle"] = float(oracle.propagator_infidelity(U_or[0], U_samples[0],
-                                                                             normalized=True))
-        extra["unitarity_error_U0"] = float(oracle.unitarity_error(U_samples[0]))
+        # sampled parity of the benchmarked run: U_0 against the oracle's (d^2 form,
+        # first order in any radial error, and its direction part), its unitarity
+        extra["U0_vs_oracle"] = dict(
+            infidelity=float(oracle.propagator_infidelity(U_or[0], U_samples[0])),
+            direction_infidelity=float(oracle.propagator_infidelity(U_or[0], U_samples[0], normalized=True)),
+            unitarity_error=float(oracle.unitarity_error(U_samples[0])))
 
     out = dict(
         metric="Magnus interval propagators/s at d=1024 (MFMA %) vs FP64 plain; p50/p99 latency",
@@ -517,10 +579,13 @@ def main():
         dtype={"c64": "c64+f64", "bf16x3": "c64(bf16x3)+f64", "c128": "c128"}[a.dtype],
         data="synthetic",
         config=dict(workload=w.name, d=w.d, K=w.K, N=w.N, M=w.M, order=w.order,
-                    precision={"c64": "complex64 MFMA products and squarings, FP64 norm/scaling/Pade solve",
+                    precision={"c64": "complex64 MFMA products and squarings, FP64 norm/scaling/Pade solve, "
+                                      "FP64-Gram unitary refinement",
                                "bf16x3": "complex64 storage, products and squarings on BF16 MFMA with three-way "
-                                         "split operands, FP64 norm/scaling/Pade solve",
-                               "c128": "complex128 throughout"}[a.dtype]),
+                                         "split operands, FP64 norm/scaling/Pade solve, FP64-Gram unitary "
+                                         "refinement",
+                               "c128": "complex128 throughout"}[a.dtype]
+                    if refine or a.dtype == "c128" else "unrefined " + a.dtype),
         roofline=roof, cpu_baseline=cpu, extra=extra,
     )
     print(json.dumps(out), flush=True)

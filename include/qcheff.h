@@ -74,6 +74,19 @@ extern "C" {
    give wrong results in this mode. */
 #define QCHEFF_SKEW_HERMITIAN 0x100
 
+/* qcheff_expm_batched: OR into dtype (QCHEFF_C64 or QCHEFF_C64_BF16X3, together
+   with QCHEFF_SKEW_HERMITIAN) to refine every result to unitarity.  The exact
+   exponential of a skew-Hermitian matrix is unitary, but each FP32 squaring
+   doubles the distance of the computed |eigenvalues| from 1, so after s
+   squarings U is off unitarity by about 2^s 2^-24.  With this flag one Newton
+   step of the polar decomposition follows the squarings: E = I - U U^dag is
+   formed in FP64 from the FP32 values (products on the FP64 matrix cores) and
+   U' = U + (1/2) E U (an FP32 product) is written, unitary up to O(|E|^2) and
+   the final rounding to complex64.  Costs one FP64 Hermitian product and one
+   FP32 product per item.  QCHEFF_EINVAL for QCHEFF_C128 (whose squarings need
+   no refinement) or without QCHEFF_SKEW_HERMITIAN. */
+#define QCHEFF_UNITARY_REFINE 0x200
+
 /* qcheff_expm_batched: OR QCHEFF_SQUARING_BOUND(n), 0 <= n <= 254, into dtype to
    enqueue exactly n squaring passes without reading the scaling exponents back
    to the host.  The call then never waits on the host and may be captured into

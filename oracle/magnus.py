@@ -250,12 +250,18 @@ def propagator_infidelity(U_ref, U, normalized=False):
 
 
 def state_infidelity(psi_ref, psi):
-    """1 - |<psi_ref|psi>|^2 / (<psi_ref|psi_ref> <psi|psi>) (the state error of Sec. 4.3).
+    """1 - |<psi_ref|psi>|^2, the final-state error of Sec. 4.3, as written there:
+    the overlap of the two vectors as they are, with no normalisation, so that a
+    state whose norm has drifted off 1 counts as wrong (the exact evolution is
+    unitary).  It is negative when |<psi_ref|psi>| exceeds 1."""
+    a, b = np.asarray(psi_ref), np.asarray(psi)
+    return 1.0 - abs(np.vdot(a, b)) ** 2
 
-    A pure state is a ray, so the overlap is taken between the normalised
-    vectors: a result whose norm finite precision has moved off 1 is compared by
-    its direction, and its norm is judged on its own (norm_error).
-    """
+
+def direction_infidelity(psi_ref, psi):
+    """1 - |<psi_ref|psi>|^2 / (<psi_ref|psi_ref> <psi|psi>): the error of the
+    state's direction alone (a pure state is a ray); with norm_error it splits the
+    state error into its two parts."""
     a, b = np.asarray(psi_ref), np.asarray(psi)
     na, nb = np.vdot(a, a).real, np.vdot(b, b).real
     return 1.0 - abs(np.vdot(a, b)) ** 2 / (na * nb)

@@ -34,6 +34,7 @@ STATE, PRODUCT = 1, 2
 REUSE_BASIS = 1
 FN_GENERATORS, FN_EXPM, FN_PROPAGATE, FN_ACTION = 1, 2, 3, 4
 SKEW_HERMITIAN = 0x100
+UNITARY_REFINE = 0x200
 KERNEL_GEMM_F32, KERNEL_GEMM_F64, KERNEL_GEMM_BF16X3, KERNEL_ACTION = 1, 2, 3, 4
 
 _DTYPES = {torch.complex128: C128, torch.complex64: C64}
@@ -172,7 +173,8 @@ def squaring_bound_flag(n: int) -> int:
 
 
 def expm_batched(omega, U=None, s_out=None, ws=None, chunk: int | None = None, stream=None,
-                 skew_hermitian: bool = False, squaring_bound: int | None = None, bf16x3: bool = False):
+                 skew_hermitian: bool = False, squaring_bound: int | None = None, bf16x3: bool = False,
+                 unitary_refine: bool = False):
     """U_b = exp(omega_b) by [13/13] Pade scaling and squaring (qcheff_expm_batched).
 
     ``U`` may be ``omega`` itself.  ``chunk`` caps the items processed at once
@@ -182,7 +184,9 @@ def expm_batched(omega, U=None, s_out=None, ws=None, chunk: int | None = None, s
     passes and never waits on the host (graph-capturable); items that need more
     come back with s = -2 and NaN entries.  ``bf16x3=True`` (complex64 only)
     runs the products on the BF16 matrix cores with three-way split operands
-    (QCHEFF_C64_BF16X3).  Returns (U, s).
+    (QCHEFF_C64_BF16X3).  ``unitary_refine=True`` (complex64, skew-Hermitian
+    inputs) follows the FP32 squarings with one FP64-Gram Newton step of the
+    polar decomposition (QCHEFF_UNITARY_REFINE).  Returns (U, s).
     """
     _dev(omega, "omega")
     B, d = omega.shape[0], omega.shape[-1]
@@ -199,7 +203,7 @@ def expm_batched(omega, U=None, s_out=None, ws=None, chunk: int | None = None, s
         ws = _workspace(workspace_bytes(FN_EXPM, max(1, min(B, chunk or B)), d, 1, 1, dt), omega.device)
     _check("qcheff_expm_batched", lib().qcheff_expm_batched(
         _ptr(omega), B, d,
-        dt | (SKEW_HERMITIAN if skew_hermitian else 0)
+        dt | (SKEW_HERMITIAN if skew_hermitian else 0) | (UNITARY_REFINE if unitary_refine else 0)
         | (0 if squaring_bound is None else squaring_bound_flag(squaring_bound)),
         _ptr(U), _ptr(s_out), _ptr(ws), ws.numel(), _stream(stream)))
     return U, s_out
@@ -246,11 +250,18 @@ def propagate_action(omega, x, traj=None, tol: float = 0.0, ws=None, stream=None
 
 
 def evolve_state(H0, Hk, u, dt_sample: float, M: int, order: int, psi0, dtype=torch.complex64,
-                 chunk: int = 64, tol: float = 0.0, stream=None):
+                 chunk: int = 64, tol: float | None = None, stream=None):
     """State-only path: coefficients, then per chunk of intervals the generators
     and the Taylor action on the state (no propagator is formed; the generators
-    of only `chunk` intervals are held at a time).  Returns psi_M."""
+    of only `chunk` intervals are held at a time).  Returns psi_M.
+
+    ``tol`` is the truncation tolerance per interval; by default 2^-24 / M for
+    complex64 generators (the truncation errors of the whole chain then stay
+    below the generators' own rounding, also in the state's norm) and the unit
+    roundoff 2^-53 for complex128."""
     N = u.shape[1]
+    if tol is None:
+        tol = 2.0 ** -24 / max(M, 1) if dtype == torch.complex64 else 0.0
     c1, c2 = magnus_coeffs(u, dt_sample, M, order, stream=stream)
     d = H0.shape[0]
     psi = psi0.clone()
@@ -282,7 +293,7 @@ def timing_read(kernel: int) -> dict:
 
 def evolve(H0, Hk, u, dt_sample: float, M: int, order: int, psi0=None, dtype=torch.complex64,
            product: bool = False, trajectory: bool = False, chunk: int | None = None, stream=None,
-           hermitian: bool = True, bf16x3: bool = False):
+           hermitian: bool = True, bf16x3: bool = False, unitary_refine: bool | None = None):
     """The whole path on the GPU: coefficients -> Omega_n -> U_n -> chain.
 
     Inputs are GPU tensors (H0 [d][d] and Hk [K][d][d] complex128, u [K][N]
@@ -291,13 +302,17 @@ def evolve(H0, Hk, u, dt_sample: float, M: int, order: int, psi0=None, dtype=tor
     closed system; the generators are then exactly skew-Hermitian and the
     exponentials use the structured Pade products.  ``bf16x3`` (with
     dtype=complex64) takes the products on the BF16 matrix cores with split
-    operands.  Returns a dict with c1, c2,
-    U, s and, as asked, psi (final state), traj, P.
+    operands.  ``unitary_refine`` (default: on for complex64 with Hermitian
+    operators) refines every FP32 propagator to unitarity after its squarings.
+    Returns a dict with c1, c2, U, s and, as asked, psi (final state), traj, P.
     """
     N = u.shape[1]
+    if unitary_refine is None:
+        unitary_refine = hermitian and dtype == torch.complex64
     c1, c2 = magnus_coeffs(u, dt_sample, M, order, stream=stream)
     omega, _ = magnus_generators(H0, Hk, c1, c2, dt_sample * (N // M), order, dtype, stream=stream)
-    U, s = expm_batched(omega, U=omega, chunk=chunk, stream=stream, skew_hermitian=hermitian, bf16x3=bf16x3)
+    U, s = expm_batched(omega, U=omega, chunk=chunk, stream=stream, skew_hermitian=hermitian, bf16x3=bf16x3,
+                        unitary_refine=unitary_refine)
     out = dict(c1=c1, c2=c2, U=U, s=s)
     if psi0 is not None:
         psi = psi0.clone()

@@ -480,7 +480,7 @@ int lu_solve(double2* aug, int* piv, int64_t d, int64_t nb, hipStream_t st) {
 
 template <typename T>
 int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t* s_out, int64_t nb, int64_t d,
-                   ExpmWs<T>& w, bool skew, int bound, bool bf16x3, hipStream_t st) {
+                   ExpmWs<T>& w, bool skew, int bound, bool bf16x3, bool refine, hipStream_t st) {
   using C2 = typename Cx<T>::t;
   const int64_t dd = d * d;
   double b[14];
@@ -546,8 +546,13 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
     QC_HIP((launch_cgemm<T>(p, st)));
   }
   if ((r = lu_solve(w.aug, w.piv, d, nb, st))) return r;
+  // The squarings ping-pong between the chunk's U and A; with the unitary
+  // refinement they run in W and V instead (the refinement reads the last one
+  // and writes U).  W and V are free once the augmented system is formed.
+  C2* sq0 = refine ? W : U;
+  C2* sq1 = refine ? V : A;
   hipLaunchKernelGGL(place_result_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, w.aug, int(d), w.s_ws,
-                     U, A);
+                     sq0, sq1);
   QC_HIP(hipGetLastError());
   // Without a bound the host reads the squaring counts back to size the
   // squaring launches; with one it enqueues exactly `bound` passes (an item
@@ -563,8 +568,39 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
     auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
     p.lda = d; p.ldb = d; p.ldc = d;
     p.sA = dd; p.sB = dd; p.sC = dd;
-    p.sq = 1; p.sq_s = w.s_ws; p.sq_step = step; p.sq_p0 = U; p.sq_p1 = A;
+    p.sq = 1; p.sq_s = w.s_ws; p.sq_step = step; p.sq_p0 = sq0; p.sq_p1 = sq1;
     QC_HIP((launch_cgemm<T>(p, st, active)));
+  }
+  if constexpr (sizeof(T) == 4) {
+    if (refine) {
+      // One Newton step of the polar decomposition: E = I - R R^dag in FP64
+      // from the FP32 result R (in sq0), then U = R + (1/2) E R.  U64 and
+      // U^dag sit side by side in the augmented-system buffer; E64 takes the
+      // space of A and A^2 (one complex128 matrix per item), E32 that of A^4.
+      hipLaunchKernelGGL(refine_prep_kernel, dim3(nblocks(d, 32), nblocks(d, 32), unsigned(nb)), dim3(256), 0, st,
+                         reinterpret_cast<const float2*>(sq0), int(d), w.aug);
+      QC_HIP(hipGetLastError());
+      double2* E64 = reinterpret_cast<double2*>(w.X[0]);
+      {
+        auto p = gemm_params<double>(int(d), int(d), int(d), int(nb), rule_cfg(d));
+        p.A = w.aug; p.lda = d; p.sA = 2 * dd;
+        p.B = w.aug + dd; p.ldb = d; p.sB = 2 * dd;
+        p.C = E64; p.ldc = d; p.sC = dd;
+        p.alpha = -1.0; p.gamma = 1.0; p.herm = 1;
+        QC_HIP((launch_cgemm<double>(p, st)));
+      }
+      float2* E32 = reinterpret_cast<float2*>(w.X[2]);
+      hipLaunchKernelGGL(to_c64_kernel, dim3(unsigned(std::min<int64_t>(nblocks(nb * dd, 256), 8192))), dim3(256), 0,
+                         st, E64, E32, nb * dd);
+      QC_HIP(hipGetLastError());
+      auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
+      p.A = E32; p.lda = d; p.sA = dd;
+      p.B = sq0; p.ldb = d; p.sB = dd;
+      p.C = U; p.ldc = d; p.sC = dd;
+      p.alpha = T(0.5);
+      p.nx = 1; p.X[0] = sq0; p.xc[0] = T(1);
+      QC_HIP((launch_cgemm<T>(p, st)));
+    }
   }
   if (mu) {
     hipLaunchKernelGGL(phase_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, U, dd, mu);
@@ -575,24 +611,25 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
 
 template <typename T>
 int run_expm(const void* omega, int64_t batch, int64_t d, void* U, int32_t* s_out, void* ws, size_t ws_bytes,
-             int dtype, bool skew, int bound, bool bf16x3, hipStream_t st) {
+             int dtype, bool skew, int bound, bool bf16x3, bool refine, hipStream_t st) {
   using C2 = typename Cx<T>::t;
   if (d <= kSmallD) {
     // one workgroup per item, everything in LDS; no workspace and no host sync
     const unsigned grid = unsigned(std::min<int64_t>(batch, 256 * 8));
     hipLaunchKernelGGL(expm_small_kernel<T>, dim3(grid), dim3(256), 0, st, static_cast<const C2*>(omega),
-                       static_cast<C2*>(U), s_out, int(d), int(batch), kTheta13);
+                       static_cast<C2*>(U), s_out, int(d), int(batch), kTheta13, refine ? 1 : 0);
     QC_HIP(hipGetLastError());
     return QCHEFF_OK;
   }
-  const int64_t chunk = expm_chunk(ws_bytes, batch, d, dtype);
+  // a chunk's items ride on the grid's y (or z) dimension
+  const int64_t chunk = std::min<int64_t>(expm_chunk(ws_bytes, batch, d, dtype), 65535);
   const int64_t dd = d * d;
   ExpmWs<T> w;
   if (!carve_expm<T>(ws, ws_bytes, chunk, d, w)) return fail(QCHEFF_EWORKSPACE, "workspace carving failed");
   for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
     const int64_t nb = std::min(chunk, batch - b0);
     int r = expm_chunk_run<T>(static_cast<const C2*>(omega) + b0 * dd, static_cast<C2*>(U) + b0 * dd,
-                              s_out ? s_out + b0 : nullptr, nb, d, w, skew, bound, bf16x3, st);
+                              s_out ? s_out + b0 : nullptr, nb, d, w, skew, bound, bf16x3, refine, st);
     if (r) return r;
   }
   return QCHEFF_OK;
@@ -830,12 +867,15 @@ int qcheff_magnus_generators(const void* H0, const void* Hk, int64_t d, int64_t 
 int qcheff_expm_batched(const void* omega, int64_t batch, int64_t d, int dtype, void* U, int32_t* s_out, void* ws,
                         size_t ws_bytes, void* stream) {
   const bool skew = (dtype & QCHEFF_SKEW_HERMITIAN) != 0;
+  const bool refine = (dtype & QCHEFF_UNITARY_REFINE) != 0;
   const int bound = ((dtype >> 16) & 0xff) - 1;   // -1: none
-  dtype &= ~(QCHEFF_SKEW_HERMITIAN | (0xff << 16));
+  dtype &= ~(QCHEFF_SKEW_HERMITIAN | QCHEFF_UNITARY_REFINE | (0xff << 16));
   const bool bf16x3 = dtype == QCHEFF_C64_BF16X3;
   if (bf16x3) dtype = QCHEFF_C64;
   Check c = check_expm(omega, batch, d, dtype, U, ws, ws_bytes);
   if (c.status) return fail(c);
+  if (refine && (dtype != QCHEFF_C64 || !skew))
+    return fail(QCHEFF_EINVAL, "QCHEFF_UNITARY_REFINE takes QCHEFF_C64 (or _BF16X3) with QCHEFF_SKEW_HERMITIAN");
   if (batch == 0) return QCHEFF_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (bound < 0 && d > kSmallD) {
@@ -846,8 +886,8 @@ int qcheff_expm_batched(const void* omega, int64_t batch, int64_t d, int dtype, 
                               "qcheff_expm_batched: a stream under graph capture needs QCHEFF_SQUARING_BOUND(n)"));
   }
   return dtype == QCHEFF_C128
-             ? run_expm<double>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, skew, bound, false, st)
-             : run_expm<float>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, skew, bound, bf16x3, st);
+             ? run_expm<double>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, skew, bound, false, false, st)
+             : run_expm<float>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, skew, bound, bf16x3, refine, st);
 }
 
 int qcheff_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, void* x, void* traj, void* ws,

@@ -5,7 +5,9 @@
 // and scaling exponent,
 // the six Pade products on 16x16x4 MFMA (one 16x16 output block per wave), the
 // FP64 elimination of the augmented system [V - U | V + U] with partial
-// pivoting and its back substitution, and the squarings.  Matrices are stored
+// pivoting and its back substitution, the squarings, and (FP32 results of
+// skew-Hermitian inputs, on request) one FP64 Newton step towards the nearest
+// unitary matrix.  Matrices are stored
 // zero-padded to 32 x 32, so every product is exact on the padding.
 #pragma once
 
@@ -93,7 +95,7 @@ __device__ __forceinline__ void small_gemm(typename Cx<T>::t (*C)[kSmallD + 1],
 template <typename T>
 __global__ __launch_bounds__(256) void expm_small_kernel(const typename Cx<T>::t* __restrict__ omega,
                                                          typename Cx<T>::t* __restrict__ U, int* __restrict__ s_out,
-                                                         int d, int batch, double theta) {
+                                                         int d, int batch, double theta, int refine) {
   using C2 = typename Cx<T>::t;
   using Acc = typename Cx<T>::acc;
   __shared__ SmallLds<T> L;
@@ -278,13 +280,46 @@ __global__ __launch_bounds__(256) void expm_small_kernel(const typename Cx<T>::t
       cur = nxt;
     }
     C2* dst = U + item * dd;
-    const double er = exp(mu.x), pr = er * cos(mu.y), pi = er * sin(mu.y);
-    for (int e = tid; e < d * d; e += 256) {
-      const C2 v = Mx[cur][e / d][e % d];
-      C2 o;
-      o.x = T(pr * double(v.x) - pi * double(v.y));
-      o.y = T(pr * double(v.y) + pi * double(v.x));
-      dst[e] = o;
+    if (refine) {
+      // One Newton step of the polar decomposition in FP64 (the FP32 squarings
+      // leave |eigenvalues| off 1 by about 2^s u32): E = I - R R^dag, then
+      // R' = R + (1/2) E R.  E takes the space of the augmented system.
+      auto& E = L.u.s.aug;
+      for (int e = tid; e < d * d; e += 256) {
+        const int i = e / d, j = e % d;
+        double gr = 0.0, gi = 0.0;
+        for (int k = 0; k < d; ++k) {
+          const C2 a = Mx[cur][i][k], b = Mx[cur][j][k];   // a conj(b)
+          gr += double(a.x) * double(b.x) + double(a.y) * double(b.y);
+          gi += double(a.y) * double(b.x) - double(a.x) * double(b.y);
+        }
+        E[i][j] = make_double2((i == j ? 1.0 : 0.0) - gr, -gi);
+      }
+      __syncthreads();
+      for (int e = tid; e < d * d; e += 256) {
+        const int i = e / d, j = e % d;
+        double cr = 0.0, ci = 0.0;
+        for (int k = 0; k < d; ++k) {
+          const double2 a = E[i][k];
+          const C2 b = Mx[cur][k][j];
+          cr += a.x * double(b.x) - a.y * double(b.y);
+          ci += a.x * double(b.y) + a.y * double(b.x);
+        }
+        const C2 v = Mx[cur][i][j];
+        C2 o;
+        o.x = T(double(v.x) + 0.5 * cr);
+        o.y = T(double(v.y) + 0.5 * ci);
+        dst[e] = o;
+      }
+    } else {
+      const double er = exp(mu.x), pr = er * cos(mu.y), pi = er * sin(mu.y);
+      for (int e = tid; e < d * d; e += 256) {
+        const C2 v = Mx[cur][e / d][e % d];
+        C2 o;
+        o.x = T(pr * double(v.x) - pi * double(v.y));
+        o.y = T(pr * double(v.y) + pi * double(v.x));
+        dst[e] = o;
+      }
     }
     __syncthreads();
   }

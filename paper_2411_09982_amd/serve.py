@@ -172,7 +172,8 @@ class Server:
                     N = r.u.shape[1]
                     omega, _ = q.magnus_generators(H0, Hk, c1, c2, r.dt_sample * (N // r.M), r.order, dtype,
                                                    stream=st)
-                    U, s = q.expm_batched(omega, U=omega, chunk=self.chunk, stream=st, skew_hermitian=True)
+                    U, s = q.expm_batched(omega, U=omega, chunk=self.chunk, stream=st, skew_hermitian=True,
+                                          unitary_refine=omega.dtype == torch.complex64)
                     q.propagate(U, q.STATE, psi, stream=st)
                     s_max = int(s.max().cpu())
                 psi_h = psi.cpu().numpy()

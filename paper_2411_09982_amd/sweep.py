@@ -66,6 +66,8 @@ class Sweep:
             g["graph"] = None
             g["bound"] = None
             self.groups.append(g)
+        # complex64 propagators are refined to unitarity after their FP32 squarings
+        self.refine = dtype == torch.complex64
         self.margin = 1
         self.replays = 0
         self.recaptures = 0
@@ -81,7 +83,7 @@ class Sweep:
             q.magnus_generators(H0, Hk, g["c1"][k], g["c2"][k], j.dt_interval, j.order, self.dtype,
                                 omega=g["omega"][k * M:(k + 1) * M], ws=g["gen_ws"])
         q.expm_batched(g["omega"], U=g["omega"], s_out=g["s"], ws=g["exp_ws"], skew_hermitian=True,
-                       squaring_bound=bound)
+                       squaring_bound=bound, unitary_refine=self.refine)
         g["psi"].copy_(g["psi0"])
         q.propagate_batched(g["omega"].view(len(g["idx"]), M, d, d), g["psi"])
 

@@ -28,8 +28,8 @@ def test_sweep_matches_single_jobs_and_oracle(dtype):
         ref = oracle.run(j.H0, j.Hk, j.u, j.dt_sample, j.M, j.order, psi0=j.psi0)
         inf = abs(oracle.state_infidelity(ref["psi"], got[i]))
         assert inf <= (1e-12 if dtype == torch.complex128 else 1e-6), (i, j.d, inf)
-        s_max = int(one["s"].max().cpu())
-        nbound = j.M * 1e-13 if dtype == torch.complex128 else j.M * 2.0 ** s_max * 2.0 ** -24
+        # complex64 propagators are refined to unitarity: the norm holds to the target
+        nbound = j.M * 1e-13 if dtype == torch.complex128 else 1e-6
         assert oracle.norm_error(got[i]) <= nbound, (i, j.d)
 
 

@@ -33,6 +33,9 @@ MUTANTS = {
     "prop_infidelity_norm_one_side": ("np.abs(tr) ** 2 / (na * nb)", "np.abs(tr) ** 2 / (na * na)"),
     "shift_sign": ("Omega = Omega - mu * np.eye", "Omega = Omega + mu * np.eye"),
     "shift_not_mean": ("complex(np.trace(Omega)) / Omega.shape[-1]", "complex(np.trace(Omega))"),
+    "generators_sign": ("return -1j * effective_hamiltonians", "return 1j * effective_hamiltonians"),
+    "state_infidelity_normalised": ("    return 1.0 - abs(np.vdot(a, b)) ** 2\n",
+                                    "    return 1.0 - abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real)\n"),
 }
 
 

@@ -178,13 +178,16 @@ def test_determinant_and_unitarity():
     np.testing.assert_allclose(res["P"] @ w.psi0, res["psi"], atol=1e-12)
 
 
-def test_state_infidelity_of_rays():
-    # a global phase or a rescaling leaves the state (a ray) unchanged; orthogonal
-    # states are infidelity 1; two unit vectors at angle a give sin^2 a
+def test_state_infidelity_definition():
+    # Sec. 4.3's error 1 - |<psi_ref|psi>|^2 on the vectors as they are: a global
+    # phase of a unit vector is no error, a rescaled vector is (1 - 1.7^2), an
+    # orthogonal state is 1, two unit vectors at angle a give sin^2 a
     g = np.random.default_rng(3)
     psi = g.standard_normal(6) + 1j * g.standard_normal(6)
     psi /= np.linalg.norm(psi)
-    assert abs(oracle.state_infidelity(psi, 1.7 * np.exp(0.4j) * psi)) < 1e-15
+    assert abs(oracle.state_infidelity(psi, np.exp(0.4j) * psi)) < 1e-15
+    assert oracle.state_infidelity(psi, 1.7 * psi) == pytest.approx(1.0 - 1.7 ** 2, abs=1e-14)
+    assert oracle.state_infidelity(psi, (1.0 + 1e-4) * psi) == pytest.approx(-2e-4 - 1e-8, abs=1e-15)
     e0, e1 = np.eye(2)[0].astype(complex), np.eye(2)[1].astype(complex)
     assert oracle.state_infidelity(e0, e1) == pytest.approx(1.0, abs=1e-15)
     a = 0.3
@@ -192,6 +195,33 @@ def test_state_infidelity_of_rays():
                                                                                                    abs=1e-15)
     assert oracle.norm_error(1.25 * psi) == pytest.approx(0.25, abs=1e-15)
     assert oracle.norm_error(psi) < 1e-15
+
+
+def test_direction_infidelity_of_rays():
+    # the direction part alone: a global phase or a rescaling leaves the ray
+    # unchanged; orthogonal rays are 1; rays at angle a give sin^2 a at any scale
+    g = np.random.default_rng(3)
+    psi = g.standard_normal(6) + 1j * g.standard_normal(6)
+    psi /= np.linalg.norm(psi)
+    assert abs(oracle.direction_infidelity(psi, 1.7 * np.exp(0.4j) * psi)) < 1e-15
+    e0, e1 = np.eye(2)[0].astype(complex), np.eye(2)[1].astype(complex)
+    assert oracle.direction_infidelity(e0, 3.0 * e1) == pytest.approx(1.0, abs=1e-15)
+    a = 0.3
+    v = 2.5 * (math.cos(a) * e0 + 1j * math.sin(a) * e1)
+    assert oracle.direction_infidelity(e0, v) == pytest.approx(math.sin(a) ** 2, abs=1e-15)
+
+
+def test_generators_sign():
+    # exp(Omega_n) must be the propagator exp(-i H-bar_n) of the interval: for a
+    # constant two-level drive the Rabi closed form fixes the sign of Omega = -i H-bar
+    D, W, T = 0.8, 2.3, 0.9
+    c1, c2 = oracle.interval_coefficients(np.full((1, 10), W), T / 10, 1, 2)
+    Om = oracle.generators(0.5 * D * SZ, (0.5 * SX)[None], c1, c2, T, 2)
+    WR = math.hypot(D, W)
+    th = 0.5 * WR * T
+    exact = math.cos(th) * np.eye(2) - 1j * math.sin(th) * (D * SZ + W * SX) / WR
+    np.testing.assert_allclose(sl.expm(Om[0]), exact, atol=1e-14)
+    np.testing.assert_allclose(Om[0] + Om[0].conj().T, 0.0, atol=1e-15)
 
 
 def test_normalized_propagator_infidelity():
