@@ -144,6 +144,9 @@ class Job:
         self.c1 = torch.empty((M, K), dtype=torch.float64, device=dev)
         self.c2 = torch.empty((M, K + K * (K - 1) // 2), dtype=torch.float64, device=dev) if w.order == 2 else None
         self.omega = torch.empty((M, d, d), dtype=self.dtype, device=dev)
+        # refined FP32-product propagators are kept in complex128 (no final rounding
+        # to complex64); otherwise U overwrites the generators in place
+        self.U = torch.empty((M, d, d), dtype=torch.complex128, device=dev) if self.refine else self.omega
         self.s = torch.empty(M, dtype=torch.int32, device=dev)
         gen_ws = q.workspace_bytes(q.FN_GENERATORS, 1, d, K, w.order, q.C128)
         self.gen_ws = torch.empty(max(gen_ws, 1), dtype=torch.uint8, device=dev) if gen_ws else None
@@ -155,8 +158,8 @@ class Job:
         ws_bytes = q.workspace_bytes(q.FN_EXPM, self.chunk, d, 1, 1, code)
         self.exp_ws = [torch.empty(ws_bytes, dtype=torch.uint8, device=dev) for _ in range(self.lanes)]
         self.lane_streams = [torch.cuda.Stream() for _ in range(self.lanes)] if self.lanes > 1 else None
-        self.prop_ws = torch.empty(q.workspace_bytes(q.FN_PROPAGATE, M, d, 1, q.STATE, code), dtype=torch.uint8,
-                                   device=dev)
+        self.prop_ws = torch.empty(q.workspace_bytes(q.FN_PROPAGATE, M, d, 1, q.STATE, q.C128 if self.refine else code),
+                                   dtype=torch.uint8, device=dev)
         self.side = torch.cuda.Stream()   # default priority
         if self.lanes > 1:
             import concurrent.futures
@@ -174,9 +177,9 @@ class Job:
         if self.lanes == 1:
             for c0 in range(0, w.M, self.chunk):
                 c1 = min(w.M, c0 + self.chunk)
-                U = self.omega[c0:c1]
-                q.expm_batched(U, U=U, s_out=self.s[c0:c1], ws=self.exp_ws[0], skew_hermitian=True,
-                               bf16x3=self.bf16x3, unitary_refine=self.refine)
+                U = self.U[c0:c1]
+                q.expm_batched(self.omega[c0:c1], U=U, s_out=self.s[c0:c1], ws=self.exp_ws[0], skew_hermitian=True,
+                               bf16x3=self.bf16x3, unitary_refine=self.refine, out_c128=self.refine)
                 ev = torch.cuda.Event()
                 ev.record(main)
                 self.side.wait_event(ev)
@@ -192,9 +195,9 @@ class Job:
             st = self.lane_streams[lane]
             c0, c1 = chunks[idx]
             st.wait_event(ready)
-            U = self.omega[c0:c1]
-            q.expm_batched(U, U=U, s_out=self.s[c0:c1], ws=self.exp_ws[lane], skew_hermitian=True,
-                           bf16x3=self.bf16x3, unitary_refine=self.refine, stream=st)
+            U = self.U[c0:c1]
+            q.expm_batched(self.omega[c0:c1], U=U, s_out=self.s[c0:c1], ws=self.exp_ws[lane], skew_hermitian=True,
+                           bf16x3=self.bf16x3, unitary_refine=self.refine, out_c128=self.refine, stream=st)
             ev = torch.cuda.Event()
             ev.record(st)
             return ev
@@ -208,7 +211,7 @@ class Job:
         for idx in range(len(chunks)):
             c0, c1 = chunks[idx]
             self.side.wait_event(futs[idx].result())
-            q.propagate(self.omega[c0:c1], q.STATE, self.psi, ws=self.prop_ws, stream=self.side)
+            q.propagate(self.U[c0:c1], q.STATE, self.psi, ws=self.prop_ws, stream=self.side)
         main.wait_stream(self.side)
 
 
@@ -364,14 +367,14 @@ def action(a):
         ws = torch.empty(q.workspace_bytes(q.FN_ACTION, P, w.d, 1, 1, q.C64 if dt_name == "c64" else q.C128),
                          dtype=torch.uint8, device=dev)
         x = psi0.clone()
-        q.propagate_action(om, x, ws=ws)              # warm-up
+        q.propagate_action(om, x, ws=ws, skew_hermitian=True)   # warm-up
 
         def passes(n):
             for _ in range(n):
                 x.copy_(psi0)
                 q.magnus_generators(H0, Hk, c1p, c2p, w.dt_interval, w.order, dtype, omega=om, ws=gws,
                                     reuse_basis=True)
-                q.propagate_action(om, x, ws=ws)
+                q.propagate_action(om, x, ws=ws, skew_hermitian=True)
             torch.cuda.synchronize()
 
         torch.cuda.synchronize()
@@ -526,7 +529,7 @@ def main():
     )
     extra.update(gemm_rates(kern, a.steps))
     psi_mixed = job.psi.cpu().numpy()
-    U_samples = {n: job.omega[n].cpu().numpy().astype(np.complex128) for n in (0, w.M // 2, w.M - 1)}
+    U_samples = {n: job.U[n].cpu().numpy().astype(np.complex128) for n in (0, w.M // 2, w.M - 1)}
     del job
     torch.cuda.empty_cache()
     ref = golden_state(a.workload)

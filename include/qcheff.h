@@ -87,6 +87,15 @@ extern "C" {
    no refinement) or without QCHEFF_SKEW_HERMITIAN. */
 #define QCHEFF_UNITARY_REFINE 0x200
 
+/* qcheff_expm_batched: OR into dtype together with QCHEFF_UNITARY_REFINE to
+   receive the refined result in FP64: U is then [batch][d][d] complex128 and
+   must not overlap omega.  The correction (1/2) E U is added to the FP32 result
+   in FP64, so U is unitary up to O(|E|^2) with no final rounding to complex64.
+   A chain of M nearly equal propagators (a drift-dominated system) repeats the
+   complex64 rounding of each one, and its norm error then grows like M 2^-24;
+   complex128 storage removes that term. */
+#define QCHEFF_OUT_C128 0x400
+
 /* qcheff_expm_batched: OR QCHEFF_SQUARING_BOUND(n), 0 <= n <= 254, into dtype to
    enqueue exactly n squaring passes without reading the scaling exponents back
    to the host.  The call then never waits on the host and may be captured into
@@ -231,12 +240,15 @@ int qcheff_propagate_batched(const void* U, int64_t B, int64_t M, int64_t d, int
  * series (O(d^2) per matrix-vector product instead of O(d^3) per propagator;
  * pays off when d is large and ||Omega_n|| moderate, e.g. many short intervals).
  *
- *   omega      [M][d][d], device, dtype (QCHEFF_C128 or QCHEFF_C64): the
- *              generators as qcheff_magnus_generators writes them, which are
- *              skew-Hermitian (Omega_ji = -conj(Omega_ij)) for Hermitian H0,
- *              H_k.  For d >= 2048 the products read the upper triangle (and
- *              the 64 x 64 diagonal tiles) only and take the lower triangle as
- *              its mirror; the shift and the norms read the whole matrix.
+ *   omega      [M][d][d], device, dtype (QCHEFF_C128 or QCHEFF_C64, optionally
+ *              | QCHEFF_SKEW_HERMITIAN): the generators.  Any square matrices;
+ *              with QCHEFF_SKEW_HERMITIAN (Omega_ji = -conj(Omega_ij), as
+ *              qcheff_magnus_generators writes them for Hermitian H0, H_k) the
+ *              products for d >= 2048 read the upper triangle (and the 64 x 64
+ *              diagonal tiles) only and take the lower triangle as its mirror,
+ *              and one row-norm pass gives both norms; the shift reads the
+ *              whole diagonal.  Inputs declared skew-Hermitian that are not
+ *              give wrong results.
  *   x          [d] complex128, device, in: psi_0, out: psi_M (FP64 state,
  *              products accumulate in FP64).
  *   traj       optional [M+1][d] complex128: psi_0 ... psi_M.
@@ -267,14 +279,18 @@ size_t qcheff_workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int o
 const char* qcheff_last_error(void);
 
 /*
- * qcheff_sync_status - waits for `stream`, then reports and clears the
- * conditions the library's kernels (and host-side checks) have flagged on the
- * current device since the previous call: a non-finite norm of a generator
- * (the scaling step of the exponential, Sec. 4.1, or the Taylor action), or a
- * zero pivot in the LU of a Pade denominator.  The affected results are NaN
- * (qcheff_expm_batched also marks them with s_out = -1); this call is the one
- * place to learn about it without inspecting them.  The flags are per device
- * and shared by every stream and thread of the process.
+ * qcheff_sync_status - reports and clears the conditions the library's kernels
+ * (and host-side checks) have flagged on the current device since the previous
+ * call: a non-finite norm of a generator (the scaling step of the exponential,
+ * Sec. 4.1, or the Taylor action), or a zero pivot in the LU of a Pade
+ * denominator.  The affected results are NaN (qcheff_expm_batched also marks
+ * them with s_out = -1); this call is the one place to learn about it without
+ * inspecting them.  The device's flag word is taken and cleared in one atomic
+ * step by a kernel enqueued on `stream` (so after the stream's earlier work),
+ * then read back; the call waits for `stream`.  A flag that a kernel on
+ * another stream sets meanwhile is kept for the next call.  The flags are per
+ * device and shared by every stream and thread of the process, so they cannot
+ * say which job raised them.
  * Returns QCHEFF_OK, QCHEFF_ENONFINITE or QCHEFF_EDEVICE.
  */
 int qcheff_sync_status(void* stream);

@@ -35,6 +35,7 @@ REUSE_BASIS = 1
 FN_GENERATORS, FN_EXPM, FN_PROPAGATE, FN_ACTION = 1, 2, 3, 4
 SKEW_HERMITIAN = 0x100
 UNITARY_REFINE = 0x200
+OUT_C128 = 0x400
 KERNEL_GEMM_F32, KERNEL_GEMM_F64, KERNEL_GEMM_BF16X3, KERNEL_ACTION = 1, 2, 3, 4
 
 _DTYPES = {torch.complex128: C128, torch.complex64: C64}
@@ -174,7 +175,7 @@ def squaring_bound_flag(n: int) -> int:
 
 def expm_batched(omega, U=None, s_out=None, ws=None, chunk: int | None = None, stream=None,
                  skew_hermitian: bool = False, squaring_bound: int | None = None, bf16x3: bool = False,
-                 unitary_refine: bool = False):
+                 unitary_refine: bool = False, out_c128: bool = False):
     """U_b = exp(omega_b) by [13/13] Pade scaling and squaring (qcheff_expm_batched).
 
     ``U`` may be ``omega`` itself.  ``chunk`` caps the items processed at once
@@ -186,7 +187,9 @@ def expm_batched(omega, U=None, s_out=None, ws=None, chunk: int | None = None, s
     runs the products on the BF16 matrix cores with three-way split operands
     (QCHEFF_C64_BF16X3).  ``unitary_refine=True`` (complex64, skew-Hermitian
     inputs) follows the FP32 squarings with one FP64-Gram Newton step of the
-    polar decomposition (QCHEFF_UNITARY_REFINE).  Returns (U, s).
+    polar decomposition (QCHEFF_UNITARY_REFINE); with ``out_c128=True`` as well
+    the refined U is written in complex128 (QCHEFF_OUT_C128; U then must not
+    overlap omega).  Returns (U, s).
     """
     _dev(omega, "omega")
     B, d = omega.shape[0], omega.shape[-1]
@@ -196,7 +199,8 @@ def expm_batched(omega, U=None, s_out=None, ws=None, chunk: int | None = None, s
             raise ValueError("bf16x3 products take complex64 matrices")
         dt = C64_BF16X3
     if U is None:
-        U = torch.empty_like(omega)
+        U = torch.empty(omega.shape, dtype=torch.complex128, device=omega.device) if out_c128 else \
+            torch.empty_like(omega)
     if s_out is None:
         s_out = torch.empty(B, dtype=torch.int32, device=omega.device)
     if ws is None:
@@ -204,6 +208,7 @@ def expm_batched(omega, U=None, s_out=None, ws=None, chunk: int | None = None, s
     _check("qcheff_expm_batched", lib().qcheff_expm_batched(
         _ptr(omega), B, d,
         dt | (SKEW_HERMITIAN if skew_hermitian else 0) | (UNITARY_REFINE if unitary_refine else 0)
+        | (OUT_C128 if out_c128 else 0)
         | (0 if squaring_bound is None else squaring_bound_flag(squaring_bound)),
         _ptr(U), _ptr(s_out), _ptr(ws), ws.numel(), _stream(stream)))
     return U, s_out
@@ -233,24 +238,26 @@ def propagate_batched(U, x, stream=None):
     return x
 
 
-def propagate_action(omega, x, traj=None, tol: float = 0.0, ws=None, stream=None):
+def propagate_action(omega, x, traj=None, tol: float = 0.0, ws=None, stream=None, skew_hermitian: bool = False):
     """psi <- exp(omega[M-1]) ... exp(omega[0]) psi by the truncated Taylor action
     (qcheff_propagate_action); omega [M][d][d] generators, x [d] complex128 in place.
-    The generators are taken as skew-Hermitian: from d = 2048 the products read
-    only their upper triangle (QCHEFF_ACTION_KERNEL=rows|tiles overrides)."""
+    ``skew_hermitian=True`` declares the generators skew-Hermitian: from d = 2048
+    the products then read only their upper triangle (QCHEFF_ACTION_KERNEL=rows|tiles
+    overrides the size rule)."""
     _dev(omega, "omega")
     _dev(x, "x")
     M, d = omega.shape[0], omega.shape[-1]
     if ws is None:
         ws = _workspace(workspace_bytes(FN_ACTION, M, d, 1, 1, _DTYPES[omega.dtype]), omega.device)
     _check("qcheff_propagate_action", lib().qcheff_propagate_action(
-        _ptr(omega), M, d, _DTYPES[omega.dtype], _ptr(x), _ptr(traj), float(tol), _ptr(ws), ws.numel(),
+        _ptr(omega), M, d, _DTYPES[omega.dtype] | (SKEW_HERMITIAN if skew_hermitian else 0), _ptr(x), _ptr(traj),
+        float(tol), _ptr(ws), ws.numel(),
         _stream(stream)))
     return x
 
 
 def evolve_state(H0, Hk, u, dt_sample: float, M: int, order: int, psi0, dtype=torch.complex64,
-                 chunk: int = 64, tol: float | None = None, stream=None):
+                 chunk: int = 64, tol: float | None = None, stream=None, hermitian: bool = True):
     """State-only path: coefficients, then per chunk of intervals the generators
     and the Taylor action on the state (no propagator is formed; the generators
     of only `chunk` intervals are held at a time).  Returns psi_M.
@@ -258,7 +265,9 @@ def evolve_state(H0, Hk, u, dt_sample: float, M: int, order: int, psi0, dtype=to
     ``tol`` is the truncation tolerance per interval; by default 2^-24 / M for
     complex64 generators (the truncation errors of the whole chain then stay
     below the generators' own rounding, also in the state's norm) and the unit
-    roundoff 2^-53 for complex128."""
+    roundoff 2^-53 for complex128.  ``hermitian`` states that H0 and every H_k
+    are exactly Hermitian, so the generators are exactly skew-Hermitian (the
+    products of large d then read half of each)."""
     N = u.shape[1]
     if tol is None:
         tol = 2.0 ** -24 / max(M, 1) if dtype == torch.complex64 else 0.0
@@ -274,7 +283,7 @@ def evolve_state(H0, Hk, u, dt_sample: float, M: int, order: int, psi0, dtype=to
         _, gen_ws = magnus_generators(H0, Hk, c1[c0:c1_], None if c2 is None else c2[c0:c1_],
                                       dt_sample * (N // M), order, dtype, omega=om, ws=gen_ws,
                                       reuse_basis=gen_ws is not None, stream=stream)
-        propagate_action(om, psi, tol=tol, ws=act_ws, stream=stream)
+        propagate_action(om, psi, tol=tol, ws=act_ws, stream=stream, skew_hermitian=hermitian)
     return psi
 
 
@@ -293,7 +302,8 @@ def timing_read(kernel: int) -> dict:
 
 def evolve(H0, Hk, u, dt_sample: float, M: int, order: int, psi0=None, dtype=torch.complex64,
            product: bool = False, trajectory: bool = False, chunk: int | None = None, stream=None,
-           hermitian: bool = True, bf16x3: bool = False, unitary_refine: bool | None = None):
+           hermitian: bool = True, bf16x3: bool = False, unitary_refine: bool | None = None,
+           out_c128: bool | None = None):
     """The whole path on the GPU: coefficients -> Omega_n -> U_n -> chain.
 
     Inputs are GPU tensors (H0 [d][d] and Hk [K][d][d] complex128, u [K][N]
@@ -303,16 +313,21 @@ def evolve(H0, Hk, u, dt_sample: float, M: int, order: int, psi0=None, dtype=tor
     exponentials use the structured Pade products.  ``bf16x3`` (with
     dtype=complex64) takes the products on the BF16 matrix cores with split
     operands.  ``unitary_refine`` (default: on for complex64 with Hermitian
-    operators) refines every FP32 propagator to unitarity after its squarings.
-    Returns a dict with c1, c2, U, s and, as asked, psi (final state), traj, P.
+    operators) refines every FP32 propagator to unitarity after its squarings,
+    and ``out_c128`` (default: with the refinement) keeps the refined U in
+    complex128.  Returns a dict with c1, c2, U, s and, as asked, psi (final
+    state), traj, P.
     """
     N = u.shape[1]
     if unitary_refine is None:
         unitary_refine = hermitian and dtype == torch.complex64
+    if out_c128 is None:
+        out_c128 = unitary_refine
     c1, c2 = magnus_coeffs(u, dt_sample, M, order, stream=stream)
     omega, _ = magnus_generators(H0, Hk, c1, c2, dt_sample * (N // M), order, dtype, stream=stream)
-    U, s = expm_batched(omega, U=omega, chunk=chunk, stream=stream, skew_hermitian=hermitian, bf16x3=bf16x3,
-                        unitary_refine=unitary_refine)
+    U, s = expm_batched(omega, U=None if out_c128 else omega, chunk=chunk, stream=stream, skew_hermitian=hermitian,
+                        bf16x3=bf16x3, unitary_refine=unitary_refine, out_c128=out_c128)
+    del omega
     out = dict(c1=c1, c2=c2, U=U, s=s)
     if psi0 is not None:
         psi = psi0.clone()

@@ -31,7 +31,16 @@ struct TimedLaunch {
   hipEvent_t a, b;
 };
 std::atomic<int> g_timing{0};
-std::atomic<unsigned> g_host_status{0};   // conditions found on the host, reported with the device's
+// Conditions found on the host (per device), reported with the device's own.
+constexpr int kMaxDevices = 64;
+std::atomic<unsigned> g_host_status[kMaxDevices];
+std::mutex g_status_mu;   // one take-and-copy of the device status word at a time
+
+void flag_host_status(unsigned bits) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+  g_host_status[dev].fetch_or(bits);
+}
 std::mutex g_timing_mu;               // guards g_timed and g_events
 std::vector<TimedLaunch> g_timed;
 // Events come from a pool and go back to it once read: creating two events per
@@ -234,7 +243,10 @@ int bf16x3_cfg() {
 // Taylor-term kernel: 0 reads Omega whole (a wave per row), 1 reads its upper
 // triangle by tiles and finishes the output blocks in a second launch.  Below
 // d = 2048 the tile grid (nb (nb + 1) / 2 workgroups) does not fill the chip.
-int action_mode(int64_t d) {
+// The tiles need generators declared skew-Hermitian (the lower triangle is not
+// read); without the declaration every product reads the whole matrix.
+int action_mode(int64_t d, bool skew) {
+  if (!skew) return 0;
   const char* v = std::getenv("QCHEFF_ACTION_KERNEL");
   if (v && std::strcmp(v, "rows") == 0) return 0;
   if (v && std::strcmp(v, "tiles") == 0) return 1;
@@ -245,7 +257,8 @@ int action_mode(int64_t d) {
 int run_coeffs(const double* u, int64_t K, int64_t N, double dt, int64_t M, int order, double* c1,
                double* c2, hipStream_t st) {
   const int64_t s = N / M;
-  hipLaunchKernelGGL(coeffs_kernel, dim3(nblocks(M, 64)), dim3(64), 0, st, u, int(K), N, M, s, dt, order, c1, c2);
+  // one wave per interval, four per workgroup
+  hipLaunchKernelGGL(coeffs_kernel, dim3(nblocks(M, 4)), dim3(256), 0, st, u, int(K), N, M, s, dt, order, c1, c2);
   QC_HIP(hipGetLastError());
   return QCHEFF_OK;
 }
@@ -478,11 +491,14 @@ int lu_solve(double2* aug, int* piv, int64_t d, int64_t nb, hipStream_t st) {
   return trsm_upper(c, 0, d, d, 2 * d);                      // R = U^{-1} Y
 }
 
+// U64: with the unitary refinement, an FP64 destination of the refined result
+// (U is then not written); null otherwise.
 template <typename T>
 int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t* s_out, int64_t nb, int64_t d,
-                   ExpmWs<T>& w, bool skew, int bound, bool bf16x3, bool refine, hipStream_t st) {
+                   ExpmWs<T>& w, bool skew, int bound, bool bf16x3, bool refine, double2* U64, hipStream_t st) {
   using C2 = typename Cx<T>::t;
   const int64_t dd = d * d;
+  C2* Ubuf = U ? U : reinterpret_cast<C2*>(U64);   // the chunk's destination, as scratch of its own type
   double b[14];
   pade_coefficients(13, b);
   const T c[14] = {T(b[0]), T(b[1]), T(b[2]), T(b[3]), T(b[4]), T(b[5]), T(b[6]),
@@ -503,8 +519,16 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
     hipLaunchKernelGGL(trace_mean_kernel<C2>, dim3(unsigned(nb)), dim3(256), 0, st, omega, int(d), w.mu);
     mu = w.mu;
   }
-  hipLaunchKernelGGL(norm1_kernel<C2>, dim3(nblocks(d, 256), unsigned(nb)), dim3(256), 0, st, omega, int(d), mu,
-                     w.norms);
+  {
+    // partial column sums per 128-row tile go to the augmented-system buffer,
+    // which is not in use before the Pade products
+    const unsigned tiles = nblocks(d, kNormRows);
+    double* partial = reinterpret_cast<double*>(w.aug);
+    hipLaunchKernelGGL(norm1_partial_kernel<C2>, dim3(nblocks(d, 64), tiles, unsigned(nb)), dim3(256), 0, st, omega,
+                       int(d), mu, partial);
+    hipLaunchKernelGGL(norm1_finish_kernel, dim3(unsigned(nb)), dim3(256), 0, st, partial, int(d), int(tiles),
+                       w.norms);
+  }
   QC_HIP(hipGetLastError());
   const unsigned sblocks = unsigned(std::min<int64_t>(nblocks(dd, 256), 1024));
   hipLaunchKernelGGL(scale_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, omega, w.X[0], int(d), mu,
@@ -522,17 +546,18 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
   // W = A6 (b13 A6 + b11 A4 + b9 A2) + b7 A6 + b5 A4 + b3 A2 + b1 I   (U = A W)
   // V = A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I
   // The inner combinations go to buffers that are free at this point: the
-  // chunk's U (its input was consumed by the scaling) and W.  V is formed first
+  // chunk's U (its input was consumed by the scaling; with an FP64 destination,
+  // the first half of that) and W.  V is formed first
   // (from W), then W (from U) overwrites its own buffer.  The outer terms are
   // added by the epilogues.
   hipLaunchKernelGGL((pade_inner_kernel<C2, T>), dim3(unsigned(std::min<int64_t>(nblocks(nb * dd, 256), 8192))),
-                     dim3(256), 0, st, A6, A4, A2, nb * dd, c[13], c[11], c[9], c[12], c[10], c[8], U, W);
+                     dim3(256), 0, st, A6, A4, A2, nb * dd, c[13], c[11], c[9], c[12], c[10], c[8], Ubuf, W);
   QC_HIP(hipGetLastError());
   const C2* Xs[3] = {A6, A4, A2};
   const T xv[3] = {c[6], c[4], c[2]};
   if ((r = gemm_sq<T>(cfg, h, V, A6, W, d, nb, st, 3, Xs, xv, c[0]))) return r;
   const T xw[3] = {c[7], c[5], c[3]};
-  if ((r = gemm_sq<T>(cfg, h, W, A6, U, d, nb, st, 3, Xs, xw, c[1]))) return r;
+  if ((r = gemm_sq<T>(cfg, h, W, A6, Ubuf, d, nb, st, 3, Xs, xw, c[1]))) return r;
   // [q | p] = [V - A W | V + A W] in FP64
   {
     auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
@@ -596,9 +621,13 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
       auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
       p.A = E32; p.lda = d; p.sA = dd;
       p.B = sq0; p.ldb = d; p.sB = dd;
-      p.C = U; p.ldc = d; p.sC = dd;
+      p.C = U64 ? sq0 : U; p.ldc = d; p.sC = dd;
       p.alpha = T(0.5);
       p.nx = 1; p.X[0] = sq0; p.xc[0] = T(1);
+      if (U64) {   // R + (1/2) E R formed and kept in FP64: no final rounding to FP32
+        p.epi = EPI_OUT64;
+        p.aug = U64; p.ld_aug = d; p.s_aug = dd;
+      }
       QC_HIP((launch_cgemm<T>(p, st)));
     }
   }
@@ -611,13 +640,14 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
 
 template <typename T>
 int run_expm(const void* omega, int64_t batch, int64_t d, void* U, int32_t* s_out, void* ws, size_t ws_bytes,
-             int dtype, bool skew, int bound, bool bf16x3, bool refine, hipStream_t st) {
+             int dtype, bool skew, int bound, bool bf16x3, bool refine, bool out64, hipStream_t st) {
   using C2 = typename Cx<T>::t;
   if (d <= kSmallD) {
     // one workgroup per item, everything in LDS; no workspace and no host sync
     const unsigned grid = unsigned(std::min<int64_t>(batch, 256 * 8));
     hipLaunchKernelGGL(expm_small_kernel<T>, dim3(grid), dim3(256), 0, st, static_cast<const C2*>(omega),
-                       static_cast<C2*>(U), s_out, int(d), int(batch), kTheta13, refine ? 1 : 0);
+                       out64 ? nullptr : static_cast<C2*>(U), out64 ? static_cast<double2*>(U) : nullptr, s_out,
+                       int(d), int(batch), kTheta13, refine ? 1 : 0);
     QC_HIP(hipGetLastError());
     return QCHEFF_OK;
   }
@@ -628,8 +658,10 @@ int run_expm(const void* omega, int64_t batch, int64_t d, void* U, int32_t* s_ou
   if (!carve_expm<T>(ws, ws_bytes, chunk, d, w)) return fail(QCHEFF_EWORKSPACE, "workspace carving failed");
   for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
     const int64_t nb = std::min(chunk, batch - b0);
-    int r = expm_chunk_run<T>(static_cast<const C2*>(omega) + b0 * dd, static_cast<C2*>(U) + b0 * dd,
-                              s_out ? s_out + b0 : nullptr, nb, d, w, skew, bound, bf16x3, refine, st);
+    int r = expm_chunk_run<T>(static_cast<const C2*>(omega) + b0 * dd,
+                              out64 ? nullptr : static_cast<C2*>(U) + b0 * dd, s_out ? s_out + b0 : nullptr, nb, d,
+                              w, skew, bound, bf16x3, refine, out64 ? static_cast<double2*>(U) + b0 * dd : nullptr,
+                              st);
     if (r) return r;
   }
   return QCHEFF_OK;
@@ -685,7 +717,7 @@ constexpr double kMaxActionTerms = double(1 << 24);   // products per interval
 
 template <typename T>
 int run_action(const void* Ov, int64_t M, int64_t d, void* x, void* traj, double tol, void* ws, size_t ws_bytes,
-               hipStream_t st) {
+               bool skew, hipStream_t st) {
   using C2 = typename Cx<T>::t;
   const C2* Om = static_cast<const C2*>(Ov);
   const int64_t dd = d * d;
@@ -696,7 +728,7 @@ int run_action(const void* Ov, int64_t M, int64_t d, void* x, void* traj, double
   unsigned long long* norms = cv.take<unsigned long long>(size_t(M) * 16);
   const int nb = int((d + kActTile - 1) / kActTile);
   double2* P = cv.take<double2>(size_t(nb) * nb * kActTile * 16);
-  const int mode = action_mode(d);
+  const int mode = action_mode(d, skew);
   double2* F = static_cast<double2*>(x);
   double2* t = static_cast<double2*>(traj);
   if (t) QC_HIP(hipMemcpyAsync(t, F, size_t(d) * 16, hipMemcpyDeviceToDevice, st));
@@ -736,7 +768,7 @@ int run_action(const void* Ov, int64_t M, int64_t d, void* x, void* traj, double
     int64_t s = 1;
     if (!(nu <= 1.7976931348623157e308) || !std::isfinite(m_n.x) || !std::isfinite(m_n.y)) {
       m = -1;   // non-finite generator: the state becomes NaN
-      g_host_status.fetch_or(STATUS_NONFINITE);
+      flag_host_status(STATUS_NONFINITE);
     } else if (nu > 0.0) {
       action_params(nu, tol, &m, &s);
       if (m == 0 || double(m) * double(s) > kMaxActionTerms)
@@ -784,6 +816,21 @@ int run_action(const void* Ov, int64_t M, int64_t d, void* x, void* traj, double
   return QCHEFF_OK;
 }
 
+// y = U x: 16-byte row loads where the rows are 16-byte aligned (complex128, or
+// complex64 with an even d), x in LDS up to d = 2048.
+template <typename C2>
+void launch_matvec(const C2* U, const double2* x, double2* y, int64_t d, hipStream_t st) {
+  const dim3 grid(nblocks(d, 4)), block(256);
+  if ((sizeof(C2) == 16 || d % 2 == 0) && reinterpret_cast<uintptr_t>(U) % 16 == 0) {
+    if (d <= 2048)
+      hipLaunchKernelGGL((matvec16_kernel<C2, true>), grid, block, size_t(d) * 16, st, U, x, y, int(d));
+    else
+      hipLaunchKernelGGL((matvec16_kernel<C2, false>), grid, block, 0, st, U, x, y, int(d));
+  } else {
+    hipLaunchKernelGGL(matvec_kernel<C2>, grid, block, 0, st, U, x, y, int(d));
+  }
+}
+
 template <typename T>
 int run_propagate(const void* Uv, int64_t M, int64_t d, int mode, void* x, void* traj, void* ws, hipStream_t st) {
   using C2 = typename Cx<T>::t;
@@ -797,7 +844,7 @@ int run_propagate(const void* Uv, int64_t M, int64_t d, int mode, void* x, void*
     const double2* cur = psi;
     for (int64_t n = 0; n < M; ++n) {
       double2* nxt = t ? t + (n + 1) * d : buf[n & 1];
-      hipLaunchKernelGGL(matvec_kernel<C2>, dim3(nblocks(d, 4)), dim3(256), 0, st, U + n * dd, cur, nxt, int(d));
+      launch_matvec<C2>(U + n * dd, cur, nxt, d, st);
       QC_HIP(hipGetLastError());
       cur = nxt;
     }
@@ -868,14 +915,16 @@ int qcheff_expm_batched(const void* omega, int64_t batch, int64_t d, int dtype, 
                         size_t ws_bytes, void* stream) {
   const bool skew = (dtype & QCHEFF_SKEW_HERMITIAN) != 0;
   const bool refine = (dtype & QCHEFF_UNITARY_REFINE) != 0;
+  const bool out64 = (dtype & QCHEFF_OUT_C128) != 0;
   const int bound = ((dtype >> 16) & 0xff) - 1;   // -1: none
-  dtype &= ~(QCHEFF_SKEW_HERMITIAN | QCHEFF_UNITARY_REFINE | (0xff << 16));
+  dtype &= ~(QCHEFF_SKEW_HERMITIAN | QCHEFF_UNITARY_REFINE | QCHEFF_OUT_C128 | (0xff << 16));
   const bool bf16x3 = dtype == QCHEFF_C64_BF16X3;
   if (bf16x3) dtype = QCHEFF_C64;
-  Check c = check_expm(omega, batch, d, dtype, U, ws, ws_bytes);
-  if (c.status) return fail(c);
   if (refine && (dtype != QCHEFF_C64 || !skew))
     return fail(QCHEFF_EINVAL, "QCHEFF_UNITARY_REFINE takes QCHEFF_C64 (or _BF16X3) with QCHEFF_SKEW_HERMITIAN");
+  if (out64 && !refine) return fail(QCHEFF_EINVAL, "QCHEFF_OUT_C128 needs QCHEFF_UNITARY_REFINE");
+  Check c = check_expm(omega, batch, d, dtype, U, ws, ws_bytes, out64 ? QCHEFF_C128 : dtype);
+  if (c.status) return fail(c);
   if (batch == 0) return QCHEFF_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (bound < 0 && d > kSmallD) {
@@ -886,8 +935,9 @@ int qcheff_expm_batched(const void* omega, int64_t batch, int64_t d, int dtype, 
                               "qcheff_expm_batched: a stream under graph capture needs QCHEFF_SQUARING_BOUND(n)"));
   }
   return dtype == QCHEFF_C128
-             ? run_expm<double>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, skew, bound, false, false, st)
-             : run_expm<float>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, skew, bound, bf16x3, refine, st);
+             ? run_expm<double>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, skew, bound, false, false, false, st)
+             : run_expm<float>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, skew, bound, bf16x3, refine, out64,
+                               st);
 }
 
 int qcheff_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, void* x, void* traj, void* ws,
@@ -901,11 +951,13 @@ int qcheff_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, v
 
 int qcheff_propagate_action(const void* omega, int64_t M, int64_t d, int dtype, void* x, void* traj, double tol,
                             void* ws, size_t ws_bytes, void* stream) {
+  const bool skew = (dtype & QCHEFF_SKEW_HERMITIAN) != 0;
+  dtype &= ~QCHEFF_SKEW_HERMITIAN;
   Check c = check_action(omega, M, d, dtype, x, tol, ws, ws_bytes);
   if (c.status) return fail(c);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  return dtype == QCHEFF_C128 ? run_action<double>(omega, M, d, x, traj, tol, ws, ws_bytes, st)
-                              : run_action<float>(omega, M, d, x, traj, tol, ws, ws_bytes, st);
+  return dtype == QCHEFF_C128 ? run_action<double>(omega, M, d, x, traj, tol, ws, ws_bytes, skew, st)
+                              : run_action<float>(omega, M, d, x, traj, tol, ws, ws_bytes, skew, st);
 }
 
 int qcheff_propagate_batched(const void* U, int64_t B, int64_t M, int64_t d, int dtype, void* x, void* stream) {
@@ -932,14 +984,19 @@ const char* qcheff_last_error(void) { return g_last_error.c_str(); }
 
 int qcheff_sync_status(void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
-  QC_HIP(hipStreamSynchronize(st));
+  int dev = 0;
+  QC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(QCHEFF_EDEVICE, "device index out of range");
   unsigned w = 0;
-  QC_HIP(hipMemcpyFromSymbol(&w, HIP_SYMBOL(status_word), sizeof(w), 0, hipMemcpyDeviceToHost));
-  if (w) {
-    const unsigned zero = 0;
-    QC_HIP(hipMemcpyToSymbol(HIP_SYMBOL(status_word), &zero, sizeof(zero), 0, hipMemcpyHostToDevice));
+  {
+    // take and clear the word on the stream (after its earlier work), then read it
+    std::lock_guard<std::mutex> lk(g_status_mu);
+    hipLaunchKernelGGL(take_status_kernel, dim3(1), dim3(1), 0, st);
+    QC_HIP(hipGetLastError());
+    QC_HIP(hipMemcpyFromSymbolAsync(&w, HIP_SYMBOL(status_taken), sizeof(w), 0, hipMemcpyDeviceToHost, st));
+    QC_HIP(hipStreamSynchronize(st));
   }
-  w |= g_host_status.exchange(0);
+  w |= g_host_status[dev].exchange(0);
   if (w & STATUS_NONFINITE) return fail(QCHEFF_ENONFINITE, "a generator or its norm was not finite");
   if (w & STATUS_ZERO_PIVOT) return fail(QCHEFF_ENONFINITE, "a Pade denominator had a zero pivot");
   return QCHEFF_OK;

@@ -2,6 +2,7 @@
 //
 //   C_b = alpha * A_b B_b + beta * C_b + sum_i xc[i] X_{i,b} + gamma * I      (EPI_STD)
 //   aug_b[:, :N] = V_b - A_b B_b,  aug_b[:, off:off+N] = V_b + A_b B_b (FP64)  (EPI_AUG)
+//   aug_b = X_{0,b} + alpha * A_b B_b, formed and written in FP64            (EPI_OUT64)
 //
 // A complex product is four real MFMA products on planar operands:
 //   Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br.
@@ -18,7 +19,7 @@
 
 namespace qcheff {
 
-enum { EPI_STD = 0, EPI_AUG = 1 };
+enum { EPI_STD = 0, EPI_AUG = 1, EPI_OUT64 = 2 };
 
 // Kernel ids of the timing instrumentation (match QCHEFF_KERNEL_* in qcheff.h).
 enum { KERNEL_GEMM_F32 = 1, KERNEL_GEMM_F64 = 2, KERNEL_GEMM_BF16X3 = 3, KERNEL_ACTION = 4 };
@@ -42,11 +43,11 @@ template <typename T> struct GemmParams {
   int cfg;                      // tile configuration (GemmTile<T, cfg>)
   int herm;                     // 0: general; +1 / -1: the result is Hermitian / skew-Hermitian
                                 // (M == N, BM == BN): only the upper triangle of tiles runs
-  int epi;                      // EPI_STD or EPI_AUG
+  int epi;                      // EPI_STD, EPI_AUG or EPI_OUT64
   int sq;                       // 1: squaring mode (sq_* fields)
   int nx;                       // number of X terms (0..3); X share C's ld and stride
   const C2* X[3]; T xc[3];
-  // EPI_AUG target (FP64 always)
+  // EPI_AUG / EPI_OUT64 target (FP64 always)
   double2* aug; int64_t ld_aug, s_aug, aug_off;
   // squaring mode: A = B = in, C = out, chosen per item from the remaining count
   const int* sq_s; int sq_step; C2* sq_p0; C2* sq_p1;
@@ -129,7 +130,13 @@ __device__ __forceinline__ void tile_epilogue(const GemmParams<T>& p, const Tile
         if (r >= p.M || c >= p.N) continue;
         if (p.herm && r > c) continue;   // written as the mirror of (c, r)
         const int64_t off = int64_t(r) * p.ldc + c;
-        if (p.epi == EPI_AUG) {
+        if (p.epi == EPI_OUT64) {
+          // a small correction added to X_0 in FP64: X_0's value is exact there
+          const C2 xv = p.X[0][b * p.sC + off];
+          p.aug[b * p.s_aug + int64_t(r) * p.ld_aug + c] =
+              make_double2(double(xv.x) + double(p.alpha * accr[i][j][e]),
+                           double(xv.y) + double(p.alpha * acci[i][j][e]));
+        } else if (p.epi == EPI_AUG) {
           // U = A W is skew-Hermitian here and V Hermitian: q = V - U, p = V + U,
           // and below the diagonal q(c, r) = conj(p(r, c)), p(c, r) = conj(q(r, c))
           C2 v = p.X[0][b * p.sC + off];

@@ -54,7 +54,13 @@ template <> __device__ __forceinline__ double2 czero<double2>() { return make_do
 // Sticky status of the kernels on this device, read and cleared by
 // qcheff_sync_status: bit 0 a non-finite norm, bit 1 a zero pivot.
 __device__ unsigned status_word;
+// Where qcheff_sync_status's one-thread kernel leaves the word it took.
+__device__ unsigned status_taken;
 enum : unsigned { STATUS_NONFINITE = 1u, STATUS_ZERO_PIVOT = 2u };
 __device__ __forceinline__ void flag_status(unsigned bits) { atomicOr(&status_word, bits); }
+
+// Takes the status word and clears it in one atomic step, so that a flag set by
+// a kernel on another stream in between is kept for the next call, not lost.
+__global__ void take_status_kernel() { status_taken = atomicExch(&status_word, 0u); }
 
 }  // namespace qcheff

@@ -94,7 +94,8 @@ __device__ __forceinline__ void small_gemm(typename Cx<T>::t (*C)[kSmallD + 1],
 
 template <typename T>
 __global__ __launch_bounds__(256) void expm_small_kernel(const typename Cx<T>::t* __restrict__ omega,
-                                                         typename Cx<T>::t* __restrict__ U, int* __restrict__ s_out,
+                                                         typename Cx<T>::t* __restrict__ U,
+                                                         double2* __restrict__ U64, int* __restrict__ s_out,
                                                          int d, int batch, double theta, int refine) {
   using C2 = typename Cx<T>::t;
   using Acc = typename Cx<T>::acc;
@@ -279,7 +280,6 @@ __global__ __launch_bounds__(256) void expm_small_kernel(const typename Cx<T>::t
       __syncthreads();
       cur = nxt;
     }
-    C2* dst = U + item * dd;
     if (refine) {
       // One Newton step of the polar decomposition in FP64 (the FP32 squarings
       // leave |eigenvalues| off 1 by about 2^s u32): E = I - R R^dag, then
@@ -306,12 +306,18 @@ __global__ __launch_bounds__(256) void expm_small_kernel(const typename Cx<T>::t
           ci += a.x * double(b.y) + a.y * double(b.x);
         }
         const C2 v = Mx[cur][i][j];
-        C2 o;
-        o.x = T(double(v.x) + 0.5 * cr);
-        o.y = T(double(v.y) + 0.5 * ci);
-        dst[e] = o;
+        const double2 r = make_double2(double(v.x) + 0.5 * cr, double(v.y) + 0.5 * ci);
+        if (U64) {   // kept in FP64
+          U64[item * dd + e] = r;
+        } else {
+          C2 o;
+          o.x = T(r.x);
+          o.y = T(r.y);
+          U[item * dd + e] = o;
+        }
       }
     } else {
+      C2* dst = U + item * dd;
       const double er = exp(mu.x), pr = er * cos(mu.y), pi = er * sin(mu.y);
       for (int e = tid; e < d * d; e += 256) {
         const C2 v = Mx[cur][e / d][e % d];

@@ -34,26 +34,67 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
 
 // ------------------------------------------------------------ coefficients
 //
-// One thread per interval n; the interval's s samples are read in order.
+// One wave per interval n.  The interval's s samples are taken in rounds of 64
+// consecutive samples, one per lane, so every load of a round is one coalesced
+// 512-byte read.
 //   c1[n][k]    = dt * sum_j u_k[j]
 //   c2[n][k]    = dt^2 * sum_j (s - 1 - 2j) u_k[j]
 //   c2[n][K+p]  = dt^2 * sum_j (u_k[j] P_l[j] - u_l[j] P_k[j]),  P[j] = sum_{i<j} u[i]
-__global__ void coeffs_kernel(const double* __restrict__ u, int K, int64_t N, int64_t M, int64_t s,
-                              double dt, int order, double* __restrict__ c1, double* __restrict__ c2) {
-  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (n >= M) return;
+// Each lane keeps compensated (Neumaier) sums of its samples; the 64 partial
+// sums are combined by a fixed tree of error-free additions (Knuth's two-sum),
+// so the result does not depend on timing.  The prefix sums P come from a scan
+// across the lanes of each round plus the running total of earlier rounds.
+
+// s + e = a + b exactly, s = fl(a + b) (Knuth's two-sum).
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Sum over the wave of the lanes' (sum, compensation) pairs; valid in lane 0.
+__device__ __forceinline__ double wave_sum_compensated(double s, double c) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double so = __shfl_down(s, off), co = __shfl_down(c, off);
+    double t, e;
+    two_sum(s, so, t, e);
+    s = t;
+    c += co + e;
+  }
+  return s + c;
+}
+
+// Inclusive prefix sum of x over the lanes of a wave.
+__device__ __forceinline__ double wave_inclusive_scan(double x, int lane) {
+  for (int off = 1; off < 64; off <<= 1) {
+    const double y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+__global__ __launch_bounds__(256) void coeffs_kernel(const double* __restrict__ u, int K, int64_t N, int64_t M,
+                                                     int64_t s, double dt, int order, double* __restrict__ c1,
+                                                     double* __restrict__ c2) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (n >= M) return;   // a whole wave leaves together
   const int64_t base = n * s;
   const int P2 = K + K * (K - 1) / 2;
   for (int k = 0; k < K; ++k) {
     const double* uk = u + int64_t(k) * N + base;
     Neumaier sum, wsum;
-    for (int64_t j = 0; j < s; ++j) {
+    for (int64_t j = lane; j < s; j += 64) {
       const double x = uk[j];
       sum.add(x);
       if (order == 2) wsum.add(double(s - 1 - 2 * j) * x);
     }
-    c1[n * K + k] = dt * sum.value();
-    if (order == 2) c2[n * P2 + k] = dt * dt * wsum.value();
+    const double c1v = wave_sum_compensated(sum.s, sum.c);
+    const double c20 = wave_sum_compensated(wsum.s, wsum.c);
+    if (lane == 0) {
+      c1[n * K + k] = dt * c1v;
+      if (order == 2) c2[n * P2 + k] = dt * dt * c20;
+    }
   }
   if (order != 2) return;
   int p = K;
@@ -61,15 +102,20 @@ __global__ void coeffs_kernel(const double* __restrict__ u, int K, int64_t N, in
     for (int l = k + 1; l < K; ++l, ++p) {
       const double* uk = u + int64_t(k) * N + base;
       const double* ul = u + int64_t(l) * N + base;
-      Neumaier acc, Pk, Pl;
-      for (int64_t j = 0; j < s; ++j) {
-        const double xk = uk[j], xl = ul[j];
-        acc.add(xk * Pl.value());
-        acc.add(-(xl * Pk.value()));
-        Pk.add(xk);
-        Pl.add(xl);
+      Neumaier acc;
+      double carry_k = 0.0, carry_l = 0.0;   // sums of the earlier rounds
+      for (int64_t j0 = 0; j0 < s; j0 += 64) {
+        const int64_t j = j0 + lane;
+        const double xk = j < s ? uk[j] : 0.0, xl = j < s ? ul[j] : 0.0;
+        const double ik = wave_inclusive_scan(xk, lane), il = wave_inclusive_scan(xl, lane);
+        const double pk = carry_k + (ik - xk), pl = carry_l + (il - xl);   // exclusive prefixes
+        acc.add(xk * pl);
+        acc.add(-(xl * pk));
+        carry_k += __shfl(ik, 63);
+        carry_l += __shfl(il, 63);
       }
-      c2[n * P2 + p] = dt * dt * acc.value();
+      const double v = wave_sum_compensated(acc.s, acc.c);
+      if (lane == 0) c2[n * P2 + p] = dt * dt * v;
     }
   }
 }
@@ -149,39 +195,77 @@ __global__ __launch_bounds__(256) void generators_kernel(const double2* __restri
 
 // ------------------------------------------------------ norm and scaling
 //
-// Column sums of |Omega| in FP64 (one thread per column), maximum per item
-// by an atomic max on the IEEE bit pattern (monotone for non-negative values).
+// Column sums of |Omega - mu I| in FP64 in two launches.  The first reads a
+// 64-column by 128-row tile per workgroup (each wave one row at a time, so a
+// wave's load is 64 consecutive elements of a row; eight rows in flight per
+// lane) and writes the tile's partial column sums; the second adds the row
+// tiles' partials of each column in a fixed order and takes the largest column
+// sum (a NaN wins), so the result is deterministic.
+constexpr int kNormRows = 128;   // rows per partial sum
+
 template <typename C2>
-__global__ __launch_bounds__(256) void norm1_kernel(const C2* __restrict__ X, int d, const double2* __restrict__ mu,
-                                                    unsigned long long* __restrict__ norms) {
-  const int b = blockIdx.y;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void norm1_partial_kernel(const C2* __restrict__ X, int d,
+                                                            const double2* __restrict__ mu,
+                                                            double* __restrict__ partial) {
+  const int b = blockIdx.z, rt = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = blockIdx.x * 64 + lane;
+  const int r0 = rt * kNormRows;
+  const int r1 = min(d, r0 + kNormRows);
   const double2 m = mu ? mu[b] : make_double2(0.0, 0.0);   // the norm is of X - mu I
+  const C2* Xb = X + int64_t(b) * d * d;
+  const int cc = min(col, d - 1);
   double sum = 0.0;
-  if (j < d) {
-    const C2* col = X + int64_t(b) * d * d + j;
-    for (int i = 0; i < d; ++i) {
-      const C2 v = col[int64_t(i) * d];
-      double x = double(v.x), y = double(v.y);
-      if (i == j) {
-        x -= m.x;
-        y -= m.y;
+  for (int i0 = r0 + wave; i0 < r1; i0 += 4 * 8) {
+    C2 v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int i = i0 + 4 * t;
+      v[t] = Xb[int64_t(min(i, d - 1)) * d + cc];
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int i = i0 + 4 * t;
+      if (i < r1) {
+        double x = double(v[t].x), y = double(v[t].y);
+        if (i == col) {
+          x -= m.x;
+          y -= m.y;
+        }
+        sum += sqrt(x * x + y * y);
       }
-      sum += sqrt(x * x + y * y);
     }
   }
+  __shared__ double red[4][64];
+  red[wave][lane] = sum;
+  __syncthreads();
+  if (wave == 0 && col < d) {
+    const double t = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    partial[(int64_t(b) * gridDim.y + rt) * d + col] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void norm1_finish_kernel(const double* __restrict__ partial, int d, int tiles,
+                                                           unsigned long long* __restrict__ norms) {
+  const int b = blockIdx.x;
+  const double* pb = partial + int64_t(b) * tiles * d;
+  double best = 0.0;
+  for (int j = threadIdx.x; j < d; j += blockDim.x) {
+    double c = 0.0;
+    for (int t = 0; t < tiles; ++t) c += pb[int64_t(t) * d + j];
+    if (c > best || c != c) best = c;   // a comparison with NaN is false: test it explicitly
+  }
   __shared__ double red[256];
-  red[threadIdx.x] = sum;
+  red[threadIdx.x] = best;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
       const double o = red[threadIdx.x + w];
-      // propagate NaN: a comparison with NaN is false, so test it explicitly
       if (o > red[threadIdx.x] || o != o) red[threadIdx.x] = o;
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicMax(norms + b, (unsigned long long)__double_as_longlong(red[0]));
+  if (threadIdx.x == 0) norms[b] = (unsigned long long)__double_as_longlong(red[0]);
 }
 
 // s = smallest s >= 0 with nrm <= theta * 2^s (exact comparisons); -1 if nrm is not finite.
@@ -333,6 +417,65 @@ __global__ __launch_bounds__(256) void to_c64_kernel(const double2* __restrict__
 // ---------------------------------------------------------------- chain
 //
 // y = U x with U in C2 (FP32 or FP64) and x, y in FP64; one wave per row.
+// A lane reads the row in 16-byte pieces (two complex64 values or one
+// complex128), eight pieces in flight before any arithmetic; x is staged in LDS
+// when it fits (XLDS).  Complex64 rows need an even d (16-byte aligned rows);
+// matvec_kernel below takes any d.
+template <typename C2> struct Vec16;
+template <> struct Vec16<float2> { using t = float4; static constexpr int per = 2; };
+template <> struct Vec16<double2> { using t = double2; static constexpr int per = 1; };
+
+template <typename C2, bool XLDS>
+__global__ __launch_bounds__(256) void matvec16_kernel(const C2* __restrict__ U, const double2* __restrict__ x,
+                                                       double2* __restrict__ y, int d) {
+  using V = typename Vec16<C2>::t;
+  constexpr int PER = Vec16<C2>::per;
+  extern __shared__ double2 xs[];   // [d] when XLDS
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + wave;
+  const bool active = row < d;
+  const int nch = d / PER;   // 16-byte pieces per row
+  const V* ur = reinterpret_cast<const V*>(U + int64_t(active ? row : 0) * d);
+  V buf[8];
+  auto load = [&](int c0) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int c = c0 + lane + 64 * t;
+      buf[t] = ur[c < nch ? c : 0];
+    }
+  };
+  load(0);   // the first pieces are in flight while x is staged
+  if constexpr (XLDS) {
+    for (int i = threadIdx.x; i < d; i += blockDim.x) xs[i] = x[i];
+    __syncthreads();
+  }
+  const double2* xv = XLDS ? xs : x;
+  double ar = 0.0, ai = 0.0;
+  for (int c0 = 0; c0 < nch; c0 += 512) {
+    if (c0 > 0) load(c0);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int c = c0 + lane + 64 * t;
+      if (c < nch) {
+        const C2* e = reinterpret_cast<const C2*>(&buf[t]);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const double2 v = xv[c * PER + q];
+          const double ur_ = double(e[q].x), ui_ = double(e[q].y);
+          ar += ur_ * v.x - ui_ * v.y;
+          ai += ur_ * v.y + ui_ * v.x;
+        }
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    ar += __shfl_down(ar, off);
+    ai += __shfl_down(ai, off);
+  }
+  if (active && lane == 0) y[row] = make_double2(ar, ai);
+}
+
+// Any d: one 8- or 16-byte element per lane per step.
 template <typename C2>
 __global__ __launch_bounds__(256) void matvec_kernel(const C2* __restrict__ U, const double2* __restrict__ x,
                                                      double2* __restrict__ y, int d) {

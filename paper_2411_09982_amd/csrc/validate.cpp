@@ -88,17 +88,22 @@ int64_t expm_chunk(size_t ws_bytes, int64_t batch, int64_t d, int dtype) {
 }
 
 Check check_expm(const void* omega, int64_t batch, int64_t d, int dtype, const void* U,
-                 const void* ws, size_t ws_bytes) {
+                 const void* ws, size_t ws_bytes, int out_dtype) {
+  if (out_dtype == 0) out_dtype = dtype;
   if (batch < 0) return Check::fail(QCHEFF_EINVAL, "batch must be >= 0");
   if (d < 1 || d > kMaxDim) return Check::fail(QCHEFF_EINVAL, "d must be in [1, 16384]");
   if (elem_bytes(dtype) == 0) return Check::fail(QCHEFF_EINVAL, "unknown dtype");
   if (batch == 0) return Check::ok();
   if (!omega || !U) return Check::fail(QCHEFF_EINVAL, "omega and U must not be NULL");
-  if (omega != U) {   // the same buffer, or two that do not overlap (U serves as scratch)
-    const size_t bytes = size_t(batch) * size_t(d) * size_t(d) * elem_bytes(dtype);
+  {
+    // the same buffer (same element type), or two that do not overlap (U serves as scratch)
+    const size_t dd = size_t(batch) * size_t(d) * size_t(d);
+    const size_t ob = dd * elem_bytes(dtype), ub = dd * elem_bytes(out_dtype);
     const uintptr_t o = reinterpret_cast<uintptr_t>(omega), u = reinterpret_cast<uintptr_t>(U);
-    if (o < u + bytes && u < o + bytes)
-      return Check::fail(QCHEFF_EINVAL, "U must be omega itself or not overlap it");
+    const bool same = omega == U && out_dtype == dtype;
+    if (!same && o < u + ub && u < o + ob)
+      return Check::fail(QCHEFF_EINVAL, out_dtype == dtype ? "U must be omega itself or not overlap it"
+                                                           : "a complex128 U must not overlap omega");
   }
   if (!ws) return Check::fail(QCHEFF_EWORKSPACE, "workspace must not be NULL");
   if (expm_chunk(ws_bytes, batch, d, dtype) < 1)

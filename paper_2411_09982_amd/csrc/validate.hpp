@@ -31,8 +31,10 @@ Check check_generators(const void* H0, const void* Hk, int64_t d, int64_t K, int
                        const void* c1, const void* c2, int64_t M, double dt_interval, int order,
                        int out_dtype, const void* omega, const void* ws, size_t ws_bytes,
                        unsigned flags);
+// out_dtype: the element type of U (dtype, or QCHEFF_C128 for an FP64 result
+// of the FP32 path); 0 means dtype.
 Check check_expm(const void* omega, int64_t batch, int64_t d, int dtype, const void* U,
-                 const void* ws, size_t ws_bytes);
+                 const void* ws, size_t ws_bytes, int out_dtype = 0);
 Check check_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, const void* x,
                       const void* traj, const void* ws, size_t ws_bytes);
 

@@ -62,6 +62,7 @@ class Result:
     admitted: float
     done: float
     path: str = "propagators"
+    finite: bool = True       # False: a generator norm or a Pade pivot was not finite (the state is NaN)
 
     @property
     def latency(self) -> float:
@@ -71,10 +72,13 @@ class Result:
 def job_bytes(d: int, K: int, M: int, order: int, precision: str, chunk: int, ws_fn=None,
               path: str = "propagators") -> int:
     """Device bytes one job holds while it runs: inputs, Omega/U (all M intervals
-    for the propagators, one chunk for the action), workspaces, state."""
+    for the propagators, one chunk for the action; complex64 propagators are
+    refined into a separate complex128 U), workspaces, state."""
     eb = 8 if precision == "c64" else 16
     inputs = (1 + K) * d * d * 16
     omega = (M if path == "propagators" else min(chunk, M)) * d * d * eb
+    if path == "propagators" and precision == "c64":
+        omega += M * d * d * 16
     coeffs = M * (2 * K + K * (K - 1) // 2) * 8
     ws = ws_fn(d, K, M, order, precision, chunk) if ws_fn else 0
     return inputs + omega + coeffs + ws + 4 * d * 16
@@ -144,7 +148,7 @@ class Server:
         if path == "action":
             return gen + q.workspace_bytes(q.FN_ACTION, min(chunk, M), d, 1, 1, code)
         return (gen + q.workspace_bytes(q.FN_EXPM, min(chunk, M), d, 1, 1, code)
-                + q.workspace_bytes(q.FN_PROPAGATE, M, d, 1, q.STATE, code))
+                + q.workspace_bytes(q.FN_PROPAGATE, M, d, 1, q.STATE, q.C128))
 
     def bytes_for(self, r: Request) -> int:
         path = path_for(r)
@@ -172,14 +176,22 @@ class Server:
                     N = r.u.shape[1]
                     omega, _ = q.magnus_generators(H0, Hk, c1, c2, r.dt_sample * (N // r.M), r.order, dtype,
                                                    stream=st)
-                    U, s = q.expm_batched(omega, U=omega, chunk=self.chunk, stream=st, skew_hermitian=True,
-                                          unitary_refine=omega.dtype == torch.complex64)
+                    # complex64: refined to unitarity and kept in complex128 (as evolve does)
+                    fp32 = omega.dtype == torch.complex64
+                    U, s = q.expm_batched(omega, U=None if fp32 else omega, chunk=self.chunk, stream=st,
+                                          skew_hermitian=True, unitary_refine=fp32, out_c128=fp32)
+                    del omega
                     q.propagate(U, q.STATE, psi, stream=st)
                     s_max = int(s.max().cpu())
                 psi_h = psi.cpu().numpy()
                 st.synchronize()
+                # The library's status flags are per device and cannot name the job
+                # that raised them; a job's own result says whether it is finite.
+                # Taking the flags here keeps them from piling up across jobs.
+                q.sync_status(st)
             done = time.perf_counter() - self.t0
-            res = Result(r.rid, psi_h, s_max, r.arrival, admitted, done, path)
+            res = Result(r.rid, psi_h, s_max, r.arrival, admitted, done, path,
+                         finite=bool(np.isfinite(psi_h).all()))
             with self.lock:
                 self.results[r.rid] = res
         except BaseException as e:  # noqa: BLE001 - reported to the caller

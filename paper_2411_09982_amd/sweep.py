@@ -55,6 +55,9 @@ class Sweep:
             g["c2"] = [torch.empty((M, jobs[i].K * (jobs[i].K + 1) // 2), dtype=torch.float64, device=device)
                        if jobs[i].order == 2 else None for i in idx]
             g["omega"] = torch.empty((len(idx) * M, d, d), dtype=dtype, device=device)
+            # complex64 propagators are refined to unitarity and kept in complex128
+            g["U"] = (torch.empty((len(idx) * M, d, d), dtype=torch.complex128, device=device)
+                      if dtype == torch.complex64 else g["omega"])
             g["psi0"] = torch.from_numpy(np.stack([jobs[i].psi0 for i in idx])).to(device)
             g["psi"] = torch.empty_like(g["psi0"])
             gw = q.workspace_bytes(q.FN_GENERATORS, 1, d, Kmax, 2, q.C128)
@@ -67,6 +70,7 @@ class Sweep:
             g["bound"] = None
             self.groups.append(g)
         # complex64 propagators are refined to unitarity after their FP32 squarings
+        # (and kept in complex128)
         self.refine = dtype == torch.complex64
         self.margin = 1
         self.replays = 0
@@ -82,10 +86,10 @@ class Sweep:
             q.magnus_coeffs(u, j.dt_sample, M, j.order, c1=g["c1"][k], c2=g["c2"][k])
             q.magnus_generators(H0, Hk, g["c1"][k], g["c2"][k], j.dt_interval, j.order, self.dtype,
                                 omega=g["omega"][k * M:(k + 1) * M], ws=g["gen_ws"])
-        q.expm_batched(g["omega"], U=g["omega"], s_out=g["s"], ws=g["exp_ws"], skew_hermitian=True,
-                       squaring_bound=bound, unitary_refine=self.refine)
+        q.expm_batched(g["omega"], U=g["U"], s_out=g["s"], ws=g["exp_ws"], skew_hermitian=True,
+                       squaring_bound=bound, unitary_refine=self.refine, out_c128=self.refine)
         g["psi"].copy_(g["psi0"])
-        q.propagate_batched(g["omega"].view(len(g["idx"]), M, d, d), g["psi"])
+        q.propagate_batched(g["U"].view(len(g["idx"]), M, d, d), g["psi"])
 
     def _capture(self, g) -> None:
         torch = self.torch

@@ -28,10 +28,10 @@ def load(name):
 
 
 def check(job, gold, fp64, say):
-    """job: a bench.Job after step() (U_n in job.omega, psi_M in job.psi)."""
+    """job: a bench.Job after step() (U_n in job.U, psi_M in job.psi)."""
     q, w = job.q, job.w
     tol = 1e-12 if fp64 else 1e-6
-    U = job.omega
+    U = job.U
     d = w.d
     # every interval's trace
     tr = torch.diagonal(U, dim1=1, dim2=2).to(torch.complex128).sum(dim=1).cpu().numpy()

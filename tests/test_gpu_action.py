@@ -41,7 +41,7 @@ def test_action_parity(d, dtype, kernel, monkeypatch):
     ref, traj_ref = _oracle_chain(seen, psi0)
     x = gpu(psi0)
     traj = torch.empty((len(norms) + 1, d), dtype=torch.complex128, device=DEV)
-    q.propagate_action(gpu(Om).to(dtype), x, traj=traj)
+    q.propagate_action(gpu(Om).to(dtype), x, traj=traj, skew_hermitian=True)
     torch.cuda.synchronize()
     # FP64 arithmetic throughout; the truncation tolerance is the storage's roundoff
     tol = 1e-12 if dtype == torch.complex128 else 4 * len(norms) * 2.0 ** -24
@@ -103,11 +103,29 @@ def test_action_tiles_large_ragged(kernel, monkeypatch):
     out = []
     for _ in range(2):
         x = gpu(psi0)
-        q.propagate_action(gpu(Om), x)
+        q.propagate_action(gpu(Om), x, skew_hermitian=True)
         torch.cuda.synchronize()
         out.append(host(x))
     assert np.abs(out[0] - ref).max() <= 1e-12
     assert np.array_equal(out[0], out[1])
+
+
+def test_action_general_generators_large():
+    # d = 2100 generators that are not skew-Hermitian, passed without the
+    # declaration: every product reads the whole matrix (a triangle-only read would
+    # miss the Hermitian part), against scipy's expm
+    import scipy.linalg as sl
+    d = 2100
+    say(f"action d={d} general generators")
+    g = np.random.default_rng(2101)
+    Om = wl.random_skew_hermitian_batch(1, d, 3.0, config_id=2101)[0]
+    Om = Om + 0.05 * wl.random_hermitian(d, g, 1.0 / np.sqrt(d))
+    psi0 = wl.random_state(d, 22)
+    ref = sl.expm(Om) @ psi0
+    x = gpu(psi0)
+    q.propagate_action(gpu(Om[None]), x)
+    torch.cuda.synchronize()
+    assert np.abs(host(x) - ref).max() <= 1e-11 * max(1.0, np.abs(ref).max())
 
 
 def test_action_more_intervals_than_grid_rows():

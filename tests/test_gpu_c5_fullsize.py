@@ -84,7 +84,7 @@ def test_c5_chain_prefix_all_precisions(job):
         ii = torch.arange(PREFIX, device=DEV)
         om, _ = q.magnus_generators(H0, Hk, c1[ii].contiguous(), c2[ii].contiguous(), w.dt_interval, w.order, dtype)
         x = torch.from_numpy(w.psi0).to(DEV)
-        q.propagate_action(om, x)
+        q.propagate_action(om, x, skew_hermitian=True)
         torch.cuda.synchronize()
         psi[prec] = host(x)
         del om

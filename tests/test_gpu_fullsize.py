@@ -44,7 +44,7 @@ def test_transmon_resonator_d1000_full_size(job_and_ref, dt_name):
     assert np.abs(job.c2.cpu().numpy() - c2o).max() <= 1e-13 * np.abs(c2o).max()
     # propagators of sampled intervals
     s = job.s.cpu().numpy()
-    U = job.omega
+    U = job.U
     for j, n in enumerate(SAMPLED):
         Ug = U[n].cpu().numpy().astype(np.complex128)
         inf = abs(oracle.propagator_infidelity(Uo[j], Ug))

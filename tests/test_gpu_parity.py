@@ -57,15 +57,16 @@ def inf_tol(dtype, s, refined=True):
     return np.maximum(INF_TOL[dtype], 4.0 * 2.0 ** np.asarray(s, dtype=float) * U32)
 
 
-EXPM_MODES = ["general", "skew", "refined"]
+EXPM_MODES = ["general", "skew", "refined", "refined_c128"]
 
 
 def expm_mode(mode, dtype):
-    """(skew_hermitian, unitary_refine) of a test mode; None where the mode does not
-    apply (the FP64 path takes no refinement)."""
-    if mode == "refined" and dtype != torch.complex64:
+    """expm_batched keywords of a test mode; None where the mode does not apply
+    (the FP64 path takes no refinement)."""
+    if mode.startswith("refined") and dtype != torch.complex64:
         return None
-    return mode != "general", mode == "refined"
+    return dict(skew_hermitian=mode != "general", unitary_refine=mode.startswith("refined"),
+                out_c128=mode == "refined_c128")
 
 
 # ------------------------------------------------------------ coefficients
@@ -160,10 +161,10 @@ def test_expm_parity(d, dtype, mode):
     # skew: the inputs are declared skew-Hermitian, so the Hermitian Pade
     # products are formed by halves and mirrored; refined: the FP32 result is
     # also refined to unitarity after its squarings
-    flags = expm_mode(mode, dtype)
-    if flags is None:
+    kw = expm_mode(mode, dtype)
+    if kw is None:
         pytest.skip("the FP64 path takes no refinement")
-    skew, refine = flags
+    refine = kw["unitary_refine"]
     say(f"expm d={d} {dtype} {mode}")
     norms = [0.0, 0.01, 1.0, 5.3, 5.4, 11.0, 11.5, 20.0, 170.0, 1500.0]   # s = 0 .. 9
     Om = wl.random_skew_hermitian_batch(len(norms), d, norms, config_id=300 + d)
@@ -171,7 +172,7 @@ def test_expm_parity(d, dtype, mode):
     seen = Om.astype(np.complex64).astype(np.complex128) if dtype == torch.complex64 else Om
     s_ref = [oracle.scaling_exponent(x, shift=(dtype == torch.complex128)) for x in seen]
     om = gpu(Om).to(dtype)
-    U, s = q.expm_batched(om, skew_hermitian=skew, unitary_refine=refine)
+    U, s = q.expm_batched(om, **kw)
     torch.cuda.synchronize()
     Ug = host(U).astype(np.complex128)
     assert list(host(s)) == s_ref
@@ -193,17 +194,17 @@ def test_expm_parity(d, dtype, mode):
 def test_expm_parity_large(d, dtype, mode):
     # d <= 1024 factors with register-resident panels, d > 1024 through the
     # global-memory panel kernel
-    flags = expm_mode(mode, dtype)
-    if flags is None:
+    kw = expm_mode(mode, dtype)
+    if kw is None:
         pytest.skip("the FP64 path takes no refinement")
-    skew, refine = flags
+    refine = kw["unitary_refine"]
     say(f"expm large d={d} {dtype} {mode}")
     norms = [3.0, 60.0, 900.0]
     Om = wl.random_skew_hermitian_batch(len(norms), d, norms, config_id=400 + d)
     ref = oracle.expm_skew_hermitian(Om)
     seen = Om.astype(np.complex64).astype(np.complex128) if dtype == torch.complex64 else Om
     s_ref = [oracle.scaling_exponent(x, shift=(dtype == torch.complex128)) for x in seen]
-    U, s = q.expm_batched(gpu(Om).to(dtype), skew_hermitian=skew, unitary_refine=refine)
+    U, s = q.expm_batched(gpu(Om).to(dtype), **kw)
     torch.cuda.synchronize()
     Ug = host(U).astype(np.complex128)
     assert list(host(s)) == s_ref
@@ -221,19 +222,18 @@ def test_expm_parity_large(d, dtype, mode):
 @pytest.mark.parametrize("d", [20, 45, 200])
 def test_expm_chunked_alias_and_nonfinite(d, dtype, mode):
     # d <= 32 runs the fused one-workgroup kernel, larger d the batched path
-    flags = expm_mode(mode, dtype)
-    if flags is None:
+    kw = expm_mode(mode, dtype)
+    if kw is None:
         pytest.skip("the FP64 path takes no refinement")
-    skew, refine = flags
+    refine = kw["unitary_refine"]
     say(f"expm chunking d={d} {dtype} {mode}")
     B = 7
     Om = wl.random_skew_hermitian_batch(B, d, np.linspace(0.5, 300, B), config_id=77)
     om = gpu(Om).to(dtype)
-    kw = dict(skew_hermitian=skew, unitary_refine=refine)
     U1, s1 = q.expm_batched(om, **kw)                        # one chunk
     U2, s2 = q.expm_batched(om, chunk=3, **kw)               # chunks of 3, 3, 1
     om3 = om.clone()
-    U3, s3 = q.expm_batched(om3, U=om3, chunk=2, **kw)       # in place
+    U3, s3 = q.expm_batched(om3, U=None if kw.get("out_c128") else om3, chunk=2, **kw)   # in place
     torch.cuda.synchronize()
     assert torch.equal(U1, U2) and torch.equal(U1, U3)
     assert torch.equal(s1, s2) and torch.equal(s1, s3)
@@ -268,17 +268,17 @@ def test_expm_skew_matches_general(d, dtype):
     assert np.all(inf <= 2 * inf_tol(dtype, host(ss), refined=False)), inf
 
 
-@pytest.mark.parametrize("dtype,refine", [(torch.complex128, False), (torch.complex64, False),
-                                          (torch.complex64, True)])
-def test_expm_squaring_bound(dtype, refine):
+@pytest.mark.parametrize("dtype,refine,out_c128", [(torch.complex128, False, False), (torch.complex64, False, False),
+                                                   (torch.complex64, True, False), (torch.complex64, True, True)])
+def test_expm_squaring_bound(dtype, refine, out_c128):
     # a bound at or above every exponent changes no bit; items above a smaller
     # bound come back with s = -2 and NaN, the others unchanged
     d = 70
     norms = [0.5, 20.0, 300.0, 6000.0]       # s = 0, 2, 6, 11
     Om = wl.random_skew_hermitian_batch(len(norms), d, norms, config_id=950)
     om = gpu(Om).to(dtype)
-    say(f"expm squaring bound {dtype} refine={refine}")
-    kw = dict(skew_hermitian=True, unitary_refine=refine)
+    say(f"expm squaring bound {dtype} refine={refine} out_c128={out_c128}")
+    kw = dict(skew_hermitian=True, unitary_refine=refine, out_c128=out_c128)
     U0, s0 = q.expm_batched(om, **kw)
     U1, s1 = q.expm_batched(om, squaring_bound=int(s0.max()), **kw)
     U2, s2 = q.expm_batched(om, squaring_bound=20, **kw)
@@ -294,10 +294,10 @@ def test_expm_squaring_bound(dtype, refine):
 def test_expm_capture_needs_a_bound(refine):
     dtype = torch.complex64
     om = gpu(wl.random_skew_hermitian_batch(2, 50, 10.0, config_id=951)).to(dtype)
-    U = torch.empty_like(om)
+    U = torch.empty(om.shape, dtype=torch.complex128 if refine else dtype, device=DEV)
     s = torch.empty(2, dtype=torch.int32, device=DEV)
     ws = torch.empty(q.workspace_bytes(q.FN_EXPM, 2, 50, 1, 1, q.C64), dtype=torch.uint8, device=DEV)
-    kw = dict(skew_hermitian=True, unitary_refine=refine)
+    kw = dict(skew_hermitian=True, unitary_refine=refine, out_c128=refine)
     q.expm_batched(om, U=U, s_out=s, ws=ws, **kw)      # tunes the tile outside capture
     torch.cuda.synchronize()
     ref = U.clone()
@@ -418,6 +418,13 @@ def test_unitary_refine_needs_complex64_skew():
     assert e.value.status == q.EINVAL
     with pytest.raises(q.QcheffError) as e:
         q.expm_batched(om.to(torch.complex64), unitary_refine=True)           # not declared skew-Hermitian
+    assert e.value.status == q.EINVAL
+    om32 = om.to(torch.complex64)
+    with pytest.raises(q.QcheffError) as e:                                   # FP64 output needs the refinement
+        q.expm_batched(om32, skew_hermitian=True, out_c128=True)
+    assert e.value.status == q.EINVAL
+    with pytest.raises(q.QcheffError) as e:                                   # a complex128 U on omega itself
+        q.expm_batched(om32, U=om32, skew_hermitian=True, unitary_refine=True, out_c128=True)
     assert e.value.status == q.EINVAL
 
 

@@ -58,3 +58,23 @@ def test_mix_equals_alone_and_oracle():
         # holds to the target on both paths
         nbound = r.M * 1e-13 if r.precision == "c128" else 1e-6
         assert oracle.norm_error(res[r.rid].psi) <= nbound, r.rid
+
+
+def test_nonfinite_request_is_marked():
+    # a request whose control holds a NaN comes back marked non-finite (its state
+    # is NaN), on either path; the requests beside it are unaffected
+    reqs = []
+    for i, d in enumerate((20, 64, 20, 64)):
+        w = wl.random_system(d, 1, 12 * 5, 12, 2, config_id=800 + i, drift_scale=15.0, drive_scale=3.0)
+        u = w.u.copy()
+        if i >= 2:
+            u[0, 7] = float("nan")
+        reqs.append(Request(i, w.H0, w.Hk, u, w.dt_sample, 12, 2, "c64", w.psi0))
+    say("serving requests with a NaN control")
+    res = Server(budget_bytes=1 << 34, max_slots=4, chunk=CHUNK).run(reqs)
+    assert {path_for(r) for r in reqs} == {"action", "propagators"}
+    for r in reqs:
+        bad = r.rid >= 2
+        assert res[r.rid].finite == (not bad), r.rid
+        assert np.isnan(res[r.rid].psi).all() == bad
+    assert q.sync_status() == q.OK        # the server took the flags

@@ -44,7 +44,7 @@ def test_spin_chain_d1024_full_size(job_and_ref, dt_name):
     assert np.abs(job.c1.cpu().numpy() - c1o).max() <= 1e-14 * np.abs(c1o).max()
     assert np.abs(job.c2.cpu().numpy() - c2o).max() <= 1e-13 * np.abs(c2o).max()
     s = job.s.cpu().numpy()
-    U = job.omega
+    U = job.U
     fp64 = dt_name == "c128"
     for j, n in enumerate(SAMPLED):
         Ug = U[n].cpu().numpy().astype(np.complex128)

@@ -42,7 +42,13 @@ def test_job_bytes_accounting():
     d, K, M = 100, 2, 40
     b64 = job_bytes(d, K, M, 2, "c64", 16)
     b128 = job_bytes(d, K, M, 2, "c128", 16)
-    assert b128 - b64 == M * d * d * 8
+    # complex64 generators (8 B) plus the refined complex128 propagators (16 B)
+    # against complex128 generators overwritten in place by U (16 B)
+    assert b64 - b128 == M * d * d * 8
+    # the action holds one chunk of generators and no propagators
+    a64 = job_bytes(d, K, M, 2, "c64", 16, path="action")
+    a128 = job_bytes(d, K, M, 2, "c128", 16, path="action")
+    assert a128 - a64 == 16 * d * d * 8
     assert job_bytes(d, K, M, 2, "c64", 16, lambda *a: 1000) == b64 + 1000
 
 
@@ -74,7 +80,8 @@ def test_path_choice_and_action_memory():
                        "c64", np.eye(d, dtype=complex)[0], path=path)
     assert path_for(req(32)) == "propagators" and path_for(req(33)) == "action"
     assert path_for(req(500, "propagators")) == "propagators" and path_for(req(8, "action")) == "action"
-    # the action holds one chunk of generators, the propagators all M
+    # the action holds one chunk of generators, the propagators all M of them
+    # (complex64) and all M refined propagators (complex128)
     d, K, M, chunk = 100, 2, 40, 8
     assert (job_bytes(d, K, M, 2, "c64", chunk, path="propagators") - job_bytes(d, K, M, 2, "c64", chunk, path="action")
-            == (M - chunk) * d * d * 8)
+            == (M - chunk) * d * d * 8 + M * d * d * 16)
