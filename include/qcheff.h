@@ -221,6 +221,24 @@ int qcheff_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, v
                      void* traj, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * qcheff_propagate_state_noalloc - qcheff_propagate in QCHEFF_STATE mode for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * the same results, with the chain's scratch (two state vectors, 2*d
+ * complex128) taken from a 512 KiB array the library holds on each device
+ * from its first use until the process ends, instead of a workspace.  It
+ * allocates nothing and calls no allocating routine.
+ *   U, M, d, dtype, x, traj   as for qcheff_propagate (x is psi [d] complex128).
+ *   d          1 .. 16384 (QCHEFF_EINVAL beyond: the scratch holds 2 * 16384).
+ * Every call on one device shares that device's scratch, which keeps the last
+ * call's contents: calls that overlap on one device (other streams, other
+ * threads) race and must be serialised by the caller.
+ * Returns QCHEFF_OK, QCHEFF_EINVAL, QCHEFF_EDEVICE.
+ */
+int qcheff_propagate_state_noalloc(const void* U, int64_t M, int64_t d, int dtype, void* x, void* traj,
+                                   void* stream);
+
+/*
  * qcheff_propagate_batched - B independent state chains of equal dimension
  * (parameter sweeps, batches of jobs): chain b computes
  * x[b] <- U[b][M-1] ... U[b][0] x[b], the stroboscopic evolution of Sec. 4.1.

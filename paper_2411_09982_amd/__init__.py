@@ -65,9 +65,10 @@ def lib() -> ctypes.CDLL:
     L.qcheff_expm_batched.argtypes = [vp, i64, i64, i32, vp, vp, vp, ctypes.c_size_t, vp]
     L.qcheff_propagate.argtypes = [vp, i64, i64, i32, i32, vp, vp, vp, ctypes.c_size_t, vp]
     L.qcheff_propagate_batched.argtypes = [vp, i64, i64, i64, i32, vp, vp]
+    L.qcheff_propagate_state_noalloc.argtypes = [vp, i64, i64, i32, vp, vp, vp]
     L.qcheff_propagate_action.argtypes = [vp, i64, i64, i32, vp, vp, dbl, vp, ctypes.c_size_t, vp]
     for f in ("qcheff_magnus_coeffs", "qcheff_magnus_generators", "qcheff_expm_batched", "qcheff_propagate",
-              "qcheff_propagate_batched", "qcheff_propagate_action"):
+              "qcheff_propagate_batched", "qcheff_propagate_action", "qcheff_propagate_state_noalloc"):
         getattr(L, f).restype = i32
     L.qcheff_workspace_bytes.argtypes = [i32, i64, i64, i64, i32, i32]
     L.qcheff_workspace_bytes.restype = ctypes.c_size_t
@@ -225,6 +226,17 @@ def propagate(U, mode: int, x, traj=None, ws=None, stream=None):
     _check("qcheff_propagate", lib().qcheff_propagate(
         _ptr(U), M, d, dt, mode, _ptr(x), _ptr(traj), _ptr(ws), 0 if ws is None else ws.numel(),
         _stream(stream)))
+    return x
+
+
+def propagate_state_noalloc(U, x, traj=None, stream=None):
+    """psi <- U_M ... U_1 psi without a workspace (qcheff_propagate_state_noalloc):
+    the library's own per-device scratch; calls that overlap on one device race."""
+    _dev(U, "U")
+    _dev(x, "x")
+    M, d = U.shape[0], U.shape[-1]
+    _check("qcheff_propagate_state_noalloc", lib().qcheff_propagate_state_noalloc(
+        _ptr(U), M, d, _DTYPES[U.dtype], _ptr(x), _ptr(traj), _stream(stream)))
     return x
 
 

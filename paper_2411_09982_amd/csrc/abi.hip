@@ -253,6 +253,32 @@ int action_mode(int64_t d, bool skew) {
   return d >= 2048 ? 1 : 0;
 }
 
+// ------------------------------------------------- allocation-free entry
+//
+// qcheff_propagate_state_noalloc takes the scratch of the state chain (two
+// ping-pong state vectors) from this file-scope device array instead of a
+// caller workspace.  Each device holds its own copy; host code never passes
+// the symbol itself to a kernel: it passes the address hipGetSymbolAddress
+// returned for the current device (kept per device below).
+constexpr int64_t kScratchVecs = 2 * kMaxDim;          // complex128 elements: 512 KiB
+static __device__ __align__(256) double2 scratch[kScratchVecs];
+std::mutex g_scratch_mu;
+double2* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_for_current_device(double2** out) {
+  int dev = 0;
+  QC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(QCHEFF_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    QC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<double2*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return QCHEFF_OK;
+}
+
 // ------------------------------------------------------------------- coeffs
 int run_coeffs(const double* u, int64_t K, int64_t N, double dt, int64_t M, int order, double* c1,
                double* c2, hipStream_t st) {
@@ -947,6 +973,19 @@ int qcheff_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, v
   hipStream_t st = static_cast<hipStream_t>(stream);
   return dtype == QCHEFF_C128 ? run_propagate<double>(U, M, d, mode, x, traj, ws, st)
                               : run_propagate<float>(U, M, d, mode, x, traj, ws, st);
+}
+
+int qcheff_propagate_state_noalloc(const void* U, int64_t M, int64_t d, int dtype, void* x, void* traj,
+                                   void* stream) {
+  Check c = check_propagate(U, M, d, dtype, QCHEFF_STATE, x, traj, nullptr, 0, /*ws_given=*/false);
+  if (c.status) return fail(c);
+  if (2 * d > kScratchVecs)
+    return fail(QCHEFF_EINVAL, "qcheff_propagate_state_noalloc: d exceeds the 16384 its scratch holds");
+  double2* ws = nullptr;
+  if (int r = scratch_for_current_device(&ws)) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return dtype == QCHEFF_C128 ? run_propagate<double>(U, M, d, QCHEFF_STATE, x, traj, ws, st)
+                              : run_propagate<float>(U, M, d, QCHEFF_STATE, x, traj, ws, st);
 }
 
 int qcheff_propagate_action(const void* omega, int64_t M, int64_t d, int dtype, void* x, void* traj, double tol,

@@ -122,7 +122,7 @@ size_t propagate_ws_bytes(int64_t M, int64_t d, int dtype, int mode) {
 }
 
 Check check_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, const void* x,
-                      const void* traj, const void* ws, size_t ws_bytes) {
+                      const void* traj, const void* ws, size_t ws_bytes, bool ws_given) {
   if (mode != QCHEFF_STATE && mode != QCHEFF_PRODUCT) return Check::fail(QCHEFF_EINVAL, "unknown mode");
   if (M < 0) return Check::fail(QCHEFF_EINVAL, "M must be >= 0");
   if (d < 1 || d > kMaxDim) return Check::fail(QCHEFF_EINVAL, "d must be in [1, 16384]");
@@ -131,7 +131,7 @@ Check check_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, 
   if (M > 0 && !U) return Check::fail(QCHEFF_EINVAL, "U must not be NULL");
   if (mode == QCHEFF_PRODUCT && traj) return Check::fail(QCHEFF_EINVAL, "traj is for QCHEFF_STATE only");
   size_t need = propagate_ws_bytes(M, d, dtype, mode);
-  if (M > 0 && need > 0 && (!ws || ws_bytes < need))
+  if (ws_given && M > 0 && need > 0 && (!ws || ws_bytes < need))
     return Check::fail(QCHEFF_EWORKSPACE, "workspace too small");
   return Check::ok();
 }

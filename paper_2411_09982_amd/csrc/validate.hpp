@@ -35,8 +35,10 @@ Check check_generators(const void* H0, const void* Hk, int64_t d, int64_t K, int
 // of the FP32 path); 0 means dtype.
 Check check_expm(const void* omega, int64_t batch, int64_t d, int dtype, const void* U,
                  const void* ws, size_t ws_bytes, int out_dtype = 0);
+// ws_given = false: the caller passes no workspace (the allocation-free entry
+// point brings its own scratch), so the workspace checks are skipped.
 Check check_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, const void* x,
-                      const void* traj, const void* ws, size_t ws_bytes);
+                      const void* traj, const void* ws, size_t ws_bytes, bool ws_given = true);
 
 Check check_propagate_batched(const void* U, int64_t B, int64_t M, int64_t d, int dtype, const void* x);
 Check check_action(const void* omega, int64_t M, int64_t d, int dtype, const void* x, double tol, const void* ws,

@@ -16,7 +16,7 @@ def test_exports_every_header_symbol():
     assert set(names) == {"qcheff_magnus_coeffs", "qcheff_magnus_generators", "qcheff_expm_batched",
                           "qcheff_propagate", "qcheff_workspace_bytes", "qcheff_last_error",
                           "qcheff_timing_enable", "qcheff_timing_read", "qcheff_propagate_batched",
-                          "qcheff_propagate_action", "qcheff_sync_status"}
+                          "qcheff_propagate_action", "qcheff_sync_status", "qcheff_propagate_state_noalloc"}
     L = q.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -164,3 +164,13 @@ def test_no_cpu_fallback_in_binding(monkeypatch, tmp_path):
     monkeypatch.setattr(q, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         q.lib()
+
+
+def test_propagate_state_noalloc_validation():
+    L = q.lib()
+    f = L.qcheff_propagate_state_noalloc
+    assert f(FAKE, 2, 20000, q.C64, FAKE, None, None) == q.EINVAL       # d beyond the scratch
+    assert f(FAKE, 2, 4, q.C64, None, None, None) == q.EINVAL           # no state
+    assert f(None, 2, 4, q.C64, FAKE, None, None) == q.EINVAL           # no propagators
+    assert f(FAKE, -1, 4, q.C64, FAKE, None, None) == q.EINVAL
+    assert f(FAKE, 2, 4, 9, FAKE, None, None) == q.EINVAL
