@@ -418,28 +418,29 @@ __global__ __launch_bounds__(256) void to_c64_kernel(const double2* __restrict__
 //
 // y = U x with U in C2 (FP32 or FP64) and x, y in FP64; one wave per row.
 // A lane reads the row in 16-byte pieces (two complex64 values or one
-// complex128), eight pieces in flight before any arithmetic; x is staged in LDS
-// when it fits (XLDS).  Complex64 rows need an even d (16-byte aligned rows);
+// complex128), 8 (complex64) or 16 (complex128) pieces in flight before any
+// arithmetic, so a d = 1024 row is one round; x is staged in LDS when it fits
+// (XLDS).  Complex64 rows need an even d (16-byte aligned rows);
 // matvec_kernel below takes any d.
 template <typename C2> struct Vec16;
-template <> struct Vec16<float2> { using t = float4; static constexpr int per = 2; };
-template <> struct Vec16<double2> { using t = double2; static constexpr int per = 1; };
+template <> struct Vec16<float2> { using t = float4; static constexpr int per = 2; static constexpr int inflight = 8; };
+template <> struct Vec16<double2> { using t = double2; static constexpr int per = 1; static constexpr int inflight = 16; };
 
 template <typename C2, bool XLDS>
 __global__ __launch_bounds__(256) void matvec16_kernel(const C2* __restrict__ U, const double2* __restrict__ x,
                                                        double2* __restrict__ y, int d) {
   using V = typename Vec16<C2>::t;
-  constexpr int PER = Vec16<C2>::per;
+  constexpr int PER = Vec16<C2>::per, NL = Vec16<C2>::inflight;
   extern __shared__ double2 xs[];   // [d] when XLDS
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + wave;
   const bool active = row < d;
   const int nch = d / PER;   // 16-byte pieces per row
   const V* ur = reinterpret_cast<const V*>(U + int64_t(active ? row : 0) * d);
-  V buf[8];
+  V buf[NL];
   auto load = [&](int c0) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < NL; ++t) {
       const int c = c0 + lane + 64 * t;
       buf[t] = ur[c < nch ? c : 0];
     }
@@ -451,10 +452,10 @@ __global__ __launch_bounds__(256) void matvec16_kernel(const C2* __restrict__ U,
   }
   const double2* xv = XLDS ? xs : x;
   double ar = 0.0, ai = 0.0;
-  for (int c0 = 0; c0 < nch; c0 += 512) {
+  for (int c0 = 0; c0 < nch; c0 += 64 * NL) {
     if (c0 > 0) load(c0);
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < NL; ++t) {
       const int c = c0 + lane + 64 * t;
       if (c < nch) {
         const C2* e = reinterpret_cast<const C2*>(&buf[t]);
