@@ -82,8 +82,11 @@ def parse():
     ap.add_argument("--serve", action="store_true",
                     help="serving mode: Poisson request streams through the continuous-batching server; "
                          "prints one JSON line of latency percentiles per rate")
-    ap.add_argument("--serve-rates", default="10,100,1000")
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-rates", default="10,30,100,300,1000")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--line-serve-rate", type=float, default=20.0,
+                    help="rate of the serving pass reported in the default line's extra (0: none)")
+    ap.add_argument("--line-serve-requests", type=int, default=200)
     ap.add_argument("--serve-dmax", type=int, default=2048)
     ap.add_argument("--serve-mmax", type=int, default=1024)
     ap.add_argument("--sweep", action="store_true",
@@ -94,6 +97,11 @@ def parse():
                     help="state-only mode: the first intervals of the d = 4096 job by the Taylor action vs the "
                          "propagator path; prints one JSON line")
     ap.add_argument("--action-intervals", type=int, default=64)
+    ap.add_argument("--c5", action="store_true",
+                    help="the d = 4096 job (four coupled transmons, M = 2000) at full length: the Taylor action on "
+                         "complex64 and complex128 generators and the streamed propagator path in complex64, "
+                         "split-BF16 and complex128; prints one JSON line")
+    ap.add_argument("--c5-intervals", type=int, default=0, help="intervals to run (0: all M)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
@@ -270,45 +278,62 @@ def cpu_baseline(w, n_int):
                        f"commutator basis + eigh propagators + state chain, {el:.1f} s"), U, psi
 
 
-def serve(a):
-    """Latency under Poisson arrivals: d ~ U{64..dmax}, M ~ U{64..mmax}, order 1 or 2,
-    FP32 or FP64 per request, admitted by an HBM budget of 200 GB, up to 8 in flight;
-    each request takes the path the server picks for it (propagators or the Taylor
-    action on the state)."""
-    import torch
+def serving_request(i, g, dmax, mmax):
+    """One request of the serving stream: d ~ U{64..dmax}, M ~ U{64..mmax}, order 1 or 2,
+    FP32 or FP64, each with probability 1/2; its operators and signals are built when
+    the job starts (from a seed drawn here)."""
     import workloads as wl
-    from paper_2411_09982_amd.serve import Request, Server, latency_percentiles, max_overlap, poisson_requests
+    from paper_2411_09982_amd.serve import Request
+    d = int(g.integers(64, dmax + 1))
+    M = int(g.integers(64, mmax + 1))
+    order = int(g.integers(1, 3))
+    prec = "c64" if g.random() < 0.5 else "c128"
+    seed = int(g.integers(0, 2 ** 31))
+    spi, t_total = 64, 50.0      # samples per interval, pulse length (ns)
 
-    def make(i, g):
-        d = int(g.integers(64, a.serve_dmax + 1))
-        M = int(g.integers(64, a.serve_mmax + 1))
-        order = int(g.integers(1, 3))
-        prec = "c64" if g.random() < 0.5 else "c128"
-        w = wl.serving_request_system(d, M, order, g)
-        return Request(i, w.H0, w.Hk, w.u, w.dt_sample, M, order, prec, w.psi0)
+    def build():
+        w = wl.serving_request_system(d, M, order, np.random.default_rng(seed), samples_per_interval=spi,
+                                      t_total=t_total)
+        return w.H0, w.Hk, w.u, w.psi0
 
+    return Request(i, None, None, None, t_total / (spi * M), M, order, prec, None, build=build, dims=(d, 1))
+
+
+def serve_pass(rate, n, seed, dmax, mmax):
+    """One Poisson stream of n requests at `rate` through the continuous-batching
+    server (HBM budget 200 GB, 8 jobs in flight); latency percentiles and rates."""
+    import torch
+    from paper_2411_09982_amd.serve import Server, latency_percentiles, max_overlap, poisson_requests
+    reqs = poisson_requests(n, rate, seed, lambda i, g: serving_request(i, g, dmax, mmax))
+    srv = Server(budget_bytes=200 << 30, max_slots=8, chunk=64)
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    lat = latency_percentiles(res)
+    paths = {}
+    for r in res.values():
+        paths[r.path] = paths.get(r.path, 0) + 1
+    out = dict(rate_req_s=rate, requests=n, p50_ms=round(lat["p50_ms"], 1), p99_ms=round(lat["p99_ms"], 1),
+               wait_p50_ms=round(lat["wait_p50_ms"], 1), wait_p99_ms=round(lat["wait_p99_ms"], 1),
+               service_p50_ms=round(lat["service_p50_ms"], 1), service_p99_ms=round(lat["service_p99_ms"], 1),
+               prep_p50_ms=round(lat["prep_p50_ms"], 1), prep_p99_ms=round(lat["prep_p99_ms"], 1),
+               completed_req_s=round(n / wall, 2), intervals_s=round(sum(r.M for r in reqs) / wall, 1),
+               wall_s=round(wall, 2), paths=paths, max_in_flight=max_overlap(res),
+               nonfinite=sum(1 for r in res.values() if not r.finite), d_range=[64, dmax], M_range=[64, mmax])
+    del srv, res
+    torch.cuda.empty_cache()
+    return out
+
+
+def serve(a):
+    """Latency under Poisson arrivals at each rate of --serve-rates, --serve-requests
+    requests each (d ~ U{64..2048}, M ~ U{64..1024}, order 1 or 2, FP32 or FP64 per
+    request); each request takes the path the server picks for it (propagators or
+    the Taylor action on the state).  One JSON line per rate."""
     for rate in [float(x) for x in a.serve_rates.split(",")]:
-        reqs = poisson_requests(a.serve_requests, rate, 2411 + int(rate), make)
-        srv = Server(budget_bytes=200 << 30, max_slots=8, chunk=64)
-        t0 = time.perf_counter()
-        res = srv.run(reqs)
-        wall = time.perf_counter() - t0
-        lat = latency_percentiles(res)
-        props = sum(r.M for r in reqs)
-        paths = {}
-        for r in res.values():
-            paths[r.path] = paths.get(r.path, 0) + 1
-        print(json.dumps(dict(metric="serving latency (Magnus propagation requests)", rate_req_s=rate,
-                              requests=len(reqs), p50_ms=round(lat["p50_ms"], 1), p99_ms=round(lat["p99_ms"], 1),
-                              wait_p50_ms=round(lat["wait_p50_ms"], 1), wait_p99_ms=round(lat["wait_p99_ms"], 1),
-                              service_p50_ms=round(lat["service_p50_ms"], 1),
-                              service_p99_ms=round(lat["service_p99_ms"], 1),
-                              intervals_s=round(props / wall, 1), paths=paths,
-                              wall_s=round(wall, 2), completed_req_s=round(len(reqs) / wall, 2),
-                              max_in_flight=max_overlap(res), d_range=[64, a.serve_dmax],
-                              M_range=[64, a.serve_mmax], data="synthetic")), flush=True)
-        del srv
-        torch.cuda.empty_cache()
+        out = serve_pass(rate, a.serve_requests, 2411 + int(rate), a.serve_dmax, a.serve_mmax)
+        print(json.dumps(dict(metric="serving latency (Magnus propagation requests)", data="synthetic", **out)),
+              flush=True)
 
 
 def sweep(a):
@@ -416,6 +441,58 @@ def action(a):
                           data="synthetic", **out)), flush=True)
 
 
+def c5(a):
+    """All intervals of the d = 4096 job (four coupled transmons, K = 4, M = 2000, order 2)
+    by each path and precision: intervals/s, the final state's norm error, and each
+    state's error (Sec. 4.3, unnormalised, and its direction part) against the
+    Taylor action on complex128 generators (FP64 throughout, the closest to exact
+    here; the oracle cannot run 2000 eigendecompositions of d = 4096)."""
+    import torch
+    import paper_2411_09982_amd as q
+    import workloads as wl
+    w = wl.coupled_transmons()
+    M = a.c5_intervals or w.M
+    N = w.N // w.M * M
+    dev = "cuda:0"
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    H0, Hk, u, psi0 = t(w.H0), t(w.Hk), t(w.u[:, :N]), t(w.psi0)
+    runs = {
+        "action_c64": lambda: q.evolve_state(H0, Hk, u, w.dt_sample, M, w.order, psi0, dtype=torch.complex64),
+        "action_c128": lambda: q.evolve_state(H0, Hk, u, w.dt_sample, M, w.order, psi0, dtype=torch.complex128),
+        "propagators_c64": lambda: q.evolve_streamed(H0, Hk, u, w.dt_sample, M, w.order, psi0,
+                                                     dtype=torch.complex64, chunk=32)[0],
+        "propagators_bf16x3": lambda: q.evolve_streamed(H0, Hk, u, w.dt_sample, M, w.order, psi0,
+                                                        dtype=torch.complex64, chunk=32, bf16x3=True)[0],
+        "propagators_c128": lambda: q.evolve_streamed(H0, Hk, u, w.dt_sample, M, w.order, psi0,
+                                                      dtype=torch.complex128, chunk=16)[0],
+    }
+    # warm-up: the first chunk of each (tile tuning, code loading)
+    uw = t(w.u[:, : w.N // w.M * 16])
+    q.evolve_state(H0, Hk, uw, w.dt_sample, 16, w.order, psi0, dtype=torch.complex64)
+    for dt, bf in ((torch.complex64, False), (torch.complex64, True), (torch.complex128, False)):
+        q.evolve_streamed(H0, Hk, uw, w.dt_sample, 16, w.order, psi0, dtype=dt, chunk=16, bf16x3=bf)
+    torch.cuda.synchronize()
+    out, psi = {}, {}
+    for name, fn in runs.items():
+        t0 = time.perf_counter()
+        x = fn()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        psi[name] = x.cpu().numpy()
+        out[name] = dict(intervals_per_s=round(M / el, 2), seconds=round(el, 2),
+                         norm_minus_1=float(np.linalg.norm(psi[name]) - 1.0))
+        print(f"# {name}: {M / el:.1f} intervals/s", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    ref = psi["action_c128"]
+    for name in runs:
+        if name != "action_c128":
+            out[name].update({k + "_vs_action_c128": v for k, v in state_errors(ref, psi[name]).items()
+                              if k != "norm_minus_1"})
+    print(json.dumps(dict(metric="d = 4096 state propagation at full length: intervals/s",
+                          config=dict(workload=w.name, d=w.d, K=w.K, M=M, order=w.order), data="synthetic",
+                          **out)), flush=True)
+
+
 def golden_state(workload):
     """psi_M of the oracle's whole chain for `workload` (tests/golden/), or None."""
     path = os.path.join(GOLDEN_DIR, f"{workload}_chain.npz")
@@ -470,6 +547,9 @@ def main():
     a = parse()
     if a.action:
         action(a)
+        return
+    if a.c5:
+        c5(a)
         return
     if a.sweep:
         sweep(a)
@@ -554,6 +634,10 @@ def main():
             second["c128"] = job_figure(w2, "c128", 1, 1, roofline=False)
             second["mixed_speedup"] = round(second[a.dtype]["value"] / second["c128"]["value"], 3)
         extra["second_workload"] = second
+
+    if a.line_serve_rate > 0:
+        # serving (the metric's p50/p99 latency): one Poisson stream below saturation
+        extra["serving"] = serve_pass(a.line_serve_rate, a.line_serve_requests, 2411, a.serve_dmax, a.serve_mmax)
 
     cpu = None
     if not a.no_cpu_baseline:

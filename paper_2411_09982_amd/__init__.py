@@ -13,8 +13,10 @@ Functions (same names as the C entry points, minus the ``qcheff_`` prefix):
   expm_batched(omega)                                   -> U, s
   propagate(U, mode, x)                                 -> x (in place)
   sync_status(stream)                                   -> OK or ENONFINITE
-and ``evolve(...)``, the four calls in sequence (the paper's evolve()), and
-``evolve_state(...)``, the state-only path through qcheff_propagate_action.
+and ``evolve(...)``, the four calls in sequence (the paper's evolve()),
+``evolve_streamed(...)``, the same with a bounded number of intervals held at a
+time, and ``evolve_state(...)``, the state-only path through
+qcheff_propagate_action.
 """
 from __future__ import annotations
 
@@ -297,6 +299,38 @@ def evolve_state(H0, Hk, u, dt_sample: float, M: int, order: int, psi0, dtype=to
                                       reuse_basis=gen_ws is not None, stream=stream)
         propagate_action(om, psi, tol=tol, ws=act_ws, stream=stream, skew_hermitian=hermitian)
     return psi
+
+
+def evolve_streamed(H0, Hk, u, dt_sample: float, M: int, order: int, psi0, dtype=torch.complex64,
+                    chunk: int = 32, bf16x3: bool = False, hermitian: bool = True, stream=None):
+    """The propagator path with bounded memory: coefficients once, then per chunk
+    of intervals the generators, their exponentials and the state chain (only
+    `chunk` generators and propagators are held at a time).  complex64 products
+    are refined to unitarity and the propagators kept in complex128.  Returns
+    (psi_M, s), s the squaring count of every interval."""
+    N = u.shape[1]
+    d = H0.shape[0]
+    c1, c2 = magnus_coeffs(u, dt_sample, M, order, stream=stream)
+    refine = hermitian and dtype == torch.complex64
+    n = min(chunk, M)
+    omega = torch.empty((n, d, d), dtype=dtype, device=H0.device)
+    U = torch.empty((n, d, d), dtype=torch.complex128, device=H0.device) if refine else omega
+    s_all = torch.empty(M, dtype=torch.int32, device=H0.device)
+    code = C64_BF16X3 if bf16x3 else _DTYPES[dtype]
+    exp_ws = _workspace(workspace_bytes(FN_EXPM, n, d, 1, 1, code), H0.device)
+    prop_ws = _workspace(workspace_bytes(FN_PROPAGATE, n, d, 1, STATE, _DTYPES[U.dtype]), H0.device)
+    psi = psi0.clone()
+    gen_ws = None
+    for c0 in range(0, M, chunk):
+        c1_ = min(M, c0 + chunk)
+        k = c1_ - c0
+        _, gen_ws = magnus_generators(H0, Hk, c1[c0:c1_], None if c2 is None else c2[c0:c1_],
+                                      dt_sample * (N // M), order, dtype, omega=omega[:k], ws=gen_ws,
+                                      reuse_basis=gen_ws is not None, stream=stream)
+        expm_batched(omega[:k], U=U[:k], s_out=s_all[c0:c1_], ws=exp_ws, stream=stream,
+                     skew_hermitian=hermitian, bf16x3=bf16x3, unitary_refine=refine, out_c128=refine)
+        propagate(U[:k], STATE, psi, ws=prop_ws, stream=stream)
+    return psi, s_all
 
 
 def timing_enable(on: bool) -> None:

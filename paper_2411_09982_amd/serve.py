@@ -33,24 +33,36 @@ import numpy as np
 @dataclasses.dataclass
 class Request:
     rid: int
-    H0: np.ndarray            # complex128 [d][d], exactly Hermitian
-    Hk: np.ndarray            # complex128 [K][d][d], each exactly Hermitian
-    u: np.ndarray             # float64 [K][N]
+    H0: np.ndarray | None     # complex128 [d][d], exactly Hermitian
+    Hk: np.ndarray | None     # complex128 [K][d][d], each exactly Hermitian
+    u: np.ndarray | None      # float64 [K][N]
     dt_sample: float
     M: int
     order: int
     precision: str            # "c64" or "c128"
-    psi0: np.ndarray          # complex128 [d]
+    psi0: np.ndarray | None   # complex128 [d]
     arrival: float = 0.0      # seconds, relative to the start of the stream
     path: str = "auto"        # "auto", "propagators" or "action"
+    # A request may carry its inputs as a recipe instead: `build()` returns
+    # (H0, Hk, u, psi0) and is called when the job starts (so a long stream of
+    # large requests does not hold every payload in host memory); `dims` = (d, K)
+    # then gives the sizes admission needs before that.
+    build: Callable | None = None
+    dims: tuple | None = None
 
     @property
     def d(self) -> int:
-        return self.H0.shape[0]
+        return self.H0.shape[0] if self.H0 is not None else self.dims[0]
 
     @property
     def K(self) -> int:
-        return self.Hk.shape[0]
+        return self.Hk.shape[0] if self.Hk is not None else self.dims[1]
+
+    def inputs(self):
+        """(H0, Hk, u, psi0), built from the recipe if the request carries one."""
+        if self.H0 is not None:
+            return self.H0, self.Hk, self.u, self.psi0
+        return self.build()
 
 
 @dataclasses.dataclass
@@ -63,6 +75,7 @@ class Result:
     done: float
     path: str = "propagators"
     finite: bool = True       # False: a generator norm or a Pade pivot was not finite (the state is NaN)
+    prep: float = 0.0         # seconds of the service time spent building the inputs and copying them in
 
     @property
     def latency(self) -> float:
@@ -162,10 +175,15 @@ class Server:
             with torch.cuda.stream(st):
                 dev = "cuda:0"
                 dtype = torch.complex64 if r.precision == "c64" else torch.complex128
-                H0 = torch.from_numpy(r.H0).to(dev, non_blocking=False)
-                Hk = torch.from_numpy(r.Hk).to(dev)
-                u = torch.from_numpy(np.ascontiguousarray(r.u)).to(dev)
-                psi = torch.from_numpy(r.psi0).to(dev)
+                t_in = time.perf_counter()
+                H0h, Hkh, uh, psi0h = r.inputs()
+                H0 = torch.from_numpy(H0h).to(dev, non_blocking=False)
+                Hk = torch.from_numpy(Hkh).to(dev)
+                u = torch.from_numpy(np.ascontiguousarray(uh)).to(dev)
+                psi = torch.from_numpy(psi0h).to(dev)
+                N = uh.shape[1]
+                del H0h, Hkh, uh, psi0h
+                prep = time.perf_counter() - t_in
                 path = path_for(r)
                 if path == "action":
                     psi = q.evolve_state(H0, Hk, u, r.dt_sample, r.M, r.order, psi, dtype=dtype, chunk=self.chunk,
@@ -173,7 +191,6 @@ class Server:
                     s_max = -1
                 else:
                     c1, c2 = q.magnus_coeffs(u, r.dt_sample, r.M, r.order, stream=st)
-                    N = r.u.shape[1]
                     omega, _ = q.magnus_generators(H0, Hk, c1, c2, r.dt_sample * (N // r.M), r.order, dtype,
                                                    stream=st)
                     # complex64: refined to unitarity and kept in complex128 (as evolve does)
@@ -191,7 +208,7 @@ class Server:
                 q.sync_status(st)
             done = time.perf_counter() - self.t0
             res = Result(r.rid, psi_h, s_max, r.arrival, admitted, done, path,
-                         finite=bool(np.isfinite(psi_h).all()))
+                         finite=bool(np.isfinite(psi_h).all()), prep=prep)
             with self.lock:
                 self.results[r.rid] = res
         except BaseException as e:  # noqa: BLE001 - reported to the caller
@@ -259,13 +276,15 @@ def max_overlap(results: dict[int, Result]) -> int:
 
 def latency_percentiles(results: dict[int, Result]) -> dict:
     """p50/p99 of the latency (arrival to completion) and of its two parts: the
-    wait for admission and the service time (admission to completion)."""
+    wait for admission and the service time (admission to completion); and of the
+    part of the service time spent building and copying the inputs."""
     vals = list(results.values())
     lat = np.array([r.latency for r in vals])
     wait = np.array([r.admitted - r.arrival for r in vals])
     svc = np.array([r.done - r.admitted for r in vals])
+    prep = np.array([r.prep for r in vals])
     out = dict(n=int(lat.size))
-    for name, a in (("", lat), ("wait_", wait), ("service_", svc)):
+    for name, a in (("", lat), ("wait_", wait), ("service_", svc), ("prep_", prep)):
         out[f"{name}p50_ms"] = float(np.percentile(a, 50) * 1e3)
         out[f"{name}p99_ms"] = float(np.percentile(a, 99) * 1e3)
     return out

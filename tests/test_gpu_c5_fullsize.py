@@ -99,3 +99,58 @@ def test_c5_chain_prefix_all_precisions(job):
         say(f"  {prec} vs FP64 path: state infidelity {inf:.3e}, norm - 1 = {np.linalg.norm(psi[prec]) - 1:.3e}")
         assert inf <= 1e-6
         assert oracle.norm_error(psi[prec]) <= 1e-6
+
+
+FULL = {}   # final states of the full-length runs of this module
+
+
+def test_c5_full_length_action(job):
+    # all 2000 intervals by the Taylor action on complex128 and complex64
+    # generators (FP64 arithmetic; the truncation of the complex64 chain is held
+    # below 2^-24 in all)
+    w, H0, Hk, c1, c2 = job
+    u = torch.from_numpy(np.ascontiguousarray(w.u)).to(DEV)
+    for name, dtype in (("action_c128", torch.complex128), ("action_c64", torch.complex64)):
+        say(f"C5 full length ({w.M} intervals), {name}")
+        x = q.evolve_state(H0, Hk, u, w.dt_sample, w.M, w.order, torch.from_numpy(w.psi0).to(DEV), dtype=dtype)
+        torch.cuda.synchronize()
+        FULL[name] = host(x)
+        say(f"  |psi_M| - 1 = {np.linalg.norm(FULL[name]) - 1:.3e}")
+    assert oracle.norm_error(FULL["action_c128"]) <= 1e-12
+    inf = abs(float(oracle.state_infidelity(FULL["action_c128"], FULL["action_c64"])))
+    say(f"  action c64 vs c128 over {w.M} intervals: state error {inf:.3e}")
+    assert inf <= 1e-6 and oracle.norm_error(FULL["action_c64"]) <= 1e-6
+
+
+def test_c5_full_length_propagators_c64(job):
+    # all 2000 intervals through the propagator path (FP32 products, FP64 solve,
+    # refinement to unitarity, complex128 propagators), 32 intervals at a time,
+    # against the FP64 action of the same job; det U_n = exp(tr Omega_n) on samples
+    w, H0, Hk, c1, c2 = job
+    if "action_c128" not in FULL:
+        pytest.skip("needs the full-length action run of this module")
+    u = torch.from_numpy(np.ascontiguousarray(w.u)).to(DEV)
+    say(f"C5 full length ({w.M} intervals), propagators c64")
+    x, s = q.evolve_streamed(H0, Hk, u, w.dt_sample, w.M, w.order, torch.from_numpy(w.psi0).to(DEV),
+                             dtype=torch.complex64, chunk=32)
+    torch.cuda.synchronize()
+    psi = host(x)
+    inf = abs(float(oracle.state_infidelity(FULL["action_c128"], psi)))
+    say(f"  vs FP64 action: state error {inf:.3e}, |psi| - 1 = {np.linalg.norm(psi) - 1:.3e}, "
+        f"s in [{int(s.min())}, {int(s.max())}]")
+    assert inf <= 1e-6 and oracle.norm_error(psi) <= 1e-6
+    for n in (0, 999, 1999):
+        ii = torch.tensor([n], device=DEV)
+        om, _ = q.magnus_generators(H0, Hk, c1[ii].contiguous(), c2[ii].contiguous(), w.dt_interval, w.order,
+                                    torch.complex64)
+        U, _ = q.expm_batched(om, skew_hermitian=True, unitary_refine=True, out_c128=True)
+        sign, logabs = torch.linalg.slogdet(U[0])
+        tr = complex(torch.diagonal(om[0]).to(torch.complex128).sum().cpu())
+        ph = float(torch.angle(sign).cpu())
+        dph = (ph - tr.imag + np.pi) % (2 * np.pi) - np.pi
+        say(f"  interval {n}: log|det U| = {float(logabs):.2e}, arg det U - Im tr Omega = {dph:.2e}")
+        # log|det| sums the d radial errors the refinement leaves (about 1e-11 each);
+        # the phase sums the d eigenvalue phase errors of the FP32 products: held to
+        # 1e-6 per eigenvalue on average
+        assert abs(float(logabs)) <= 1e-6 and abs(dph) <= w.d * 1e-6
+        del om, U

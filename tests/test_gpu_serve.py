@@ -78,3 +78,33 @@ def test_nonfinite_request_is_marked():
         assert res[r.rid].finite == (not bad), r.rid
         assert np.isnan(res[r.rid].psi).all() == bad
     assert q.sync_status() == q.OK        # the server took the flags
+
+
+def test_large_requests_both_paths():
+    # d >= 1024 on both paths in one mix (the propagators forced for two of them):
+    # each result equals the job run alone, bit for bit, and the oracle's chain
+    g = np.random.default_rng(1024)
+    specs = [(1024, "c64", "propagators"), (1024, "c128", "propagators"), (1100, "c64", "action"),
+             (1030, "c128", "action")]
+    reqs = []
+    for i, (d, prec, path) in enumerate(specs):
+        w = wl.serving_request_system(d, 6, 2, g)
+        reqs.append(Request(i, w.H0, w.Hk, w.u, w.dt_sample, w.M, 2, prec, w.psi0, arrival=0.01 * i, path=path))
+    say("serving four requests of d >= 1024 on both paths")
+    res = Server(budget_bytes=1 << 36, max_slots=4, chunk=CHUNK).run(reqs)
+    dev = "cuda:0"
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    for r in reqs:
+        dtype = torch.complex64 if r.precision == "c64" else torch.complex128
+        if r.path == "action":
+            alone = q.evolve_state(t(r.H0), t(r.Hk), t(r.u), r.dt_sample, r.M, r.order, t(r.psi0), dtype=dtype,
+                                   chunk=CHUNK).cpu().numpy()
+        else:
+            alone = q.evolve(t(r.H0), t(r.Hk), t(r.u), r.dt_sample, r.M, r.order, psi0=t(r.psi0), dtype=dtype,
+                             chunk=CHUNK)["psi"].cpu().numpy()
+        assert res[r.rid].path == r.path
+        assert np.array_equal(alone, res[r.rid].psi), r.rid
+        ref = oracle.run(r.H0, r.Hk, r.u, r.dt_sample, r.M, r.order, psi0=r.psi0)["psi"]
+        inf = abs(oracle.state_infidelity(ref, res[r.rid].psi))
+        say(f"  request {r.rid}: d={r.d} {r.precision} {r.path}: state error {inf:.2e}")
+        assert inf <= (1e-12 if r.precision == "c128" else 1e-6), (r.rid, inf)
