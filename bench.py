@@ -456,15 +456,23 @@ def c5(a):
     dev = "cuda:0"
     t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
     H0, Hk, u, psi0 = t(w.H0), t(w.Hk), t(w.u[:, :N]), t(w.psi0)
+    last = [time.perf_counter()]
+
+    def progress(n):   # a line every half minute from the streamed runs (each chunk's exponentials wait once)
+        if time.perf_counter() - last[0] > 30.0:
+            last[0] = time.perf_counter()
+            print(f"#   {n} of {M} intervals", file=sys.stderr, flush=True)
+
     runs = {
         "action_c64": lambda: q.evolve_state(H0, Hk, u, w.dt_sample, M, w.order, psi0, dtype=torch.complex64),
         "action_c128": lambda: q.evolve_state(H0, Hk, u, w.dt_sample, M, w.order, psi0, dtype=torch.complex128),
         "propagators_c64": lambda: q.evolve_streamed(H0, Hk, u, w.dt_sample, M, w.order, psi0,
-                                                     dtype=torch.complex64, chunk=32)[0],
+                                                     dtype=torch.complex64, chunk=32, progress=progress)[0],
         "propagators_bf16x3": lambda: q.evolve_streamed(H0, Hk, u, w.dt_sample, M, w.order, psi0,
-                                                        dtype=torch.complex64, chunk=32, bf16x3=True)[0],
+                                                        dtype=torch.complex64, chunk=32, bf16x3=True,
+                                                        progress=progress)[0],
         "propagators_c128": lambda: q.evolve_streamed(H0, Hk, u, w.dt_sample, M, w.order, psi0,
-                                                      dtype=torch.complex128, chunk=16)[0],
+                                                      dtype=torch.complex128, chunk=16, progress=progress)[0],
     }
     # warm-up: the first chunk of each (tile tuning, code loading)
     uw = t(w.u[:, : w.N // w.M * 16])

@@ -302,12 +302,13 @@ def evolve_state(H0, Hk, u, dt_sample: float, M: int, order: int, psi0, dtype=to
 
 
 def evolve_streamed(H0, Hk, u, dt_sample: float, M: int, order: int, psi0, dtype=torch.complex64,
-                    chunk: int = 32, bf16x3: bool = False, hermitian: bool = True, stream=None):
+                    chunk: int = 32, bf16x3: bool = False, hermitian: bool = True, stream=None, progress=None):
     """The propagator path with bounded memory: coefficients once, then per chunk
     of intervals the generators, their exponentials and the state chain (only
     `chunk` generators and propagators are held at a time).  complex64 products
     are refined to unitarity and the propagators kept in complex128.  Returns
-    (psi_M, s), s the squaring count of every interval."""
+    (psi_M, s), s the squaring count of every interval.  ``progress(n)``, if given,
+    is called after each chunk has been enqueued with the intervals done so far."""
     N = u.shape[1]
     d = H0.shape[0]
     c1, c2 = magnus_coeffs(u, dt_sample, M, order, stream=stream)
@@ -330,6 +331,8 @@ def evolve_streamed(H0, Hk, u, dt_sample: float, M: int, order: int, psi0, dtype
         expm_batched(omega[:k], U=U[:k], s_out=s_all[c0:c1_], ws=exp_ws, stream=stream,
                      skew_hermitian=hermitian, bf16x3=bf16x3, unitary_refine=refine, out_c128=refine)
         propagate(U[:k], STATE, psi, ws=prop_ws, stream=stream)
+        if progress is not None:
+            progress(c1_)
     return psi, s_all
 
 
