@@ -102,6 +102,11 @@ def parse():
                          "complex64 and complex128 generators and the streamed propagator path in complex64, "
                          "split-BF16 and complex128; prints one JSON line")
     ap.add_argument("--c5-intervals", type=int, default=0, help="intervals to run (0: all M)")
+    ap.add_argument("--npad", action="store_true",
+                    help="numerical NPAD on the test matrix a^dag a + (a + a^dag): five consecutive rotations of "
+                         "the five smallest couplings, one step of all N/2 disjoint pairs, the largest-coupling "
+                         "search; prints one JSON line")
+    ap.add_argument("--npad-n", type=int, default=16384)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
@@ -501,6 +506,61 @@ def c5(a):
                           **out)), flush=True)
 
 
+def npad_bench(a):
+    """Numerical NPAD (Sec. 3.2) on the benchmark matrix of App. B, a^dag a + (a + a^dag)
+    truncated to N levels, stored dense in complex128: the time of one NPAD step of five
+    consecutive rotations (the five smallest couplings, (0,1) ... (4,5)), of one step
+    eliminating all N/2 disjoint pairs (2m, 2m+1) at once (HBM-bound: every entry is
+    read and written once by the row pass and once by the column pass), and of the
+    largest-coupling search (every entry read once)."""
+    import torch
+    import paper_2411_09982_amd as q
+    N = a.npad_n
+    dev = "cuda:0"
+    H = torch.zeros((N, N), dtype=torch.complex128, device=dev)
+    n = torch.arange(N, device=dev, dtype=torch.float64)
+    H.diagonal().copy_(n.to(torch.complex128))
+    off = torch.sqrt(n[1:]).to(torch.complex128)
+    H.diagonal(1).copy_(off)
+    H.diagonal(-1).copy_(off)
+    H0 = H.clone()
+    ws = torch.empty(q.workspace_bytes(q.FN_NPAD, N // 2, N, 1, 1, q.C128), dtype=torch.uint8, device=dev)
+    five = [torch.tensor([[k, k + 1]], dtype=torch.int64, device=dev) for k in range(5)]
+    allp = torch.stack([torch.arange(0, N, 2, device=dev), torch.arange(1, N, 2, device=dev)], dim=1).contiguous()
+    ij = torch.empty((1, 2), dtype=torch.int64, device=dev)
+    mag = torch.empty(1, dtype=torch.float64, device=dev)
+
+    def timed_ms(fn, reps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def step5():
+        for p in five:
+            q.npad_eliminate(H, p, ws=ws)
+
+    t5 = timed_ms(step5, 50)
+    H.copy_(H0)
+    tall = timed_ms(lambda: q.npad_eliminate(H, allp, ws=ws), 10)
+    tl = timed_ms(lambda: q.npad_largest(H, ij, mag, ws=ws), 20)
+    byt_all = 4.0 * N * N * 16        # two passes, each reading and writing every entry
+    byt_l = 1.0 * N * N * 16 / 2      # the upper triangle read once
+    ok = q.sync_status() == q.OK
+    print(json.dumps(dict(metric="numerical NPAD (Givens-rotation SWT), dense complex128", N=N, data="synthetic",
+                          matrix="a^dag a + (a + a^dag)", step_of_5_rotations_ms=round(t5, 4),
+                          all_pairs_step_ms=round(tall, 3), all_pairs_rotations_per_s=round(N / 2 / (tall * 1e-3)),
+                          all_pairs_hbm_gbs=round(byt_all / (tall * 1e-3) / 1e9, 1),
+                          largest_coupling_ms=round(tl, 3),
+                          largest_coupling_hbm_gbs=round(byt_l / (tl * 1e-3) / 1e9, 1), status_ok=ok)), flush=True)
+
+
 def golden_state(workload):
     """psi_M of the oracle's whole chain for `workload` (tests/golden/), or None."""
     path = os.path.join(GOLDEN_DIR, f"{workload}_chain.npz")
@@ -558,6 +618,9 @@ def main():
         return
     if a.c5:
         c5(a)
+        return
+    if a.npad:
+        npad_bench(a)
         return
     if a.sweep:
         sweep(a)

@@ -117,6 +117,7 @@ extern "C" {
 #define QCHEFF_FN_EXPM       2
 #define QCHEFF_FN_PROPAGATE  3
 #define QCHEFF_FN_ACTION     4  /* qcheff_propagate_action: batch = M */
+#define QCHEFF_FN_NPAD       5  /* qcheff_npad_eliminate / _largest: batch = P */
 
 /*
  * qcheff_magnus_coeffs - per-interval Magnus coefficients of the control
@@ -285,6 +286,44 @@ int qcheff_propagate_action(const void* omega, int64_t M, int64_t d, int dtype, 
                             double tol, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * qcheff_npad_eliminate - one step of numerical NPAD (Sec. 3.2): the couplings
+ * H[i_p][j_p], p < P, of a dense Hermitian H are eliminated in place by
+ * H <- G H G^dag, G the product of the two-level Givens rotations of the pairs
+ * (Eq. tls-ham).  The rotation of (i, j) diagonalises H restricted to {i, j}
+ * without exchanging its two levels: with delta = (H_ii - H_jj)/2, g = |H_ij|,
+ * e = H_ij/g, r = sqrt(delta^2 + g^2), c = sqrt((1 + |delta|/r)/2) and
+ * s = sign(delta) g / (2 r c) (delta = 0 counts as positive),
+ * G_ii = G_jj = c, G_ij = s e, G_ji = -s conj(e).  Rotations of disjoint pairs
+ * commute, so all P are one unitary; their parameters come from H before the step.
+ *
+ *   H          [d][d] Hermitian, device, QCHEFF_C128 or QCHEFF_C64, in place
+ *              (arithmetic in FP64; complex64 entries rounded once at the store).
+ *   d          2 .. 131072.
+ *   pairs      [P][2] int64, device: (i_p, j_p).  Pairs that overlap another pair
+ *              or leave [0, d) (i == j included) are left alone and make the next
+ *              qcheff_sync_status return QCHEFF_EINVAL; the others are applied.
+ *   P          0 .. d/2.
+ *   ws         qcheff_workspace_bytes(QCHEFF_FN_NPAD, P, d, 1, 1, dtype) bytes.
+ *   Enqueue-only.  Returns QCHEFF_OK, QCHEFF_EINVAL, QCHEFF_EWORKSPACE, QCHEFF_EDEVICE.
+ */
+int qcheff_npad_eliminate(void* H, int64_t d, int dtype, const int64_t* pairs, int64_t P, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/*
+ * qcheff_npad_largest - the coupling NPAD eliminates next when it goes by size
+ * (Sec. 3.2: rotating away the largest off-diagonal terms first): (i, j), i < j,
+ * of the largest |H_ij| above the diagonal, the first in row-major order among
+ * equal magnitudes; a NaN counts as the largest.
+ *   ij_out     [2] int64, device, written (the layout of one `pairs` row, so it can
+ *              be passed straight to qcheff_npad_eliminate with P = 1).
+ *   mag_out    optional [1] double, device: the magnitude.
+ *   ws         qcheff_workspace_bytes(QCHEFF_FN_NPAD, 0, d, 1, 1, dtype) bytes.
+ *   Enqueue-only.  Returns QCHEFF_OK, QCHEFF_EINVAL, QCHEFF_EWORKSPACE, QCHEFF_EDEVICE.
+ */
+int qcheff_npad_largest(const void* H, int64_t d, int dtype, int64_t* ij_out, double* mag_out, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/*
  * qcheff_workspace_bytes - workspace needed by `fn` (QCHEFF_FN_*):
  *   GENERATORS: (batch, K, order, d) -> commutator basis bytes (0 for order 1);
  *   EXPM:       bytes to process `batch` items at once (per-item size x batch);
@@ -309,7 +348,9 @@ const char* qcheff_last_error(void);
  * another stream sets meanwhile is kept for the next call.  The flags are per
  * device and shared by every stream and thread of the process, so they cannot
  * say which job raised them.
- * Returns QCHEFF_OK, QCHEFF_ENONFINITE or QCHEFF_EDEVICE.
+ * Returns QCHEFF_OK, QCHEFF_ENONFINITE, QCHEFF_EINVAL (a qcheff_npad_eliminate call
+ * was given pairs that overlapped or left [0, d); those pairs were left alone) or
+ * QCHEFF_EDEVICE.
  */
 int qcheff_sync_status(void* stream);
 

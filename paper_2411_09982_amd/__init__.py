@@ -15,8 +15,9 @@ Functions (same names as the C entry points, minus the ``qcheff_`` prefix):
   sync_status(stream)                                   -> OK or ENONFINITE
 and ``evolve(...)``, the four calls in sequence (the paper's evolve()),
 ``evolve_streamed(...)``, the same with a bounded number of intervals held at a
-time, and ``evolve_state(...)``, the state-only path through
-qcheff_propagate_action.
+time, ``evolve_state(...)``, the state-only path through
+qcheff_propagate_action, and the NPAD steps of Sec. 3.2 (npad_eliminate,
+npad_largest, npad_iterate).
 """
 from __future__ import annotations
 
@@ -34,7 +35,7 @@ OK, EINVAL, EWORKSPACE, EDEVICE, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -
 C128, C64, C64_BF16X3 = 1, 2, 3
 STATE, PRODUCT = 1, 2
 REUSE_BASIS = 1
-FN_GENERATORS, FN_EXPM, FN_PROPAGATE, FN_ACTION = 1, 2, 3, 4
+FN_GENERATORS, FN_EXPM, FN_PROPAGATE, FN_ACTION, FN_NPAD = 1, 2, 3, 4, 5
 SKEW_HERMITIAN = 0x100
 UNITARY_REFINE = 0x200
 OUT_C128 = 0x400
@@ -68,9 +69,12 @@ def lib() -> ctypes.CDLL:
     L.qcheff_propagate.argtypes = [vp, i64, i64, i32, i32, vp, vp, vp, ctypes.c_size_t, vp]
     L.qcheff_propagate_batched.argtypes = [vp, i64, i64, i64, i32, vp, vp]
     L.qcheff_propagate_state_noalloc.argtypes = [vp, i64, i64, i32, vp, vp, vp]
+    L.qcheff_npad_eliminate.argtypes = [vp, i64, i32, vp, i64, vp, ctypes.c_size_t, vp]
+    L.qcheff_npad_largest.argtypes = [vp, i64, i32, vp, vp, vp, ctypes.c_size_t, vp]
     L.qcheff_propagate_action.argtypes = [vp, i64, i64, i32, vp, vp, dbl, vp, ctypes.c_size_t, vp]
     for f in ("qcheff_magnus_coeffs", "qcheff_magnus_generators", "qcheff_expm_batched", "qcheff_propagate",
-              "qcheff_propagate_batched", "qcheff_propagate_action", "qcheff_propagate_state_noalloc"):
+              "qcheff_propagate_batched", "qcheff_propagate_action", "qcheff_propagate_state_noalloc",
+              "qcheff_npad_eliminate", "qcheff_npad_largest"):
         getattr(L, f).restype = i32
     L.qcheff_workspace_bytes.argtypes = [i32, i64, i64, i64, i32, i32]
     L.qcheff_workspace_bytes.restype = ctypes.c_size_t
@@ -98,11 +102,12 @@ def _check(fn: str, status: int) -> None:
 
 
 def sync_status(stream=None) -> int:
-    """qcheff_sync_status: waits for the stream; OK, or ENONFINITE if a generator
-    norm was not finite or a Pade denominator had a zero pivot since the last call
-    (the flags are then cleared).  Raises only for a device error."""
+    """qcheff_sync_status: waits for the stream; OK, ENONFINITE if a generator
+    norm was not finite or a Pade denominator had a zero pivot, or EINVAL if NPAD
+    pairs overlapped or left the matrix, since the last call (the flags are then
+    cleared).  Raises only for a device error."""
     st = lib().qcheff_sync_status(_stream(stream))
-    if st not in (OK, ENONFINITE):
+    if st not in (OK, ENONFINITE, EINVAL):
         _check("qcheff_sync_status", st)
     return st
 
@@ -334,6 +339,56 @@ def evolve_streamed(H0, Hk, u, dt_sample: float, M: int, order: int, psi0, dtype
         if progress is not None:
             progress(c1_)
     return psi, s_all
+
+
+# ------------------------------------------------------------------- NPAD
+
+def npad_eliminate(H, pairs, ws=None, stream=None):
+    """One NPAD step (qcheff_npad_eliminate): the couplings H[i, j] of the disjoint
+    `pairs` ([P][2] int64 on the GPU, or a list of (i, j)) are rotated away in place,
+    H <- G H G^dag.  Returns H."""
+    _dev(H, "H")
+    d = H.shape[0]
+    if not isinstance(pairs, torch.Tensor):
+        pairs = torch.tensor(list(pairs), dtype=torch.int64).reshape(-1, 2).to(H.device)
+    _dev(pairs, "pairs")
+    P = pairs.shape[0]
+    code = _DTYPES[H.dtype]
+    if ws is None:
+        ws = _workspace(workspace_bytes(FN_NPAD, P, d, 1, 1, code), H.device)
+    _check("qcheff_npad_eliminate", lib().qcheff_npad_eliminate(
+        _ptr(H), d, code, _ptr(pairs), P, _ptr(ws), ws.numel(), _stream(stream)))
+    return H
+
+
+def npad_largest(H, ij=None, mag=None, ws=None, stream=None):
+    """(i, j), i < j, of the largest |H_ij| as an int64 GPU tensor [1][2] (a `pairs`
+    argument for npad_eliminate), and its magnitude (float64 GPU tensor [1])."""
+    _dev(H, "H")
+    d = H.shape[0]
+    code = _DTYPES[H.dtype]
+    if ij is None:
+        ij = torch.empty((1, 2), dtype=torch.int64, device=H.device)
+    if mag is None:
+        mag = torch.empty(1, dtype=torch.float64, device=H.device)
+    if ws is None:
+        ws = _workspace(workspace_bytes(FN_NPAD, 0, d, 1, 1, code), H.device)
+    _check("qcheff_npad_largest", lib().qcheff_npad_largest(
+        _ptr(H), d, code, _ptr(ij), _ptr(mag), _ptr(ws), ws.numel(), _stream(stream)))
+    return ij, mag
+
+
+def npad_iterate(H, n: int, stream=None):
+    """n NPAD steps, each rotating away the largest remaining coupling, all on the
+    stream (the pair found by one step feeds the next without a host round trip)."""
+    d = H.shape[0]
+    ws = _workspace(workspace_bytes(FN_NPAD, 1, d, 1, 1, _DTYPES[H.dtype]), H.device)
+    ij = torch.empty((1, 2), dtype=torch.int64, device=H.device)
+    mag = torch.empty(1, dtype=torch.float64, device=H.device)
+    for _ in range(n):
+        npad_largest(H, ij, mag, ws=ws, stream=stream)
+        npad_eliminate(H, ij, ws=ws, stream=stream)
+    return H
 
 
 def timing_enable(on: bool) -> None:

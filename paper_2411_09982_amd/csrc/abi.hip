@@ -19,6 +19,7 @@
 #include "lu.hpp"
 #include "expm_small.hpp"
 #include "action.hpp"
+#include "npad.hpp"
 #include "validate.hpp"
 
 namespace qcheff {
@@ -693,6 +694,60 @@ int run_expm(const void* omega, int64_t batch, int64_t d, void* U, int32_t* s_ou
   return QCHEFF_OK;
 }
 
+// --------------------------------------------------------------------- NPAD
+struct NpadWs {
+  int* mark;
+  NpadRot* rot;
+  int* active;
+  Best* part;
+};
+
+bool carve_npad(void* ws, size_t bytes, int64_t P, int64_t d, NpadWs& w) {
+  Carver cv{static_cast<char*>(ws), bytes};
+  w.mark = cv.take<int>(size_t(d) * 4);
+  w.rot = cv.take<NpadRot>(size_t(std::max<int64_t>(P, 1)) * sizeof(NpadRot));
+  w.active = cv.take<int>(size_t(std::max<int64_t>(P, 1)) * 4);
+  w.part = cv.take<Best>(size_t((d + 3) / 4) * sizeof(Best));
+  return w.mark && w.rot && w.active && w.part;
+}
+
+template <typename C2>
+int run_npad_eliminate(C2* H, int64_t d, const int64_t* pairs, int64_t P, NpadWs& w, hipStream_t st) {
+  if (P == 0) return QCHEFF_OK;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(nblocks(d, 256)), dim3(256), 0, st, reinterpret_cast<uint32_t*>(w.mark), d,
+                     0u);
+  hipLaunchKernelGGL(npad_mark_kernel, dim3(nblocks(P, 256)), dim3(256), 0, st, pairs, P, d, w.mark);
+  hipLaunchKernelGGL(npad_params_kernel<C2>, dim3(nblocks(P, 256)), dim3(256), 0, st, H, d, pairs, P, w.mark, w.rot,
+                     w.active);
+  QC_HIP(hipGetLastError());
+  const unsigned gx = unsigned(std::min<int64_t>(nblocks(d, 256), 64));
+  for (int64_t p0 = 0; p0 < P; p0 += 65535) {
+    const unsigned np = unsigned(std::min<int64_t>(65535, P - p0));
+    hipLaunchKernelGGL(npad_rows_kernel<C2>, dim3(gx, np), dim3(256), 0, st, H, d, pairs, p0, w.rot, w.active);
+  }
+  QC_HIP(hipGetLastError());
+  if (P >= 64) {
+    // threads over the pairs of a row; rows spread over grid y
+    const unsigned gy = unsigned(std::min<int64_t>(d, 65535));
+    hipLaunchKernelGGL((npad_cols_kernel<C2, true>), dim3(nblocks(P, 256), gy), dim3(256), 0, st, H, d, pairs, P,
+                       int64_t(0), w.rot, w.active);
+  } else {
+    hipLaunchKernelGGL((npad_cols_kernel<C2, false>), dim3(gx, unsigned(P)), dim3(256), 0, st, H, d, pairs, P,
+                       int64_t(0), w.rot, w.active);
+  }
+  QC_HIP(hipGetLastError());
+  return QCHEFF_OK;
+}
+
+template <typename C2>
+int run_npad_largest(const C2* H, int64_t d, int64_t* ij, double* mag, NpadWs& w, hipStream_t st) {
+  const int64_t nb = (d + 3) / 4;
+  hipLaunchKernelGGL(npad_largest_partial_kernel<C2>, dim3(unsigned(nb)), dim3(256), 0, st, H, d, w.part);
+  hipLaunchKernelGGL(npad_largest_final_kernel, dim3(1), dim3(256), 0, st, w.part, nb, d, ij, mag);
+  QC_HIP(hipGetLastError());
+  return QCHEFF_OK;
+}
+
 // ---------------------------------------------------------------- propagate
 // ------------------------------------------------------- state-only action
 // sum_{k > m} x^k / k! (x >= 0), summed until the terms stop mattering.
@@ -999,6 +1054,29 @@ int qcheff_propagate_action(const void* omega, int64_t M, int64_t d, int dtype, 
                               : run_action<float>(omega, M, d, x, traj, tol, ws, ws_bytes, skew, st);
 }
 
+int qcheff_npad_eliminate(void* H, int64_t d, int dtype, const int64_t* pairs, int64_t P, void* ws, size_t ws_bytes,
+                          void* stream) {
+  Check c = check_npad(H, d, dtype, P, pairs, ws, ws_bytes);
+  if (c.status) return fail(c);
+  NpadWs w;
+  if (!carve_npad(ws, ws_bytes, P, d, w)) return fail(QCHEFF_EWORKSPACE, "workspace carving failed");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return dtype == QCHEFF_C128 ? run_npad_eliminate(static_cast<double2*>(H), d, pairs, P, w, st)
+                              : run_npad_eliminate(static_cast<float2*>(H), d, pairs, P, w, st);
+}
+
+int qcheff_npad_largest(const void* H, int64_t d, int dtype, int64_t* ij_out, double* mag_out, void* ws,
+                        size_t ws_bytes, void* stream) {
+  Check c = check_npad(H, d, dtype, 0, ij_out, ws, ws_bytes);
+  if (c.status) return fail(c);
+  if (!ij_out) return fail(QCHEFF_EINVAL, "ij_out must not be NULL");
+  NpadWs w;
+  if (!carve_npad(ws, ws_bytes, 0, d, w)) return fail(QCHEFF_EWORKSPACE, "workspace carving failed");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return dtype == QCHEFF_C128 ? run_npad_largest(static_cast<const double2*>(H), d, ij_out, mag_out, w, st)
+                              : run_npad_largest(static_cast<const float2*>(H), d, ij_out, mag_out, w, st);
+}
+
 int qcheff_propagate_batched(const void* U, int64_t B, int64_t M, int64_t d, int dtype, void* x, void* stream) {
   Check c = check_propagate_batched(U, B, M, d, dtype, x);
   if (c.status) return fail(c);
@@ -1038,6 +1116,8 @@ int qcheff_sync_status(void* stream) {
   w |= g_host_status[dev].exchange(0);
   if (w & STATUS_NONFINITE) return fail(QCHEFF_ENONFINITE, "a generator or its norm was not finite");
   if (w & STATUS_ZERO_PIVOT) return fail(QCHEFF_ENONFINITE, "a Pade denominator had a zero pivot");
+  if (w & STATUS_BAD_PAIRS)
+    return fail(QCHEFF_EINVAL, "qcheff_npad_eliminate: pairs overlapped or left [0, d) and were left alone");
   return QCHEFF_OK;
 }
 

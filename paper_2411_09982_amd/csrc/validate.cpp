@@ -168,7 +168,24 @@ Check check_action(const void* omega, int64_t M, int64_t d, int dtype, const voi
   return Check::ok();
 }
 
+size_t npad_ws_bytes(int64_t P, int64_t d) {
+  if (P < 0 || d < 2) return 0;
+  const size_t p = size_t(P > 0 ? P : 1);
+  return align256(size_t(d) * 4) + align256(p * 32) + align256(p * 4) + align256(size_t((d + 3) / 4) * 16);
+}
+
+Check check_npad(const void* H, int64_t d, int dtype, int64_t P, const void* ptr, const void* ws, size_t ws_bytes) {
+  if (d < 2 || d > (int64_t(1) << 17)) return Check::fail(QCHEFF_EINVAL, "d must be in [2, 131072]");
+  if (dtype != QCHEFF_C128 && dtype != QCHEFF_C64) return Check::fail(QCHEFF_EINVAL, "unknown dtype");
+  if (P < 0 || P > d / 2) return Check::fail(QCHEFF_EINVAL, "P must be in [0, d/2] (disjoint pairs)");
+  if (!H) return Check::fail(QCHEFF_EINVAL, "H must not be NULL");
+  if (P > 0 && !ptr) return Check::fail(QCHEFF_EINVAL, "pairs must not be NULL");
+  if (!ws || ws_bytes < npad_ws_bytes(P, d)) return Check::fail(QCHEFF_EWORKSPACE, "workspace too small");
+  return Check::ok();
+}
+
 size_t workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int order, int dtype) {
+  if (fn == QCHEFF_FN_NPAD) return elem_bytes(dtype) ? npad_ws_bytes(batch, d) : 0;
   if (d < 1 || d > kMaxDim) return 0;
   switch (fn) {
     case QCHEFF_FN_GENERATORS:

@@ -54,6 +54,11 @@ size_t expm_ws_bytes(int64_t batch, int64_t d, int dtype);
 int64_t expm_chunk(size_t ws_bytes, int64_t batch, int64_t d, int dtype);  // items per chunk, 0 if none fit
 size_t propagate_ws_bytes(int64_t M, int64_t d, int dtype, int mode);
 size_t action_ws_bytes(int64_t M, int64_t d);
+// qcheff_npad_*: H, d >= 2, dtype, P >= 0 pairs (device; checked by the kernels),
+// workspace of npad_ws_bytes(P, d).
+size_t npad_ws_bytes(int64_t P, int64_t d);
+Check check_npad(const void* H, int64_t d, int dtype, int64_t P, const void* ptr, const void* ws, size_t ws_bytes);
+
 size_t workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int order, int dtype);
 
 }  // namespace qcheff

@@ -16,7 +16,8 @@ def test_exports_every_header_symbol():
     assert set(names) == {"qcheff_magnus_coeffs", "qcheff_magnus_generators", "qcheff_expm_batched",
                           "qcheff_propagate", "qcheff_workspace_bytes", "qcheff_last_error",
                           "qcheff_timing_enable", "qcheff_timing_read", "qcheff_propagate_batched",
-                          "qcheff_propagate_action", "qcheff_sync_status", "qcheff_propagate_state_noalloc"}
+                          "qcheff_propagate_action", "qcheff_sync_status", "qcheff_propagate_state_noalloc",
+                          "qcheff_npad_eliminate", "qcheff_npad_largest"}
     L = q.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -174,3 +175,19 @@ def test_propagate_state_noalloc_validation():
     assert f(None, 2, 4, q.C64, FAKE, None, None) == q.EINVAL           # no propagators
     assert f(FAKE, -1, 4, q.C64, FAKE, None, None) == q.EINVAL
     assert f(FAKE, 2, 4, 9, FAKE, None, None) == q.EINVAL
+
+
+def test_npad_validation():
+    L = q.lib()
+    need = q.workspace_bytes(q.FN_NPAD, 3, 10, 1, 1, q.C128)
+    assert need == 256 + 256 + 256 + 256
+    e = L.qcheff_npad_eliminate
+    assert e(FAKE, 1, q.C128, FAKE, 0, FAKE, need, None) == q.EINVAL            # d < 2
+    assert e(FAKE, 10, q.C128, FAKE, 6, FAKE, need, None) == q.EINVAL           # P > d / 2
+    assert e(FAKE, 10, 7, FAKE, 3, FAKE, need, None) == q.EINVAL                # dtype
+    assert e(None, 10, q.C128, FAKE, 3, FAKE, need, None) == q.EINVAL           # H
+    assert e(FAKE, 10, q.C128, None, 3, FAKE, need, None) == q.EINVAL           # pairs
+    assert e(FAKE, 10, q.C128, FAKE, 3, FAKE, need - 1, None) == q.EWORKSPACE
+    lg = L.qcheff_npad_largest
+    assert lg(FAKE, 10, q.C64, None, None, FAKE, need, None) == q.EINVAL        # ij_out
+    assert lg(FAKE, 10, q.C64, FAKE, None, None, 0, None) == q.EWORKSPACE
