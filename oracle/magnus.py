@@ -20,7 +20,10 @@ Readings of the paper this file takes (the paper is silent or garbled there):
   * sample i of u holds on [t0 + i dt, t0 + (i+1) dt) (zero-order hold), and the
     N samples split into M equal intervals of s = N / M samples;
   * the series is read per interval [t_n, t_n + Delta t] and truncated at order
-    1 or 2; the second-order term uses t2 < t1 and the prefactor -i/2;
+    1, 2 or 3; the second-order term uses t2 < t1 and the prefactor -i/2; the
+    third-order term (Eq. magnus-exp's H-bar^(3), "the pattern of nested
+    commutators" the paper leaves unwritten) is the standard one, -(1/6) times the
+    triple integral over t3 < t2 < t1 of [H1,[H2,H3]] + [H3,[H2,H1]];
   * U_n = exp(-i H-bar_n) with hbar = 1; the generator is Omega_n = -i H-bar_n;
   * later intervals multiply on the left.
 
@@ -155,6 +158,61 @@ def generators(H0, Hk, c1, c2, dt_interval, order):
     return -1j * effective_hamiltonians(H0, Hk, c1, c2, dt_interval, order)
 
 
+# ------------------------------------------------------- third-order term
+
+def third_order_coefficients(u, dt_sample, M):
+    """T[n, a, b, c] = int_{t3 < t2 < t1 in interval n} x_a(t1) x_b(t2) x_c(t3) for the
+    zero-order-hold signals x_0 = 1 (the drift) and x_k = u_{k-1}.
+
+    Cells i (of t1), j (of t2), k (of t3) contribute the volume of the simplex
+    t3 < t2 < t1 inside their product, in units of dt^3: 1 for i > j > k, 1/2 for
+    i = j > k or i > j = k, 1/6 for i = j = k.  Summed with exclusive prefix sums
+    C_c[j] = sum_{k<j} x_c[k], Q[i] = sum_{j<i} x_b[j] C_c[j], R[i] = sum_{j<i} x_b[j] x_c[j]:
+        T / dt^3 = sum_i x_a[i] (Q[i] + x_b[i] C_c[i] / 2 + R[i] / 2 + x_b[i] x_c[i] / 6).
+    """
+    u = np.asarray(u, dtype=np.float64)
+    K, N = u.shape
+    s = N // M
+    dt = float(dt_sample)
+    x = np.vstack([np.ones(N), u])
+    T = np.empty((M, K + 1, K + 1, K + 1))
+    for n in range(M):
+        seg = x[:, n * s:(n + 1) * s]
+        for a in range(K + 1):
+            for b in range(K + 1):
+                for c in range(K + 1):
+                    Cc = np.concatenate([[0.0], np.cumsum(seg[c])[:-1]])
+                    bc = seg[b] * Cc
+                    Q = np.concatenate([[0.0], np.cumsum(bc)[:-1]])
+                    bb = seg[b] * seg[c]
+                    R = np.concatenate([[0.0], np.cumsum(bb)[:-1]])
+                    T[n, a, b, c] = dt ** 3 * math.fsum(seg[a] * (Q + 0.5 * bc + 0.5 * R + bb / 6.0))
+    return T
+
+
+def third_order_term(H0, Hk, T):
+    """H-bar^(3)_n, the third-order term of Eq. magnus-exp for H(t) of
+    Eq. magnus-generic-ham: with A = -i H, Omega_3 = (1/6) int_{t3<t2<t1}
+    ([A1, [A2, A3]] + [A3, [A2, A1]]), so
+        H-bar^(3)_n = i Omega_3 = -(1/6) sum_{a,b,c} T[n,a,b,c] ([H_a, [H_b, H_c]] + [H_c, [H_b, H_a]])
+    with H_0 the drift and H_{k+1} = Hk[k]."""
+    H = [np.asarray(H0, dtype=np.complex128)] + [np.asarray(h, dtype=np.complex128) for h in Hk]
+    nb = len(H)
+    M = T.shape[0]
+    d = H[0].shape[0]
+    nested = {}
+    for a in range(nb):
+        for b in range(nb):
+            for c in range(nb):
+                nested[a, b, c] = (commutator(H[a], commutator(H[b], H[c]))
+                                   + commutator(H[c], commutator(H[b], H[a])))
+    out = np.zeros((M, d, d), dtype=np.complex128)
+    for n in range(M):
+        for (a, b, c), C in nested.items():
+            out[n] = out[n] - (T[n, a, b, c] / 6.0) * C
+    return out
+
+
 # ------------------------------------------------------------- exponential
 
 def propagator_from_hamiltonian(Hbar):
@@ -282,15 +340,21 @@ def unitarity_error(U):
 # --------------------------------------------------------------------- job
 
 def run(H0, Hk, u, dt_sample, M, order, psi0=None, product=False, check=True):
-    """The whole path on the CPU: coefficients -> Omega_n -> U_n -> chain."""
+    """The whole path on the CPU: coefficients -> Omega_n -> U_n -> chain.  Order 3
+    adds the third-order term (third_order_term) to the second-order H-bar_n."""
     if check:
         check_inputs(H0, Hk, u, M)
     N = np.asarray(u).shape[1]
     dt_interval = dt_sample * (N // M)
-    c1, c2 = interval_coefficients(u, dt_sample, M, order)
-    Hbar = effective_hamiltonians(H0, Hk, c1, c2, dt_interval, order)
+    c1, c2 = interval_coefficients(u, dt_sample, M, min(order, 2))
+    Hbar = effective_hamiltonians(H0, Hk, c1, c2, dt_interval, min(order, 2))
+    T = None
+    if order == 3:
+        T = third_order_coefficients(u, dt_sample, M)
+        Hbar = Hbar + third_order_term(H0, Hk, T)
+        Hbar = 0.5 * (Hbar + np.conj(np.swapaxes(Hbar, -1, -2)))
     U = propagator_from_hamiltonian(Hbar)
-    out = dict(c1=c1, c2=c2, Hbar=Hbar, Omega=-1j * Hbar, U=U)
+    out = dict(c1=c1, c2=c2, T=T, Hbar=Hbar, Omega=-1j * Hbar, U=U)
     if psi0 is not None:
         out["psi"], out["traj"] = propagate_state(U, psi0, trajectory=True)
     if product:

@@ -34,6 +34,10 @@ MUTANTS = {
     "shift_sign": ("Omega = Omega - mu * np.eye", "Omega = Omega + mu * np.eye"),
     "shift_not_mean": ("complex(np.trace(Omega)) / Omega.shape[-1]", "complex(np.trace(Omega))"),
     "generators_sign": ("return -1j * effective_hamiltonians", "return 1j * effective_hamiltonians"),
+    "third_order_sixth": ("out[n] = out[n] - (T[n, a, b, c] / 6.0) * C", "out[n] = out[n] - (T[n, a, b, c] / 3.0) * C"),
+    "third_order_sign": ("out[n] = out[n] - (T[n, a, b, c] / 6.0) * C", "out[n] = out[n] + (T[n, a, b, c] / 6.0) * C"),
+    "third_order_tie_weight": ("(Q + 0.5 * bc + 0.5 * R + bb / 6.0)", "(Q + bc + 0.5 * R + bb / 6.0)"),
+    "third_order_nesting": ("+ commutator(H[c], commutator(H[b], H[a])))", "+ commutator(H[a], commutator(H[b], H[c])))"),
     "state_infidelity_normalised": ("    return 1.0 - abs(np.vdot(a, b)) ** 2\n",
                                     "    return 1.0 - abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real)\n"),
 }

@@ -346,3 +346,94 @@ def test_pade_theta_reproduces_higham_table():
     for m, val in table.items():
         assert pt.theta(m, 2.0 ** -53, n=120) == pytest.approx(val, rel=1e-14)
     assert oracle.THETA13_F64 == table[13]
+
+
+# --------------------------------------------------------- third-order term
+
+def _bch_cells(H0, Hk, u, dt):
+    """A_j = -i (H0 + sum_k u[k, j] H_k) of each cell j and the exact log of the
+    product exp(A_s dt) ... exp(A_1 dt) (scipy.linalg.logm)."""
+    A = [-1j * (H0 + sum(u[k, j] * Hk[k] for k in range(len(Hk)))) for j in range(u.shape[1])]
+    P = np.eye(H0.shape[0], dtype=complex)
+    for a in A:
+        P = sl.expm(a * dt) @ P
+    return A, sl.logm(P)
+
+
+def _omega3(H0, Hk, u, dt):
+    T = oracle.third_order_coefficients(u, dt, 1)
+    return -1j * oracle.third_order_term(H0, Hk, T)[0]
+
+
+def test_third_order_two_cells_is_bch():
+    # for two cells the third-order term is the degree-3 part of the
+    # Baker-Campbell-Hausdorff series, dt^3/12 ([A2,[A2,A1]] + [A1,[A1,A2]]), exactly
+    g = np.random.default_rng(21)
+    H0, Hk = wl.random_hermitian(4, g), np.stack([wl.random_hermitian(4, g) for _ in range(2)])
+    u = g.standard_normal((2, 2))
+    dt = 0.3
+    A1, A2 = [-1j * (H0 + u[0, j] * Hk[0] + u[1, j] * Hk[1]) for j in range(2)]
+    c = lambda X, Y: X @ Y - Y @ X
+    bch3 = dt ** 3 / 12.0 * (c(A2, c(A2, A1)) + c(A1, c(A1, A2)))
+    np.testing.assert_allclose(_omega3(H0, Hk, u, dt), bch3, atol=1e-15)
+
+
+def test_third_order_leaves_fourth_order_residual():
+    # over several cells, Omega_1 + Omega_2 + Omega_3 matches log of the exact
+    # product up to O(dt^4): halving dt divides the residual by 16
+    g = np.random.default_rng(22)
+    H0, Hk = wl.random_hermitian(3, g), np.stack([wl.random_hermitian(3, g)])
+    u = g.standard_normal((1, 5))
+    res = []
+    for dt in (0.08, 0.04, 0.02):
+        _, L = _bch_cells(H0, Hk, u, dt)
+        c1, c2 = oracle.interval_coefficients(u, dt, 1, 2)
+        Om12 = oracle.generators(H0, Hk, c1, c2, 5 * dt, 2)[0]
+        res.append(np.abs(L - Om12 - _omega3(H0, Hk, u, dt)).max())
+    ratios = [res[i] / res[i + 1] for i in range(2)]
+    assert all(14.0 < r < 18.0 for r in ratios), (res, ratios)
+
+
+def test_third_order_coefficients_by_cell_volumes():
+    # brute force over cell triples with the simplex volumes 1, 1/2, 1/6
+    g = np.random.default_rng(23)
+    u = g.standard_normal((2, 5))
+    dt = 0.7
+    T = oracle.third_order_coefficients(u, dt, 1)[0]
+    x = np.vstack([np.ones(5), u])
+    for a in range(3):
+        for b in range(3):
+            for c in range(3):
+                tot = 0.0
+                for i in range(5):
+                    for j in range(i + 1):
+                        for k in range(j + 1):
+                            vol = 1.0 if i > j > k else (1.0 / 6.0 if i == j == k else 0.5)
+                            tot += vol * x[a, i] * x[b, j] * x[c, k]
+                assert T[a, b, c] == pytest.approx(dt ** 3 * tot, rel=1e-13, abs=1e-15)
+
+
+def test_third_order_vanishes_for_constant_signals():
+    # a constant H commutes with itself at all times
+    g = np.random.default_rng(24)
+    H0, Hk = wl.random_hermitian(3, g), np.stack([wl.random_hermitian(3, g)])
+    u = np.full((1, 6), 0.8)
+    assert np.abs(_omega3(H0, Hk, u, 0.1)).max() < 1e-15
+
+
+def test_third_order_convergence():
+    # with the third-order term the method stays fourth order (its own error is of
+    # the size of the fourth-order term) but with a smaller constant than order 2
+    N = 2048
+    w = wl.random_system(3, 2, N, 1, 1, config_id=33, drift_scale=2.0, drive_scale=1.0, t_total=2.0)
+    ref = _fine_product(w)
+    errs = {}
+    for order in (2, 3):
+        errs[order] = [np.abs(oracle.run(w.H0, w.Hk, w.u, w.dt_sample, M, order, product=True)["P"] - ref).max()
+                       for M in (16, 32, 64)]
+    slopes = [math.log2(errs[3][i] / errs[3][i + 1]) for i in range(2)]
+    assert all(abs(x - 4.0) < 0.25 for x in slopes), slopes
+    assert all(e3 < 0.5 * e2 for e2, e3 in zip(errs[2], errs[3])), errs
+    # one sample per interval: every term beyond the first vanishes, the result is exact
+    r = oracle.run(w.H0, w.Hk, w.u[:, :64], w.dt_sample, 64, 3, product=True)
+    assert np.abs(r["T"]).max() > 0 and np.abs(oracle.third_order_term(w.H0, w.Hk, r["T"])).max() < 1e-14
