@@ -129,7 +129,7 @@ extern "C" {
  *   K, N       controls and samples; K >= 1, N >= 1, N % M == 0.
  *   dt_sample  cell width (> 0, finite).
  *   M          number of intervals; interval n owns samples [n*s, (n+1)*s), s = N/M.
- *   order      1 or 2.
+ *   order      1, 2 or 3 (3: K <= 3, else QCHEFF_EUNSUPPORTED).
  *   c1         [M][K] float64, device, written:
  *                c1[n][k] = dt_sample * sum_j u[k][n*s + j].
  *   c2         order 2: [M][K + K(K-1)/2] float64, device, written; ignored
@@ -140,6 +140,15 @@ extern "C" {
  *                c2[n][K+p] = dt^2 * sum_j sum_{i<j} (u_k[j] u_l[i] - u_l[j] u_k[i]).
  *              Both are the exact double integrals for a zero-order-hold
  *              signal.  Sums are compensated (Neumaier) in FP64.
+ *              Order 3 (the third-order term H-bar^(3) of Eq. magnus-exp): c2 is
+ *              [M][P2 + P3], P2 = K + K(K-1)/2 as above and then P3 = (K+1)K(K+3)/2
+ *              columns, one per index triple (a, b, c) of {0..K}^3 with a <= c and
+ *              not a = b = c, in the order a, then c, then b (index 0 is the drift,
+ *              x_0 = 1, and x_k = u_{k-1}):
+ *                c3[n][q] = T_abc + T_cba (a < c) or T_aba (a = c),
+ *                T_abc = int_{t3<t2<t1 in interval n} x_a(t1) x_b(t2) x_c(t3),
+ *              exact for a zero-order-hold signal (cells add dt^3 x_a x_b x_c, ties
+ *              half or a sixth of it).
  *   Returns QCHEFF_OK, QCHEFF_EINVAL (shapes, NULL pointers, order, N % M,
  *   dt_sample), QCHEFF_EDEVICE.
  */
@@ -150,7 +159,9 @@ int qcheff_magnus_coeffs(const double* u, int64_t K, int64_t N, double dt_sample
  * qcheff_magnus_generators - Omega_n = -i H-bar_n for M intervals
  * (Eq. magnus-first-order-term; second-order term of Eq. magnus-avg):
  *   H-bar_n = dt_interval H0 + sum_k c1[n][k] H_k
- *             - (i/2) ( sum_k c2[n][k] [H0,H_k] + sum_{k<l} c2[n][K+p(k,l)] [H_k,H_l] ).
+ *             - (i/2) ( sum_k c2[n][k] [H0,H_k] + sum_{k<l} c2[n][K+p(k,l)] [H_k,H_l] )
+ *             - (1/6) sum_q c3[n][q] ( [H_a,[H_b,H_c]] + [H_c,[H_b,H_a]] )   (order 3;
+ *   q over the triples of qcheff_magnus_coeffs, H_0 the drift).
  *
  *   H0         [d][d] Hermitian, device, op_dtype.
  *   Hk         [K][d][d] Hermitian, device, op_dtype.  Hermiticity is not checked.
@@ -161,14 +172,15 @@ int qcheff_magnus_coeffs(const double* u, int64_t K, int64_t N, double dt_sample
  *   dt_interval  interval length s*dt_sample.
  *   out_dtype  QCHEFF_C128 or QCHEFF_C64 (FP64 assembly, one rounding at the store).
  *   omega      [M][d][d] out_dtype, device, written.
- *   ws         order 2: holds the commutator basis, K + K(K-1)/2 matrices in
- *              C128, computed here (two-operator products on MFMA, FP64) unless
+ *   ws         orders 2 and 3: holds the commutator basis, K + K(K-1)/2 matrices
+ *              in C128 (order 3: then the P3 nested commutators and two scratch
+ *              matrices), computed here (products on MFMA, FP64) unless
  *              flags has QCHEFF_REUSE_BASIS, in which case ws must hold the
  *              basis of an earlier call with the same H0, Hk (the operators are
  *              unchanged when only the control signals change).  Order 1 needs
  *              no workspace.
  *   Returns QCHEFF_OK, QCHEFF_EINVAL, QCHEFF_EWORKSPACE, QCHEFF_EUNSUPPORTED
- *   (op_dtype other than C128, K > 8), QCHEFF_EDEVICE.
+ *   (op_dtype other than C128, K > 8, or K > 3 at order 3), QCHEFF_EDEVICE.
  */
 int qcheff_magnus_generators(const void* H0, const void* Hk, int64_t d, int64_t K, int op_dtype,
                              const double* c1, const double* c2, int64_t M, double dt_interval,

@@ -138,17 +138,25 @@ def _workspace(nbytes: int, device) -> torch.Tensor | None:
 
 # --------------------------------------------------------------------- ABI
 
+def c2_columns(K: int, order: int) -> int:
+    """Columns of the coefficient table c2: K + K(K-1)/2 second-order ones, and at
+    order 3 the (K+1)K(K+3)/2 third-order ones after them."""
+    if order < 2:
+        return 0
+    return K + K * (K - 1) // 2 + ((K + 1) * K * (K + 3) // 2 if order == 3 else 0)
+
+
 def magnus_coeffs(u: torch.Tensor, dt_sample: float, M: int, order: int, c1=None, c2=None, stream=None):
     """Per-interval coefficients (qcheff_magnus_coeffs).  u: [K][N] float64 on the GPU."""
     _dev(u, "u")
     K, N = u.shape
     if c1 is None:
         c1 = torch.empty((M, K), dtype=torch.float64, device=u.device)
-    if order == 2 and c2 is None:
-        c2 = torch.empty((M, K + K * (K - 1) // 2), dtype=torch.float64, device=u.device)
+    if order >= 2 and c2 is None:
+        c2 = torch.empty((M, c2_columns(K, order)), dtype=torch.float64, device=u.device)
     _check("qcheff_magnus_coeffs", lib().qcheff_magnus_coeffs(
-        _ptr(u), K, N, float(dt_sample), M, order, _ptr(c1), _ptr(c2) if order == 2 else None, _stream(stream)))
-    return c1, (c2 if order == 2 else None)
+        _ptr(u), K, N, float(dt_sample), M, order, _ptr(c1), _ptr(c2) if order >= 2 else None, _stream(stream)))
+    return c1, (c2 if order >= 2 else None)
 
 
 def magnus_generators(H0, Hk, c1, c2, dt_interval: float, order: int, out_dtype=torch.complex64,

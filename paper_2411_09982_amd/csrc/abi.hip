@@ -284,8 +284,13 @@ int scratch_for_current_device(double2** out) {
 int run_coeffs(const double* u, int64_t K, int64_t N, double dt, int64_t M, int order, double* c1,
                double* c2, hipStream_t st) {
   const int64_t s = N / M;
+  const int ldc2 = int(n_c2_cols(K, order));
   // one wave per interval, four per workgroup
-  hipLaunchKernelGGL(coeffs_kernel, dim3(nblocks(M, 4)), dim3(256), 0, st, u, int(K), N, M, s, dt, order, c1, c2);
+  hipLaunchKernelGGL(coeffs_kernel, dim3(nblocks(M, 4)), dim3(256), 0, st, u, int(K), N, M, s, dt, order, c1, c2,
+                     ldc2);
+  if (order == 3)
+    hipLaunchKernelGGL(coeffs3_kernel, dim3(nblocks(M, 4)), dim3(256), 0, st, u, int(K), N, M, s, dt, ldc2,
+                       int(n_c2(K)), c2);
   QC_HIP(hipGetLastError());
   return QCHEFF_OK;
 }
@@ -295,7 +300,7 @@ template <int K, int ORDER, typename OutC2>
 hipError_t launch_generators(const double2* H0, const double2* Hk, const double2* Cb, int64_t d,
                              const double* c1, const double* c2, int64_t M, double dt, OutC2* omega,
                              hipStream_t st) {
-  constexpr int NC = K + ((ORDER == 2) ? K + K * (K - 1) / 2 : 0);
+  constexpr int NC = K + ((ORDER >= 2) ? K + K * (K - 1) / 2 : 0) + ((ORDER == 3) ? (K + 1) * K * (K + 3) / 2 : 0);
   const int64_t dd = d * d;
   // A block reads its operator values once per chunk of nch intervals, so the
   // chunks are as long as 48 KB of coefficients allow, unless the grid would
@@ -314,12 +319,21 @@ template <int ORDER, typename OutC2>
 hipError_t dispatch_generators(int K, const double2* H0, const double2* Hk, const double2* Cb, int64_t d,
                                const double* c1, const double* c2, int64_t M, double dt, OutC2* omega,
                                hipStream_t st) {
-  switch (K) {
+  if constexpr (ORDER == 3) {   // the third-order term takes K <= 3
+    switch (K) {
+      case 1: return launch_generators<1, 3, OutC2>(H0, Hk, Cb, d, c1, c2, M, dt, omega, st);
+      case 2: return launch_generators<2, 3, OutC2>(H0, Hk, Cb, d, c1, c2, M, dt, omega, st);
+      case 3: return launch_generators<3, 3, OutC2>(H0, Hk, Cb, d, c1, c2, M, dt, omega, st);
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (K) {
 #define QC_CASE(k) \
   case k: return launch_generators<k, ORDER, OutC2>(H0, Hk, Cb, d, c1, c2, M, dt, omega, st);
-    QC_CASE(1) QC_CASE(2) QC_CASE(3) QC_CASE(4) QC_CASE(5) QC_CASE(6) QC_CASE(7) QC_CASE(8)
+      QC_CASE(1) QC_CASE(2) QC_CASE(3) QC_CASE(4) QC_CASE(5) QC_CASE(6) QC_CASE(7) QC_CASE(8)
 #undef QC_CASE
-    default: return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
   }
 }
 
@@ -335,12 +349,27 @@ int commutator(const double2* F, const double2* G, double2* C, int64_t d, hipStr
   return QCHEFF_OK;
 }
 
+// [H_b, H_c] from the second-order basis (0 is the drift): [H0, H_k] is basis
+// entry k - 1, [H_k, H_l] (k < l) entry K + pair(k - 1, l - 1); [H_c, H_b] = -[H_b, H_c].
+// Returns the entry and the sign, or sign 0 for b == c.
+int comm_entry(int b, int c, int K, int* sign) {
+  if (b == c) {
+    *sign = 0;
+    return 0;
+  }
+  *sign = b < c ? 1 : -1;
+  const int lo = std::min(b, c), hi = std::max(b, c);
+  if (lo == 0) return hi - 1;
+  const int k = lo - 1, l = hi - 1;
+  return K + k * K - k * (k + 1) / 2 + (l - k - 1);
+}
+
 int run_generators(const double2* H0, const double2* Hk, int64_t d, int64_t K, const double* c1,
                    const double* c2, int64_t M, double dt, int order, int out_dtype, void* omega,
                    void* ws, unsigned flags, hipStream_t st) {
   double2* Cb = static_cast<double2*>(ws);
   const int64_t dd = d * d;
-  if (order == 2 && !(flags & QCHEFF_REUSE_BASIS)) {
+  if (order >= 2 && !(flags & QCHEFF_REUSE_BASIS)) {
     int q = 0;
     for (int64_t k = 0; k < K; ++k, ++q) {
       int r = commutator(H0, Hk + k * dd, Cb + q * dd, d, st);
@@ -351,15 +380,54 @@ int run_generators(const double2* H0, const double2* Hk, int64_t d, int64_t K, c
         int r = commutator(Hk + k * dd, Hk + l * dd, Cb + q * dd, d, st);
         if (r) return r;
       }
+    if (order == 3) {
+      // [H_a, [H_b, H_c]] + [H_c, [H_b, H_a]] for the triples of the third-order term,
+      // each [H, D] = H D + (H D)^dag formed from one FP64 product
+      const int P2 = int(n_c2(K));
+      double2* C3 = Cb + int64_t(P2) * dd;
+      double2* X1 = C3 + n_c3(K) * dd;
+      double2* X2 = X1 + dd;
+      auto H = [&](int a) { return a == 0 ? H0 : Hk + int64_t(a - 1) * dd; };
+      auto product = [&](int a, int b, int c, double2* X) -> int {   // X = H_a [H_b, H_c], or 0 if b == c
+        int sign;
+        const int ent = comm_entry(b, c, int(K), &sign);
+        if (!sign) return 0;
+        auto p = gemm_params<double>(int(d), int(d), int(d), 1);
+        p.A = H(a); p.lda = d; p.sA = 0;
+        p.B = Cb + int64_t(ent) * dd; p.ldb = d; p.sB = 0;
+        p.C = X; p.ldc = d; p.sC = 0;
+        p.alpha = double(sign);
+        QC_HIP((launch_cgemm<double>(p, st)));
+        return 1;
+      };
+      int t = 0;
+      for (int a = 0; a <= K; ++a)
+        for (int c = a; c <= K; ++c)
+          for (int b = 0; b <= K; ++b) {
+            if (a == b && b == c) continue;
+            const int u1 = product(a, b, c, X1);
+            if (u1 < 0) return u1;
+            const int u2 = product(c, b, a, X2);
+            if (u2 < 0) return u2;
+            hipLaunchKernelGGL(hermitian_sum_kernel, dim3(nblocks(dd, 256)), dim3(256), 0, st, u1 ? X1 : nullptr,
+                               u2 ? X2 : nullptr, C3 + int64_t(t) * dd, int(d));
+            QC_HIP(hipGetLastError());
+            ++t;
+          }
+    }
   }
   if (M == 0) return QCHEFF_OK;
   hipError_t e;
   if (out_dtype == QCHEFF_C128) {
-    e = (order == 2) ? dispatch_generators<2>(int(K), H0, Hk, Cb, d, c1, c2, M, dt, static_cast<double2*>(omega), st)
-                     : dispatch_generators<1>(int(K), H0, Hk, Cb, d, c1, c2, M, dt, static_cast<double2*>(omega), st);
+    double2* om = static_cast<double2*>(omega);
+    e = order == 3   ? dispatch_generators<3>(int(K), H0, Hk, Cb, d, c1, c2, M, dt, om, st)
+        : order == 2 ? dispatch_generators<2>(int(K), H0, Hk, Cb, d, c1, c2, M, dt, om, st)
+                     : dispatch_generators<1>(int(K), H0, Hk, Cb, d, c1, c2, M, dt, om, st);
   } else {
-    e = (order == 2) ? dispatch_generators<2>(int(K), H0, Hk, Cb, d, c1, c2, M, dt, static_cast<float2*>(omega), st)
-                     : dispatch_generators<1>(int(K), H0, Hk, Cb, d, c1, c2, M, dt, static_cast<float2*>(omega), st);
+    float2* om = static_cast<float2*>(omega);
+    e = order == 3   ? dispatch_generators<3>(int(K), H0, Hk, Cb, d, c1, c2, M, dt, om, st)
+        : order == 2 ? dispatch_generators<2>(int(K), H0, Hk, Cb, d, c1, c2, M, dt, om, st)
+                     : dispatch_generators<1>(int(K), H0, Hk, Cb, d, c1, c2, M, dt, om, st);
   }
   QC_HIP(e);
   return QCHEFF_OK;

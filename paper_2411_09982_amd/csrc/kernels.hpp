@@ -75,28 +75,28 @@ __device__ __forceinline__ double wave_inclusive_scan(double x, int lane) {
 
 __global__ __launch_bounds__(256) void coeffs_kernel(const double* __restrict__ u, int K, int64_t N, int64_t M,
                                                      int64_t s, double dt, int order, double* __restrict__ c1,
-                                                     double* __restrict__ c2) {
+                                                     double* __restrict__ c2, int ldc2) {
   const int lane = threadIdx.x & 63;
   const int64_t n = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (n >= M) return;   // a whole wave leaves together
   const int64_t base = n * s;
-  const int P2 = K + K * (K - 1) / 2;
+  const int P2 = ldc2;   // row stride of c2 (the second-order columns come first)
   for (int k = 0; k < K; ++k) {
     const double* uk = u + int64_t(k) * N + base;
     Neumaier sum, wsum;
     for (int64_t j = lane; j < s; j += 64) {
       const double x = uk[j];
       sum.add(x);
-      if (order == 2) wsum.add(double(s - 1 - 2 * j) * x);
+      if (order >= 2) wsum.add(double(s - 1 - 2 * j) * x);
     }
     const double c1v = wave_sum_compensated(sum.s, sum.c);
     const double c20 = wave_sum_compensated(wsum.s, wsum.c);
     if (lane == 0) {
       c1[n * K + k] = dt * c1v;
-      if (order == 2) c2[n * P2 + k] = dt * dt * c20;
+      if (order >= 2) c2[n * P2 + k] = dt * dt * c20;
     }
   }
-  if (order != 2) return;
+  if (order < 2) return;
   int p = K;
   for (int k = 0; k < K; ++k) {
     for (int l = k + 1; l < K; ++l, ++p) {
@@ -118,6 +118,89 @@ __global__ __launch_bounds__(256) void coeffs_kernel(const double* __restrict__ 
       if (lane == 0) c2[n * P2 + p] = dt * dt * v;
     }
   }
+}
+
+// Third-order coefficients: for the index triples q = (a, b, c) of {0..K}^3 with
+// a <= c and not a = b = c (in the order a, then c, then b; x_0 = 1 is the drift,
+// x_k = u_{k-1}), c2[n][col0 + q] = T_abc + T_cba (a < c) or T_aba (a = c), where
+// T_abc = int_{t3<t2<t1} x_a(t1) x_b(t2) x_c(t3) over interval n.  For a
+// zero-order-hold signal, cells i > j > k add dt^3 x_a[i] x_b[j] x_c[k], ties add
+// half (i = j or j = k) or a sixth (all equal) of that; with running sums
+// C = sum_{k<j} x_c[k], Q = sum_{j<i} x_b[j] C[j], R = sum_{j<i} x_b[j] x_c[j] each
+// cell i adds x_a[i] (Q + x_b[i] C / 2 + R / 2 + x_b[i] x_c[i] / 6).  One wave per
+// interval, one lane per triple walking the samples in time order; the samples
+// pass through LDS in tiles of 256 per control, loaded by the whole wave.
+constexpr int kC3Tile = 256;
+
+__device__ __forceinline__ bool c3_triple(int q, int K, int& a, int& b, int& c) {
+  int r = 0;
+  for (a = 0; a <= K; ++a)
+    for (c = a; c <= K; ++c)
+      for (b = 0; b <= K; ++b) {
+        if (a == b && b == c) continue;
+        if (r++ == q) return true;
+      }
+  return false;
+}
+
+__global__ __launch_bounds__(256) void coeffs3_kernel(const double* __restrict__ u, int K, int64_t N, int64_t M,
+                                                      int64_t s, double dt, int ldc2, int col0,
+                                                      double* __restrict__ c2) {
+  __shared__ double tile[4][3][kC3Tile];   // per wave, K <= 3 controls
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t n = int64_t(blockIdx.x) * 4 + wave;
+  int a = 0, b = 0, c = 0;
+  const bool mine = n < M && c3_triple(lane, K, a, b, c);
+  double C1 = 0.0, Q1 = 0.0, R1 = 0.0, C2 = 0.0, Q2 = 0.0, R2 = 0.0;
+  Neumaier T1, T2;
+  for (int64_t t0 = 0; t0 < s; t0 += kC3Tile) {   // the same trip count in every wave
+    const int cnt = int(min(int64_t(kC3Tile), s - t0));
+    if (n < M)
+      for (int k = 0; k < K; ++k)
+        for (int l = lane; l < cnt; l += 64) tile[wave][k][l] = u[int64_t(k) * N + n * s + t0 + l];
+    __syncthreads();
+    if (mine) {
+      for (int i = 0; i < cnt; ++i) {
+        const double xa = a ? tile[wave][a - 1][i] : 1.0;
+        const double xb = b ? tile[wave][b - 1][i] : 1.0;
+        const double xc = c ? tile[wave][c - 1][i] : 1.0;
+        T1.add(xa * (Q1 + 0.5 * xb * C1 + 0.5 * R1 + xb * xc * (1.0 / 6.0)));
+        Q1 += xb * C1;
+        R1 += xb * xc;
+        C1 += xc;
+        T2.add(xc * (Q2 + 0.5 * xb * C2 + 0.5 * R2 + xb * xa * (1.0 / 6.0)));
+        Q2 += xb * C2;
+        R2 += xb * xa;
+        C2 += xa;
+      }
+    }
+    __syncthreads();
+  }
+  if (mine) {
+    const double v = a < c ? T1.value() + T2.value() : T1.value();
+    c2[n * ldc2 + col0 + lane] = dt * dt * dt * v;
+  }
+}
+
+// C = (X1 + X1^dag) + (X2 + X2^dag) for square d x d matrices (X1 or X2 null: left
+// out): the third-order basis element [H_a, D1] + [H_c, D2] from X1 = H_a D1,
+// X2 = H_c D2 with Hermitian H and anti-Hermitian D (then [H, D] = H D + (H D)^dag).
+__global__ void hermitian_sum_kernel(const double2* __restrict__ X1, const double2* __restrict__ X2,
+                                     double2* __restrict__ C, int d) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= int64_t(d) * d) return;
+  const int64_t i = e / d, j = e % d;
+  const int64_t t = j * d + i;
+  double re = 0.0, im = 0.0;
+  if (X1) {
+    re += X1[e].x + X1[t].x;
+    im += X1[e].y - X1[t].y;
+  }
+  if (X2) {
+    re += X2[e].x + X2[t].x;
+    im += X2[e].y - X2[t].y;
+  }
+  C[e] = make_double2(re, im);
 }
 
 // ------------------------------------------------------ commutator basis
@@ -142,7 +225,8 @@ __global__ void antihermitian_part_kernel(double2* X, int d) {
 
 // ------------------------------------------------------------- generators
 //
-// Omega_n[e] = -i ( dt H0[e] + sum_k c1[n][k] H_k[e] - (i/2) sum_p c2[n][p] C_p[e] )
+// Omega_n[e] = -i ( dt H0[e] + sum_k c1[n][k] H_k[e] - (i/2) sum_p c2[n][p] C_p[e]
+//                  - (1/6) sum_q c3[n][q] C3_q[e] )   (the last term at order 3)
 // One thread per matrix element e holds the operator values in registers and
 // walks a chunk of intervals; coefficients of the chunk sit in LDS.
 template <int K, int ORDER, typename OutC2>
@@ -152,14 +236,15 @@ __global__ __launch_bounds__(256) void generators_kernel(const double2* __restri
                                                          const double* __restrict__ c1,
                                                          const double* __restrict__ c2, int64_t M,
                                                          int nch, double dt, OutC2* __restrict__ omega) {
-  constexpr int P2 = (ORDER == 2) ? K + K * (K - 1) / 2 : 0;
-  constexpr int NC = K + P2;
+  constexpr int P2 = (ORDER >= 2) ? K + K * (K - 1) / 2 : 0;
+  constexpr int P3 = (ORDER == 3) ? (K + 1) * K * (K + 3) / 2 : 0;
+  constexpr int NC = K + P2 + P3;
   extern __shared__ double sh[];  // [nch][NC]
   const int64_t n0 = int64_t(blockIdx.y) * nch;
   const int cnt = int(min(int64_t(nch), M - n0));
   for (int i = threadIdx.x; i < cnt * NC; i += blockDim.x) {
     const int r = i / NC, q = i % NC;
-    sh[i] = (q < K) ? c1[(n0 + r) * K + q] : c2[(n0 + r) * P2 + (q - K)];
+    sh[i] = (q < K) ? c1[(n0 + r) * K + q] : c2[(n0 + r) * (P2 + P3) + (q - K)];
   }
   __syncthreads();
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -168,9 +253,9 @@ __global__ __launch_bounds__(256) void generators_kernel(const double2* __restri
   double2 hk[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) hk[k] = Hk[int64_t(k) * dd + e];
-  double2 cb[P2 > 0 ? P2 : 1];
+  double2 cb[P2 + P3 > 0 ? P2 + P3 : 1];   // second-order basis, then the third-order one
 #pragma unroll
-  for (int q = 0; q < P2; ++q) cb[q] = Cb[int64_t(q) * dd + e];
+  for (int q = 0; q < P2 + P3; ++q) cb[q] = Cb[int64_t(q) * dd + e];
   for (int r = 0; r < cnt; ++r) {
     const double* cf = sh + r * NC;
     double hr = dt * h0.x, hi = dt * h0.y;
@@ -179,7 +264,7 @@ __global__ __launch_bounds__(256) void generators_kernel(const double2* __restri
       hr += cf[k] * hk[k].x;
       hi += cf[k] * hk[k].y;
     }
-    if constexpr (ORDER == 2) {
+    if constexpr (ORDER >= 2) {
       double sr = 0.0, si = 0.0;
 #pragma unroll
       for (int q = 0; q < P2; ++q) {
@@ -188,6 +273,17 @@ __global__ __launch_bounds__(256) void generators_kernel(const double2* __restri
       }
       hr += 0.5 * si;   // -(i/2) (sr + i si) = si/2 - i sr/2
       hi -= 0.5 * sr;
+    }
+    if constexpr (ORDER == 3) {
+      // -(1/6) sum_q c3[q] ([H_a,[H_b,H_c]] + [H_c,[H_b,H_a]])
+      double tr = 0.0, ti = 0.0;
+#pragma unroll
+      for (int q = 0; q < P3; ++q) {
+        tr += cf[K + P2 + q] * cb[P2 + q].x;
+        ti += cf[K + P2 + q] * cb[P2 + q].y;
+      }
+      hr -= tr * (1.0 / 6.0);
+      hi -= ti * (1.0 / 6.0);
     }
     omega[(n0 + r) * dd + e] = to_c2<OutC2>(hi, -hr);  // -i (hr + i hi)
   }

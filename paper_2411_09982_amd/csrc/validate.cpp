@@ -18,27 +18,31 @@ static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 Check check_coeffs(const void* u, int64_t K, int64_t N, double dt_sample, int64_t M, int order,
                    const void* c1, const void* c2) {
-  if (order != 1 && order != 2) return Check::fail(QCHEFF_EINVAL, "order must be 1 or 2");
+  if (order < 1 || order > 3) return Check::fail(QCHEFF_EINVAL, "order must be 1, 2 or 3");
   if (K < 1) return Check::fail(QCHEFF_EINVAL, "K must be >= 1");
   if (N < 1 || M < 1) return Check::fail(QCHEFF_EINVAL, "N and M must be >= 1");
   if (N % M != 0) return Check::fail(QCHEFF_EINVAL, "N must be a multiple of M");
   if (!finite_pos(dt_sample)) return Check::fail(QCHEFF_EINVAL, "dt_sample must be finite and > 0");
   if (!u || !c1) return Check::fail(QCHEFF_EINVAL, "u and c1 must not be NULL");
-  if (order == 2 && !c2) return Check::fail(QCHEFF_EINVAL, "c2 must not be NULL for order 2");
+  if (order >= 2 && !c2) return Check::fail(QCHEFF_EINVAL, "c2 must not be NULL for order 2 or 3");
+  if (order == 3 && K > kMaxControls3)
+    return Check::fail(QCHEFF_EUNSUPPORTED, "the third-order term takes at most 3 controls");
   if (K > 4096 || N > (int64_t(1) << 40)) return Check::fail(QCHEFF_EINVAL, "K or N too large");
   return Check::ok();
 }
 
 size_t generators_ws_bytes(int64_t d, int64_t K, int order) {
-  if (order != 2) return 0;
-  return align256(size_t(n_c2(K)) * size_t(d) * size_t(d) * 16);
+  if (order == 2) return align256(size_t(n_c2(K)) * size_t(d) * size_t(d) * 16);
+  // order 3: both bases and two scratch products
+  if (order == 3) return align256(size_t(n_c2(K) + n_c3(K) + 2) * size_t(d) * size_t(d) * 16);
+  return 0;
 }
 
 Check check_generators(const void* H0, const void* Hk, int64_t d, int64_t K, int op_dtype,
                        const void* c1, const void* c2, int64_t M, double dt_interval, int order,
                        int out_dtype, const void* omega, const void* ws, size_t ws_bytes,
                        unsigned flags) {
-  if (order != 1 && order != 2) return Check::fail(QCHEFF_EINVAL, "order must be 1 or 2");
+  if (order < 1 || order > 3) return Check::fail(QCHEFF_EINVAL, "order must be 1, 2 or 3");
   if (d < 1 || d > kMaxDim) return Check::fail(QCHEFF_EINVAL, "d must be in [1, 16384]");
   if (K < 1) return Check::fail(QCHEFF_EINVAL, "K must be >= 1");
   if (M < 0) return Check::fail(QCHEFF_EINVAL, "M must be >= 0");
@@ -48,11 +52,13 @@ Check check_generators(const void* H0, const void* Hk, int64_t d, int64_t K, int
     return Check::fail(QCHEFF_EINVAL, "unknown dtype");
   if (op_dtype != QCHEFF_C128) return Check::fail(QCHEFF_EUNSUPPORTED, "operators must be QCHEFF_C128");
   if (K > kMaxControls) return Check::fail(QCHEFF_EUNSUPPORTED, "at most 8 controls");
+  if (order == 3 && K > kMaxControls3)
+    return Check::fail(QCHEFF_EUNSUPPORTED, "the third-order term takes at most 3 controls");
   if (!H0 || !Hk) return Check::fail(QCHEFF_EINVAL, "H0 and Hk must not be NULL");
   if (M > 0 && (!c1 || !omega)) return Check::fail(QCHEFF_EINVAL, "c1 and omega must not be NULL");
-  if (order == 2 && M > 0 && !c2) return Check::fail(QCHEFF_EINVAL, "c2 must not be NULL for order 2");
-  if (order == 2) {
-    if (!ws) return Check::fail(QCHEFF_EWORKSPACE, "order 2 needs a workspace for the commutator basis");
+  if (order >= 2 && M > 0 && !c2) return Check::fail(QCHEFF_EINVAL, "c2 must not be NULL for order 2 or 3");
+  if (order >= 2) {
+    if (!ws) return Check::fail(QCHEFF_EWORKSPACE, "orders 2 and 3 need a workspace for the commutator basis");
     if (ws_bytes < generators_ws_bytes(d, K, order))
       return Check::fail(QCHEFF_EWORKSPACE, "workspace too small for the commutator basis");
   }
@@ -189,7 +195,7 @@ size_t workspace_bytes(int fn, int64_t batch, int64_t d, int64_t K, int order, i
   if (d < 1 || d > kMaxDim) return 0;
   switch (fn) {
     case QCHEFF_FN_GENERATORS:
-      if (K < 1 || (order != 1 && order != 2)) return 0;
+      if (K < 1 || order < 1 || order > 3 || (order == 3 && K > kMaxControls3)) return 0;
       return generators_ws_bytes(d, K, order);
     case QCHEFF_FN_EXPM:
       return expm_ws_bytes(batch, d, dtype == QCHEFF_C64_BF16X3 ? QCHEFF_C64 : dtype);

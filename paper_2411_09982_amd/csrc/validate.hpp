@@ -23,6 +23,13 @@ struct Check {
 
 inline int64_t n_pairs(int64_t K) { return K * (K - 1) / 2; }
 inline int64_t n_c2(int64_t K) { return K + n_pairs(K); }
+// Third-order basis: the index triples (a, b, c) of {0..K}^3 with a <= c, not
+// a = b = c (x_0 the drift), whose nested commutators [H_a,[H_b,H_c]] + [H_c,[H_b,H_a]]
+// weight the third-order term; (K+1) K (K+3) / 2 of them.
+inline int64_t n_c3(int64_t K) { return (K + 1) * K * (K + 3) / 2; }
+constexpr int64_t kMaxControls3 = 3;    // largest K of the third-order term
+// columns of the coefficient table c2 for `order` (second-order ones first)
+inline int64_t n_c2_cols(int64_t K, int order) { return order == 3 ? n_c2(K) + n_c3(K) : order == 2 ? n_c2(K) : 0; }
 size_t elem_bytes(int dtype);   // 16 for C128, 8 for C64, 0 otherwise
 
 Check check_coeffs(const void* u, int64_t K, int64_t N, double dt_sample, int64_t M, int order,

@@ -34,7 +34,7 @@ def test_coeffs_validation():
     L = q.lib()
     assert L.qcheff_magnus_coeffs(FAKE, 1, 10, 0.1, 3, 1, FAKE, None, None) == q.EINVAL
     assert "multiple" in _err()
-    assert L.qcheff_magnus_coeffs(FAKE, 1, 10, 0.1, 5, 3, FAKE, FAKE, None) == q.EINVAL
+    assert L.qcheff_magnus_coeffs(FAKE, 1, 10, 0.1, 5, 4, FAKE, FAKE, None) == q.EINVAL
     assert "order" in _err()
     assert L.qcheff_magnus_coeffs(FAKE, 1, 10, 0.1, 5, 2, FAKE, None, None) == q.EINVAL
     assert L.qcheff_magnus_coeffs(None, 1, 10, 0.1, 5, 1, FAKE, None, None) == q.EINVAL
@@ -191,3 +191,16 @@ def test_npad_validation():
     lg = L.qcheff_npad_largest
     assert lg(FAKE, 10, q.C64, None, None, FAKE, need, None) == q.EINVAL        # ij_out
     assert lg(FAKE, 10, q.C64, FAKE, None, None, 0, None) == q.EWORKSPACE
+
+
+def test_order3_validation():
+    L = q.lib()
+    assert L.qcheff_magnus_coeffs(FAKE, 4, 10, 0.1, 5, 3, FAKE, FAKE, None) == q.EUNSUPPORTED   # K > 3
+    assert L.qcheff_magnus_coeffs(FAKE, 2, 10, 0.1, 5, 4, FAKE, FAKE, None) == q.EINVAL        # order 4
+    assert L.qcheff_magnus_coeffs(FAKE, 2, 10, 0.1, 5, 3, FAKE, None, None) == q.EINVAL        # no c2
+    # basis: K + K(K-1)/2 commutators, (K+1)K(K+3)/2 nested ones, two scratch matrices
+    assert q.workspace_bytes(q.FN_GENERATORS, 1, 4, 2, 3, q.C128) == (3 + 15 + 2) * 16 * 16
+    assert q.workspace_bytes(q.FN_GENERATORS, 1, 4, 4, 3, q.C128) == 0
+    g = L.qcheff_magnus_generators
+    assert g(FAKE, FAKE, 4, 4, q.C128, FAKE, FAKE, 3, 0.1, 3, q.C64, FAKE, FAKE, 1 << 20, 0, None) == q.EUNSUPPORTED
+    assert q.c2_columns(2, 3) == 3 + 15 and q.c2_columns(3, 2) == 6 and q.c2_columns(1, 1) == 0
