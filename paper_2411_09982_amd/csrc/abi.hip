@@ -497,8 +497,9 @@ struct LuCtx {
 int lu_gemm_update(const LuCtx& c, int64_t r0, int64_t r1, int64_t c0, int64_t c1, int64_t k0, int64_t k1) {
   // A[r0:r1, c0:c1] -= A[r0:r1, k0:k1] * A[k0:k1, c0:c1]
   if (r1 <= r0 || c1 <= c0 || k1 <= k0) return QCHEFF_OK;
-  // narrow updates (a 32-row leaf block, a 16-column panel) take the small tile
-  const int cfg = (r1 - r0 <= 48 || c1 - c0 <= 48) ? 1 : rule_cfg(c.d);
+  // narrow updates (a 32-row leaf block, a 16-column panel) and short ones
+  // (K <= 64, bound by reading and writing C) take the small tile
+  const int cfg = (r1 - r0 <= 48 || c1 - c0 <= 48 || k1 - k0 <= 64) ? 1 : rule_cfg(c.d);
   auto p = gemm_params<double>(int(r1 - r0), int(c1 - c0), int(k1 - k0), int(c.nb), cfg);
   p.A = c.aug + r0 * c.ld + k0; p.lda = c.ld; p.sA = c.stride;
   p.B = c.aug + k0 * c.ld + c0; p.ldb = c.ld; p.sB = c.stride;
@@ -524,8 +525,13 @@ int64_t split_point(int64_t r0, int64_t r1, int64_t unit) {
 // X <- L^{-1} X, L unit lower on rows/cols [r0, r1), X = A[r0:r1, c0:c1]
 int trsm_lower(const LuCtx& c, int64_t r0, int64_t r1, int64_t c0, int64_t c1) {
   if (r1 - r0 <= kTrsmNb) {
-    hipLaunchKernelGGL(trsm_lower_unit_kernel, dim3(nblocks(c1 - c0, 256), unsigned(c.nb)), dim3(256), 0, c.st,
-                       c.aug, c.ld, c.stride, int(r0), int(r1), int(c0), int(c1));
+    const dim3 grid(nblocks(c1 - c0, 256), unsigned(c.nb));
+    if (r1 - r0 == kTrsmNb)
+      hipLaunchKernelGGL(trsm_lower_unit_kernel, grid, dim3(256), 0, c.st, c.aug, c.ld, c.stride, int(r0), int(c0),
+                         int(c1));
+    else
+      hipLaunchKernelGGL(trsm_lower_unit_ragged_kernel, grid, dim3(256), 0, c.st, c.aug, c.ld, c.stride, int(r0),
+                         int(r1), int(c0), int(c1));
     QC_HIP(hipGetLastError());
     return QCHEFF_OK;
   }
@@ -539,8 +545,13 @@ int trsm_lower(const LuCtx& c, int64_t r0, int64_t r1, int64_t c0, int64_t c1) {
 // X <- U^{-1} X, U upper on rows/cols [r0, r1), X = A[r0:r1, c0:c1]
 int trsm_upper(const LuCtx& c, int64_t r0, int64_t r1, int64_t c0, int64_t c1) {
   if (r1 - r0 <= kTrsmNb) {
-    hipLaunchKernelGGL(trsm_upper_kernel, dim3(nblocks(c1 - c0, 256), unsigned(c.nb)), dim3(256), 0, c.st, c.aug,
-                       c.ld, c.stride, int(r0), int(r1), int(c0), int(c1));
+    const dim3 grid(nblocks(c1 - c0, 256), unsigned(c.nb));
+    if (r1 - r0 == kTrsmNb)
+      hipLaunchKernelGGL(trsm_upper_kernel, grid, dim3(256), 0, c.st, c.aug, c.ld, c.stride, int(r0), int(c0),
+                         int(c1));
+    else
+      hipLaunchKernelGGL(trsm_upper_ragged_kernel, grid, dim3(256), 0, c.st, c.aug, c.ld, c.stride, int(r0), int(r1),
+                         int(c0), int(c1));
     QC_HIP(hipGetLastError());
     return QCHEFF_OK;
   }
@@ -564,15 +575,25 @@ int lu_panel(const LuCtx& c, int64_t k0, int64_t k1) {
   return QCHEFF_OK;
 }
 
-int lu_factor(const LuCtx& c, int64_t k0, int64_t k1) {
-  if (k1 - k0 <= c.panel_nb) return lu_panel(c, k0, k1);
-  const int64_t km = split_point(k0, k1, c.panel_nb);
+// Factors columns [k0, k1) and applies their L (row interchanges, forward
+// solve) to the columns [k1, cend) as well.  Called with cend = k1 inside the
+// left half; along the right edge of the recursion (k1 = d) cend = 2d carries the
+// right-hand sides p, so their forward solve rides in the same launches as the
+// factorization's own updates instead of a recursion of its own.
+int lu_factor(const LuCtx& c, int64_t k0, int64_t k1, int64_t cend) {
   int r;
-  if ((r = lu_factor(c, k0, km))) return r;
-  if ((r = lu_pivots(c, k0, km, km, k1))) return r;          // left pivots on the right half
-  if ((r = trsm_lower(c, k0, km, km, k1))) return r;         // U12 = L11^{-1} A12
-  if ((r = lu_gemm_update(c, km, c.d, km, k1, k0, km))) return r;  // A22 -= L21 U12
-  if ((r = lu_factor(c, km, k1))) return r;
+  if (k1 - k0 <= c.panel_nb) {
+    if ((r = lu_panel(c, k0, k1))) return r;
+    if (cend <= k1) return QCHEFF_OK;
+    if ((r = lu_pivots(c, k0, k1, k1, cend))) return r;
+    return trsm_lower(c, k0, k1, k1, cend);
+  }
+  const int64_t km = split_point(k0, k1, c.panel_nb);
+  if ((r = lu_factor(c, k0, km, km))) return r;
+  if ((r = lu_pivots(c, k0, km, km, cend))) return r;          // left pivots on the right part
+  if ((r = trsm_lower(c, k0, km, km, cend))) return r;         // U12 = L11^{-1} A12
+  if ((r = lu_gemm_update(c, km, c.d, km, cend, k0, km))) return r;  // A22 -= L21 U12
+  if ((r = lu_factor(c, km, k1, cend))) return r;
   return lu_pivots(c, km, k1, k0, km);                       // right pivots on the left half's L
 }
 
@@ -580,9 +601,7 @@ int lu_solve(double2* aug, int* piv, int64_t d, int64_t nb, hipStream_t st) {
   LuCtx c{aug, piv, d, 2 * d, 2 * d * d, nb, st, 32, 0};
   if (d <= 1024) { c.panel_nb = 16; c.panel_rows = 1024; }
   int r;
-  if ((r = lu_factor(c, 0, d))) return r;
-  if ((r = lu_pivots(c, 0, d, d, 2 * d))) return r;          // P p
-  if ((r = trsm_lower(c, 0, d, d, 2 * d))) return r;         // Y = L^{-1} P p
+  if ((r = lu_factor(c, 0, d, 2 * d))) return r;             // P, L^{-1} on p along the way
   return trsm_upper(c, 0, d, d, 2 * d);                      // R = U^{-1} Y
 }
 

@@ -66,6 +66,7 @@ def test_action_edge_cases():
     q.propagate_action(gpu(Om), x)
     torch.cuda.synchronize()
     assert np.isnan(host(x)).all()
+    assert q.sync_status() == q.ENONFINITE and q.sync_status() == q.OK   # reported once, then cleared
     # a norm that would need more than 2^24 products per interval is refused
     big = wl.random_skew_hermitian_batch(1, d, 1e9, config_id=6)
     with pytest.raises(q.QcheffError):

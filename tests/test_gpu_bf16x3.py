@@ -70,6 +70,7 @@ def test_expm_bf16x3_chunks_alias_nonfinite():
     torch.cuda.synchronize()
     assert torch.equal(U1, U2) and torch.equal(U1, U3) and torch.equal(s1, s2)
     assert int(s4[2]) == -1 and torch.isnan(U4[2]).all()
+    assert q.sync_status() == q.ENONFINITE and q.sync_status() == q.OK   # reported once, then cleared
     keep = [0, 1, 3, 4, 5, 6]
     assert torch.equal(U4[keep], U1[keep])
 

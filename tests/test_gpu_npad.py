@@ -42,6 +42,7 @@ def _tol(dtype, H):
 @pytest.mark.parametrize("d,P", [(2, 1), (7, 3), (64, 1), (64, 32), (300, 17), (300, 150), (1030, 63), (1030, 515)])
 def test_eliminate_parity(d, P, dtype):
     say(f"npad eliminate d={d} P={P} {dtype}")
+    q.sync_status()   # flags another test may have left
     H = _herm(d, d + P)
     Hd = torch.from_numpy(H).to(DEV).to(dtype)
     seen = Hd.cpu().numpy().astype(np.complex128)          # what the GPU sees

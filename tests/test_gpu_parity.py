@@ -166,6 +166,7 @@ def test_expm_parity(d, dtype, mode):
         pytest.skip("the FP64 path takes no refinement")
     refine = kw["unitary_refine"]
     say(f"expm d={d} {dtype} {mode}")
+    q.sync_status()   # flags another test may have left
     norms = [0.0, 0.01, 1.0, 5.3, 5.4, 11.0, 11.5, 20.0, 170.0, 1500.0]   # s = 0 .. 9
     Om = wl.random_skew_hermitian_batch(len(norms), d, norms, config_id=300 + d)
     ref = oracle.expm_skew_hermitian(Om)
@@ -186,6 +187,7 @@ def test_expm_parity(d, dtype, mode):
         assert oracle.unitarity_error(Ug) <= 1e-6
     else:
         assert oracle.unitarity_error(Ug) <= 1e-3
+    assert q.sync_status() == q.OK   # no pivot of a Pade denominator was zero
 
 
 @pytest.mark.parametrize("mode", EXPM_MODES)
@@ -199,6 +201,7 @@ def test_expm_parity_large(d, dtype, mode):
         pytest.skip("the FP64 path takes no refinement")
     refine = kw["unitary_refine"]
     say(f"expm large d={d} {dtype} {mode}")
+    q.sync_status()   # flags another test may have left
     norms = [3.0, 60.0, 900.0]
     Om = wl.random_skew_hermitian_batch(len(norms), d, norms, config_id=400 + d)
     ref = oracle.expm_skew_hermitian(Om)
@@ -215,6 +218,7 @@ def test_expm_parity_large(d, dtype, mode):
         assert np.abs(Ug - ref).max() <= 1e-10
     elif refine:
         assert oracle.unitarity_error(Ug) <= 1e-6
+    assert q.sync_status() == q.OK
 
 
 @pytest.mark.parametrize("mode", EXPM_MODES)
