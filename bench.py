@@ -348,13 +348,12 @@ def sweep(a):
     from paper_2411_09982_amd.sweep import Sweep
     jobs = wl.sweep_instances(a.sweep_jobs)
     dtype = torch.complex64 if a.dtype == "c64" else torch.complex128
-    sw = Sweep(jobs, dtype)
     n_int = sum(j.M for j in jobs)
     counts = {}
     for j in jobs:
         counts[j.d] = counts.get(j.d, 0) + 1
 
-    def timed_runs(mode):
+    def timed_runs(sw, mode):
         for _ in range(max(a.warmup, 0)):
             sw.run()
         torch.cuda.synchronize()
@@ -372,9 +371,18 @@ def sweep(a):
                               ms_per_d={str(k): round(1000 * v / a.steps, 1) for k, v in sorted(per.items())})),
               flush=True)
 
-    timed_runs("eager")
-    sw.capture()
-    timed_runs("hip graph per group")
+    # each group's exponentials on their own, then every group's in one grouped
+    # call per pass (one persistent launch per product stage, the groups' solves
+    # side by side); eagerly and replayed from captured graphs.  The last line
+    # (grouped, replayed) is the figure of this mode.
+    for grouped in (False, True):
+        sw = Sweep(jobs, dtype, grouped=grouped)
+        name = "grouped" if grouped else "per group"
+        timed_runs(sw, f"eager, {name}")
+        sw.capture()
+        timed_runs(sw, f"hip graph, {name}")
+        del sw
+        torch.cuda.empty_cache()
 
 
 def action(a):

@@ -216,6 +216,44 @@ int qcheff_expm_batched(const void* omega, int64_t batch, int64_t d, int dtype, 
                         int32_t* s_out, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * qcheff_expm_grouped - qcheff_expm_batched over several batches of different
+ * dimension at once: the uneven parameter sweeps the paper runs by
+ * exponentiating all Magnus intervals of a job in parallel (Sec. 4.1, 4.3),
+ * taken across jobs of different Hilbert-space dimension.
+ *
+ *   G          number of groups, 1..8.
+ *   omega      host array of G device pointers: group g's [batch[g]][d[g]][d[g]]
+ *              generators in dtype (as qcheff_expm_batched's omega).
+ *   batch, d   host arrays of G sizes.
+ *   dtype      as for qcheff_expm_batched, flags included; every group uses it.
+ *   U          host array of G device pointers: group g's results (as
+ *              qcheff_expm_batched's U, in complex128 with QCHEFF_OUT_C128).
+ *              Groups must not overlap one another.
+ *   s_out      NULL, or a host array of G device pointers (each NULL or
+ *              [batch[g]] int32), as for qcheff_expm_batched.
+ *   ws         one workspace for all groups with d[g] > 32, at least the sum of
+ *              qcheff_workspace_bytes(QCHEFF_FN_EXPM, 1, d[g], 1, 1, dtype) over
+ *              them (groups with d[g] <= 32 run in the fused one-workgroup
+ *              kernel and need none).
+ *   The groups with d[g] > 32 advance in rounds: each round takes a slice of
+ *   every unfinished group, as large as the workspace allows with the same
+ *   number of rounds for all.  In a round every product stage (A^2, A^4, A^6,
+ *   the two Pade polynomials, the augmented system, each squaring, the two
+ *   products of the unitary refinement) is ONE persistent launch over all
+ *   groups' tiles (a work list of (group, item, tile) with each group's d and
+ *   each item's squaring count); the elementwise steps and the LU solve run per
+ *   group.  Split-BF16 products are launched per group.  Results equal those of
+ *   qcheff_expm_batched on each group up to the rounding of the tile shape the
+ *   round uses (the one tuned for its largest group).
+ *   Without a squaring bound the call waits on the stream once per round; with
+ *   QCHEFF_SQUARING_BOUND(n) it never waits (graph-capturable).
+ *   Returns QCHEFF_OK, QCHEFF_EINVAL, QCHEFF_EWORKSPACE, QCHEFF_EUNSUPPORTED
+ *   (graph capture without a bound), QCHEFF_EDEVICE.
+ */
+int qcheff_expm_grouped(int G, const void* const* omega, const int64_t* batch, const int64_t* d, int dtype,
+                        void* const* U, int32_t* const* s_out, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * qcheff_propagate - stroboscopic chain of the interval propagators (Sec. 4.1:
  * the evolution is exact at multiples of the interval; later intervals act
  * on the left).

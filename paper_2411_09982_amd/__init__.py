@@ -11,6 +11,7 @@ Functions (same names as the C entry points, minus the ``qcheff_`` prefix):
   magnus_coeffs(u, dt_sample, M, order)                 -> c1, c2
   magnus_generators(H0, Hk, c1, c2, dt_interval, order, out_dtype) -> omega
   expm_batched(omega)                                   -> U, s
+  expm_grouped([omega_g, ...])                          -> [U_g], [s_g]
   propagate(U, mode, x)                                 -> x (in place)
   sync_status(stream)                                   -> OK or ENONFINITE
 and ``evolve(...)``, the four calls in sequence (the paper's evolve()),
@@ -72,7 +73,9 @@ def lib() -> ctypes.CDLL:
     L.qcheff_npad_eliminate.argtypes = [vp, i64, i32, vp, i64, vp, ctypes.c_size_t, vp]
     L.qcheff_npad_largest.argtypes = [vp, i64, i32, vp, vp, vp, ctypes.c_size_t, vp]
     L.qcheff_propagate_action.argtypes = [vp, i64, i64, i32, vp, vp, dbl, vp, ctypes.c_size_t, vp]
-    for f in ("qcheff_magnus_coeffs", "qcheff_magnus_generators", "qcheff_expm_batched", "qcheff_propagate",
+    L.qcheff_expm_grouped.argtypes = [i32, vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
+    for f in ("qcheff_magnus_coeffs", "qcheff_magnus_generators", "qcheff_expm_batched", "qcheff_expm_grouped",
+              "qcheff_propagate",
               "qcheff_propagate_batched", "qcheff_propagate_action", "qcheff_propagate_state_noalloc",
               "qcheff_npad_eliminate", "qcheff_npad_largest"):
         getattr(L, f).restype = i32
@@ -228,6 +231,63 @@ def expm_batched(omega, U=None, s_out=None, ws=None, chunk: int | None = None, s
         | (0 if squaring_bound is None else squaring_bound_flag(squaring_bound)),
         _ptr(U), _ptr(s_out), _ptr(ws), ws.numel(), _stream(stream)))
     return U, s_out
+
+
+def expm_grouped_ws_bytes(dims_batches, dtype, chunk: int = 256) -> int:
+    """Workspace for qcheff_expm_grouped over (d, batch) groups: the rounds take
+    `chunk` items of the group of largest d at a time, and so many of every other
+    group (d > 32) that all groups finish in the same number of rounds."""
+    code = _DTYPES[dtype] if not isinstance(dtype, int) else dtype
+    big = [(d, b) for d, b in dims_batches if d > 32 and b > 0]
+    if not big:
+        return 0
+    dmax, bmax = max(big)
+    rounds = -(-bmax // max(1, chunk))
+    return sum(workspace_bytes(FN_EXPM, max(1, -(-b // rounds)), d, 1, 1, code) for d, b in big)
+
+
+def expm_grouped(omegas, Us=None, s_outs=None, ws=None, chunk: int = 256, stream=None,
+                 skew_hermitian: bool = False, squaring_bound: int | None = None, bf16x3: bool = False,
+                 unitary_refine: bool = False, out_c128: bool = False):
+    """exp of several batches of different dimension at once (qcheff_expm_grouped):
+    omegas is a list of [B_g][d_g][d_g] tensors of one dtype; the flags are those
+    of expm_batched.  Every product stage of a round is one launch over all
+    groups.  Returns (Us, ss), lists by group."""
+    G = len(omegas)
+    if not 1 <= G <= 8:
+        raise ValueError("expm_grouped takes 1 to 8 groups")
+    for o in omegas:
+        _dev(o, "omega")
+    dev = omegas[0].device
+    dt = _DTYPES[omegas[0].dtype]
+    if any(_DTYPES[o.dtype] != dt for o in omegas):
+        raise ValueError("every group must have the same dtype")
+    if bf16x3:
+        if dt != C64:
+            raise ValueError("bf16x3 products take complex64 matrices")
+        dt = C64_BF16X3
+    if Us is None:
+        Us = [torch.empty(o.shape, dtype=torch.complex128, device=dev) if out_c128 else torch.empty_like(o)
+              for o in omegas]
+    if s_outs is None:
+        s_outs = [torch.empty(o.shape[0], dtype=torch.int32, device=dev) for o in omegas]
+    if ws is None:
+        ws = _workspace(max(1, expm_grouped_ws_bytes([(o.shape[-1], o.shape[0]) for o in omegas], dt, chunk)), dev)
+    arr = ctypes.c_void_p * G
+    i64a = ctypes.c_int64 * G
+    om_p = arr(*[_ptr(o) for o in omegas])
+    u_p = arr(*[_ptr(u) for u in Us])
+    s_p = arr(*[_ptr(x) for x in s_outs])
+    batch = i64a(*[o.shape[0] for o in omegas])
+    dims = i64a(*[o.shape[-1] for o in omegas])
+    _check("qcheff_expm_grouped", lib().qcheff_expm_grouped(
+        G, ctypes.cast(om_p, ctypes.c_void_p), ctypes.cast(batch, ctypes.c_void_p), ctypes.cast(dims, ctypes.c_void_p),
+        dt | (SKEW_HERMITIAN if skew_hermitian else 0) | (UNITARY_REFINE if unitary_refine else 0)
+        | (OUT_C128 if out_c128 else 0)
+        | (0 if squaring_bound is None else squaring_bound_flag(squaring_bound)),
+        ctypes.cast(u_p, ctypes.c_void_p), ctypes.cast(s_p, ctypes.c_void_p), _ptr(ws),
+        0 if ws is None else ws.numel(), _stream(stream)))
+    return Us, s_outs
 
 
 def propagate(U, mode: int, x, traj=None, ws=None, stream=None):

@@ -605,110 +605,323 @@ int lu_solve(double2* aug, int* piv, int64_t d, int64_t nb, hipStream_t st) {
   return trsm_upper(c, 0, d, d, 2 * d);                      // R = U^{-1} Y
 }
 
-// U64: with the unitary refinement, an FP64 destination of the refined result
-// (U is then not written); null otherwise.
+// Side streams of the current device for the grouped exponential (created on
+// first use, default priority, kept for the life of the process) and the
+// events that fork work onto them and join it back.
+struct SideStreams {
+  static constexpr int kCount = 4;
+  hipStream_t stream[kCount];
+  hipEvent_t fork;
+  hipEvent_t join[kCount];
+  std::mutex mu;   // held from the fork to the join, so concurrent calls do not mix their events
+};
+
+int side_streams(SideStreams** out) {
+  static std::mutex mu;
+  static std::map<int, SideStreams*> by_dev;
+  int dev = 0;
+  QC_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = by_dev.find(dev);
+  if (it != by_dev.end()) {
+    *out = it->second;
+    return QCHEFF_OK;
+  }
+  auto* s = new SideStreams{};
+  for (int k = 0; k < SideStreams::kCount; ++k) {
+    QC_HIP(hipStreamCreateWithFlags(&s->stream[k], hipStreamNonBlocking));
+    QC_HIP(hipEventCreateWithFlags(&s->join[k], hipEventDisableTiming));
+  }
+  QC_HIP(hipEventCreateWithFlags(&s->fork, hipEventDisableTiming));
+  by_dev[dev] = s;
+  *out = s;
+  return QCHEFF_OK;
+}
+
+// One chunk of one dimension group in a round of the exponential: its input
+// and outputs (U, or U64 with the unitary refinement: an FP64 destination of
+// the refined result, U then null) and its carved workspace.
+template <typename T> struct ExpmChunk {
+  const typename Cx<T>::t* omega;
+  typename Cx<T>::t* U;
+  double2* U64;
+  int32_t* s_out;
+  int64_t nb, d;
+  ExpmWs<T> w;
+};
+
+// One product stage over the round's groups: a single group takes the
+// per-launch kernel (with the timing record), several the persistent grouped
+// kernel, whose grid is as many workgroups as the chip holds at once.
+template <typename T, int CFG>
+hipError_t launch_grouped_cfg(const GemmGroups<T>& gg, hipStream_t st) {
+  using G = GemmTile<T, CFG>;
+  auto kern = cgemm_grouped_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT, G::WPE>;
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(kern), G::NT, 0) !=
+            hipSuccess || n < 1)
+      n = 1;
+    per_cu = n;
+  }
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  // as many workgroups as the chip holds at once, a multiple of the XCD count
+  const int slots = kXcds * gg.per_xcd;
+  const int grid = std::max(kXcds, std::min(slots, per_cu * cus) / kXcds * kXcds);
+  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(G::NT), 0, st, gg);
+  return hipGetLastError();
+}
+
 template <typename T>
-int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t* s_out, int64_t nb, int64_t d,
-                   ExpmWs<T>& w, bool skew, int bound, bool bf16x3, bool refine, double2* U64, hipStream_t st) {
-  using C2 = typename Cx<T>::t;
+hipError_t launch_stage(GemmParams<T>* p, int G, hipStream_t st, const int64_t* active = nullptr) {
+  if (G == 1) return launch_cgemm<T>(p[0], st, active ? active[0] : -1);
+  if (p[0].cfg >= 2) {   // split-BF16 tiles (FP32 only): per group
+    for (int g = 0; g < G; ++g)
+      if (hipError_t e = launch_cgemm<T>(p[g], st, active ? active[g] : -1)) return e;
+    return hipSuccess;
+  }
+  GemmGroups<T> gg{};
+  gg.G = G;
+  double flops = 0.0, bytes = 0.0;
+  int64_t xslots[kXcds] = {};
+  for (int g = 0; g < G; ++g) {
+    gg.p[g] = p[g];
+    const bool empty = p[g].M <= 0 || p[g].N <= 0 || p[g].batch <= 0;
+    const int64_t tiles = empty ? 0
+                        : p[g].herm ? int64_t(p[g].tiles_m) * (p[g].tiles_m + 1) / 2
+                                    : int64_t(p[g].tiles_m) * p[g].tiles_n;
+    // the group's items split evenly over the XCDs
+    for (int x = 0; x < kXcds; ++x) {
+      const int64_t i0 = empty ? 0 : int64_t(p[g].batch) * x / kXcds;
+      const int64_t i1 = empty ? 0 : int64_t(p[g].batch) * (x + 1) / kXcds;
+      gg.item0[x][g] = int(i0);
+      gg.base[x][g] = int(xslots[x]);
+      xslots[x] += (i1 - i0) * tiles;
+    }
+    const double outs = p[g].herm ? double(p[g].M) * (p[g].M + 1) / 2 : double(p[g].M) * p[g].N;
+    const double act = double(active ? active[g] : p[g].batch);
+    flops += 8.0 * outs * double(p[g].K) * act;
+    bytes += (double(p[g].M) * p[g].K + double(p[g].K) * p[g].N + double(p[g].M) * p[g].N) *
+             sizeof(typename Cx<T>::t) * act;
+  }
+  int64_t most = 0;
+  for (int x = 0; x < kXcds; ++x) {
+    gg.base[x][G] = int(xslots[x]);
+    most = std::max(most, xslots[x]);
+  }
+  if (most == 0) return hipSuccess;
+  if (most * kXcds > 0x7fffffff) return hipErrorInvalidValue;
+  gg.per_xcd = int(most);
+  LaunchTimer tm;
+  tm.begin(st);
+  const hipError_t e = p[0].cfg == 1 ? launch_grouped_cfg<T, 1>(gg, st) : launch_grouped_cfg<T, 0>(gg, st);
+  if (tm.on) tm.end(st, sizeof(T) == 8 ? KERNEL_GEMM_F64 : KERNEL_GEMM_F32, flops, bytes);
+  return e;
+}
+
+// Product parameters for one chunk: out = A B (+ sum_i xc[i] X_i + gamma I).
+template <typename T>
+GemmParams<T> chunk_product(int cfg, int herm, typename Cx<T>::t* out, const typename Cx<T>::t* A,
+                            const typename Cx<T>::t* B, int64_t d, int64_t nb, int nx = 0,
+                            const typename Cx<T>::t* const* X = nullptr, const T* xc = nullptr, T gamma = T(0)) {
+  auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
+  p.herm = herm;
   const int64_t dd = d * d;
-  C2* Ubuf = U ? U : reinterpret_cast<C2*>(U64);   // the chunk's destination, as scratch of its own type
+  p.A = A; p.lda = d; p.sA = dd;
+  p.B = B; p.ldb = d; p.sB = dd;
+  p.C = out; p.ldc = d; p.sC = dd;
+  p.nx = nx;
+  for (int i = 0; i < nx; ++i) { p.X[i] = X[i]; p.xc[i] = xc[i]; }
+  p.gamma = gamma;
+  return p;
+}
+
+// The product tile of a round: the split-BF16 kernel, or the configuration the
+// tuner picked for the group with the most product work.
+template <typename T>
+int round_cfg(ExpmChunk<T>* ch, int G, bool bf16x3, hipStream_t st, int* cfg) {
+  if (bf16x3) {
+    *cfg = bf16x3_cfg();
+    return QCHEFF_OK;
+  }
+  int gmax = 0;
+  for (int g = 1; g < G; ++g)
+    if (double(ch[g].d) * ch[g].d * ch[g].d * ch[g].nb > double(ch[gmax].d) * ch[gmax].d * ch[gmax].d * ch[gmax].nb)
+      gmax = g;
+  // the tuner times on the scaled A of that group, into its W (free before the products)
+  return square_cfg<T>(ch[gmax].d, ch[gmax].nb, ch[gmax].w.X[0], ch[gmax].w.X[4], st, cfg);
+}
+
+// The exponentials of one round: a chunk of each of G dimension groups (G = 1
+// for qcheff_expm_batched).  The elementwise steps and the FP64 solve run per
+// group; every product stage (the Pade products, each squaring, the
+// refinement's two products) is one launch over all groups.  *cfg is the tile
+// of the products: chosen in the first round (cfg < 0 on entry: after the
+// scaling, by round_cfg) and kept for the later ones, so that an item's
+// rounding does not depend on which round it falls in.
+template <typename T>
+int expm_round(ExpmChunk<T>* ch, int G, int* cfg_io, bool bf16x3, bool skew, int bound, bool refine,
+               hipStream_t st) {
+  using C2 = typename Cx<T>::t;
   double b[14];
   pade_coefficients(13, b);
   const T c[14] = {T(b[0]), T(b[1]), T(b[2]), T(b[3]), T(b[4]), T(b[5]), T(b[6]),
                    T(b[7]), T(b[8]), T(b[9]), T(b[10]), T(b[11]), T(b[12]), T(b[13])};
-  // norms and smax start at zero (a fill kernel, not a memset)
-  hipLaunchKernelGGL(fill_u32_kernel, dim3(nblocks(nb * 2, 256)), dim3(256), 0, st,
-                     reinterpret_cast<uint32_t*>(w.norms), nb * 2, 0u);
-  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(w.smax), int64_t(1), 0u);
-  QC_HIP(hipGetLastError());
-  // Trace reduction in FP64 only: exp(Omega) = e^mu exp(Omega - mu I), mu = tr(Omega) / d.
-  // It centres the spectrum, which for a drift-dominated generator halves the
-  // norm (one squaring less) but moves the low-energy end, where such a system's
-  // states live, from the middle of the scaled spectrum (where the Pade
-  // approximant is most accurate) to its edge; in FP32 that costs more accuracy
-  // in those states than the saved squaring wins.
-  const double2* mu = nullptr;
-  if (sizeof(T) == 8) {
-    hipLaunchKernelGGL(trace_mean_kernel<C2>, dim3(unsigned(nb)), dim3(256), 0, st, omega, int(d), w.mu);
-    mu = w.mu;
+  const double2* mu[kMaxGroups] = {};
+  C2* Ubuf[kMaxGroups];
+  for (int g = 0; g < G; ++g) {
+    ExpmChunk<T>& k = ch[g];
+    ExpmWs<T>& w = k.w;
+    const int64_t d = k.d, nb = k.nb, dd = d * d;
+    Ubuf[g] = k.U ? k.U : reinterpret_cast<C2*>(k.U64);   // the chunk's destination, as scratch of its own type
+    // norms and smax start at zero (a fill kernel, not a memset)
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(nblocks(nb * 2, 256)), dim3(256), 0, st,
+                       reinterpret_cast<uint32_t*>(w.norms), nb * 2, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(w.smax), int64_t(1),
+                       0u);
+    QC_HIP(hipGetLastError());
+    // Trace reduction in FP64 only: exp(Omega) = e^mu exp(Omega - mu I), mu = tr(Omega) / d.
+    // It centres the spectrum, which for a drift-dominated generator halves the
+    // norm (one squaring less) but moves the low-energy end, where such a system's
+    // states live, from the middle of the scaled spectrum (where the Pade
+    // approximant is most accurate) to its edge; in FP32 that costs more accuracy
+    // in those states than the saved squaring wins.
+    if (sizeof(T) == 8) {
+      hipLaunchKernelGGL(trace_mean_kernel<C2>, dim3(unsigned(nb)), dim3(256), 0, st, k.omega, int(d), w.mu);
+      mu[g] = w.mu;
+    }
+    {
+      // partial column sums per 128-row tile go to the augmented-system buffer,
+      // which is not in use before the Pade products
+      const unsigned tiles = nblocks(d, kNormRows);
+      double* partial = reinterpret_cast<double*>(w.aug);
+      hipLaunchKernelGGL(norm1_partial_kernel<C2>, dim3(nblocks(d, 64), tiles, unsigned(nb)), dim3(256), 0, st,
+                         k.omega, int(d), mu[g], partial);
+      hipLaunchKernelGGL(norm1_finish_kernel, dim3(unsigned(nb)), dim3(256), 0, st, partial, int(d), int(tiles),
+                         w.norms);
+    }
+    QC_HIP(hipGetLastError());
+    const unsigned sblocks = unsigned(std::min<int64_t>(nblocks(dd, 256), 1024));
+    hipLaunchKernelGGL(scale_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, k.omega, w.X[0], int(d),
+                       mu[g], w.norms, kTheta13, bound, w.s_ws, k.s_out, w.smax);
+    QC_HIP(hipGetLastError());
   }
-  {
-    // partial column sums per 128-row tile go to the augmented-system buffer,
-    // which is not in use before the Pade products
-    const unsigned tiles = nblocks(d, kNormRows);
-    double* partial = reinterpret_cast<double*>(w.aug);
-    hipLaunchKernelGGL(norm1_partial_kernel<C2>, dim3(nblocks(d, 64), tiles, unsigned(nb)), dim3(256), 0, st, omega,
-                       int(d), mu, partial);
-    hipLaunchKernelGGL(norm1_finish_kernel, dim3(unsigned(nb)), dim3(256), 0, st, partial, int(d), int(tiles),
-                       w.norms);
-  }
-  QC_HIP(hipGetLastError());
-  const unsigned sblocks = unsigned(std::min<int64_t>(nblocks(dd, 256), 1024));
-  hipLaunchKernelGGL(scale_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, omega, w.X[0], int(d), mu,
-                     w.norms, kTheta13, bound, w.s_ws, s_out, w.smax);
-  QC_HIP(hipGetLastError());
-  C2 *A = w.X[0], *A2 = w.X[1], *A4 = w.X[2], *A6 = w.X[3], *W = w.X[4], *V = w.X[5];
-  int r, cfg = bf16x3_cfg();   // a split-BF16 tile, or the tuned FP32 / FP64 one
-  if (!bf16x3 && (r = square_cfg<T>(d, nb, A, W, st, &cfg))) return r;
+  if (*cfg_io < 0)   // a split-BF16 tile, or the tuned FP32 / FP64 one
+    if (int r = round_cfg<T>(ch, G, bf16x3, st, cfg_io)) return r;
+  const int cfg = *cfg_io;
   // For skew-Hermitian A every even power, W and V are Hermitian (and A W
   // skew-Hermitian): only half of each of those products is formed.
   const int h = skew ? 1 : 0;
-  if ((r = gemm_sq<T>(cfg, h, A2, A, A, d, nb, st))) return r;
-  if ((r = gemm_sq<T>(cfg, h, A4, A2, A2, d, nb, st))) return r;
-  if ((r = gemm_sq<T>(cfg, h, A6, A4, A2, d, nb, st))) return r;
+  GemmParams<T> p[kMaxGroups];
+  for (int g = 0; g < G; ++g) { auto& w = ch[g].w; p[g] = chunk_product<T>(cfg, h, w.X[1], w.X[0], w.X[0], ch[g].d, ch[g].nb); }
+  QC_HIP(launch_stage<T>(p, G, st));   // A^2
+  for (int g = 0; g < G; ++g) { auto& w = ch[g].w; p[g] = chunk_product<T>(cfg, h, w.X[2], w.X[1], w.X[1], ch[g].d, ch[g].nb); }
+  QC_HIP(launch_stage<T>(p, G, st));   // A^4
+  for (int g = 0; g < G; ++g) { auto& w = ch[g].w; p[g] = chunk_product<T>(cfg, h, w.X[3], w.X[2], w.X[1], ch[g].d, ch[g].nb); }
+  QC_HIP(launch_stage<T>(p, G, st));   // A^6
   // W = A6 (b13 A6 + b11 A4 + b9 A2) + b7 A6 + b5 A4 + b3 A2 + b1 I   (U = A W)
   // V = A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I
   // The inner combinations go to buffers that are free at this point: the
   // chunk's U (its input was consumed by the scaling; with an FP64 destination,
-  // the first half of that) and W.  V is formed first
-  // (from W), then W (from U) overwrites its own buffer.  The outer terms are
-  // added by the epilogues.
-  hipLaunchKernelGGL((pade_inner_kernel<C2, T>), dim3(unsigned(std::min<int64_t>(nblocks(nb * dd, 256), 8192))),
-                     dim3(256), 0, st, A6, A4, A2, nb * dd, c[13], c[11], c[9], c[12], c[10], c[8], Ubuf, W);
-  QC_HIP(hipGetLastError());
-  const C2* Xs[3] = {A6, A4, A2};
-  const T xv[3] = {c[6], c[4], c[2]};
-  if ((r = gemm_sq<T>(cfg, h, V, A6, W, d, nb, st, 3, Xs, xv, c[0]))) return r;
-  const T xw[3] = {c[7], c[5], c[3]};
-  if ((r = gemm_sq<T>(cfg, h, W, A6, Ubuf, d, nb, st, 3, Xs, xw, c[1]))) return r;
-  // [q | p] = [V - A W | V + A W] in FP64
-  {
-    auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
-    p.A = A; p.lda = d; p.sA = dd;
-    p.B = W; p.ldb = d; p.sB = dd;
-    p.C = V; p.ldc = d; p.sC = dd;
-    p.X[0] = V;
-    p.epi = EPI_AUG;
-    p.herm = -h;
-    p.aug = w.aug; p.ld_aug = 2 * d; p.s_aug = 2 * dd; p.aug_off = d;
-    QC_HIP((launch_cgemm<T>(p, st)));
+  // the first half of that) and W.  V is formed first (from W), then W (from U)
+  // overwrites its own buffer.  The outer terms are added by the epilogues.
+  for (int g = 0; g < G; ++g) {
+    auto& w = ch[g].w;
+    const int64_t n = ch[g].nb * ch[g].d * ch[g].d;
+    hipLaunchKernelGGL((pade_inner_kernel<C2, T>), dim3(unsigned(std::min<int64_t>(nblocks(n, 256), 8192))),
+                       dim3(256), 0, st, w.X[3], w.X[2], w.X[1], n, c[13], c[11], c[9], c[12], c[10], c[8], Ubuf[g],
+                       w.X[4]);
   }
-  if ((r = lu_solve(w.aug, w.piv, d, nb, st))) return r;
+  QC_HIP(hipGetLastError());
+  const T xv[3] = {c[6], c[4], c[2]};
+  const T xw[3] = {c[7], c[5], c[3]};
+  for (int g = 0; g < G; ++g) {
+    auto& w = ch[g].w;
+    const C2* Xs[3] = {w.X[3], w.X[2], w.X[1]};
+    p[g] = chunk_product<T>(cfg, h, w.X[5], w.X[3], w.X[4], ch[g].d, ch[g].nb, 3, Xs, xv, c[0]);
+  }
+  QC_HIP(launch_stage<T>(p, G, st));   // V
+  for (int g = 0; g < G; ++g) {
+    auto& w = ch[g].w;
+    const C2* Xs[3] = {w.X[3], w.X[2], w.X[1]};
+    p[g] = chunk_product<T>(cfg, h, w.X[4], w.X[3], Ubuf[g], ch[g].d, ch[g].nb, 3, Xs, xw, c[1]);
+  }
+  QC_HIP(launch_stage<T>(p, G, st));   // W
+  // [q | p] = [V - A W | V + A W] in FP64
+  for (int g = 0; g < G; ++g) {
+    auto& w = ch[g].w;
+    const int64_t d = ch[g].d, dd = d * d;
+    p[g] = chunk_product<T>(cfg, -h, w.X[5], w.X[0], w.X[4], d, ch[g].nb);
+    p[g].X[0] = w.X[5];
+    p[g].epi = EPI_AUG;
+    p[g].aug = w.aug; p[g].ld_aug = 2 * d; p[g].s_aug = 2 * dd; p[g].aug_off = d;
+  }
+  QC_HIP(launch_stage<T>(p, G, st));
   // The squarings ping-pong between the chunk's U and A; with the unitary
   // refinement they run in W and V instead (the refinement reads the last one
   // and writes U).  W and V are free once the augmented system is formed.
-  C2* sq0 = refine ? W : U;
-  C2* sq1 = refine ? V : A;
-  hipLaunchKernelGGL(place_result_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, w.aug, int(d), w.s_ws,
-                     sq0, sq1);
-  QC_HIP(hipGetLastError());
+  C2* sq0[kMaxGroups];
+  C2* sq1[kMaxGroups];
+  // The solves of several groups run side by side on the library's side streams
+  // (forked from and joined back into `st` through events, which graph capture
+  // records as dependencies): a solve is a chain of many small dependent
+  // launches, and the groups' chains fill each other's idle time.
+  SideStreams* side = nullptr;
+  std::unique_lock<std::mutex> side_lock;
+  if (G > 1) {
+    if (int r = side_streams(&side)) return r;
+    side_lock = std::unique_lock<std::mutex>(side->mu);
+    QC_HIP(hipEventRecord(side->fork, st));
+  }
+  for (int g = 0; g < G; ++g) {
+    auto& w = ch[g].w;
+    const int64_t d = ch[g].d, dd = d * d;
+    hipStream_t sg = st;
+    if (side) {
+      sg = side->stream[g % SideStreams::kCount];
+      QC_HIP(hipStreamWaitEvent(sg, side->fork, 0));
+    }
+    if (int r = lu_solve(w.aug, w.piv, d, ch[g].nb, sg)) return r;
+    sq0[g] = refine ? w.X[4] : ch[g].U;
+    sq1[g] = refine ? w.X[5] : w.X[0];
+    const unsigned sblocks = unsigned(std::min<int64_t>(nblocks(dd, 256), 1024));
+    hipLaunchKernelGGL(place_result_kernel<C2>, dim3(sblocks, unsigned(ch[g].nb)), dim3(256), 0, sg, w.aug, int(d),
+                       w.s_ws, sq0[g], sq1[g]);
+    QC_HIP(hipGetLastError());
+  }
+  if (side) {
+    for (int k = 0; k < std::min(G, SideStreams::kCount); ++k) {
+      QC_HIP(hipEventRecord(side->join[k], side->stream[k]));
+      QC_HIP(hipStreamWaitEvent(st, side->join[k], 0));
+    }
+    side_lock.unlock();
+  }
   // Without a bound the host reads the squaring counts back to size the
   // squaring launches; with one it enqueues exactly `bound` passes (an item
   // leaves the passes once its own count is done) and never waits.
-  std::vector<int> s_host(size_t(nb), bound);
-  if (bound < 0) {
-    QC_HIP(hipMemcpyAsync(s_host.data(), w.s_ws, size_t(nb) * sizeof(int), hipMemcpyDeviceToHost, st));
-    QC_HIP(hipStreamSynchronize(st));
+  std::vector<int> s_host[kMaxGroups];
+  for (int g = 0; g < G; ++g) {
+    s_host[g].assign(size_t(ch[g].nb), bound);
+    if (bound < 0)
+      QC_HIP(hipMemcpyAsync(s_host[g].data(), ch[g].w.s_ws, size_t(ch[g].nb) * sizeof(int), hipMemcpyDeviceToHost, st));
   }
-  const int smax = std::max(0, *std::max_element(s_host.begin(), s_host.end()));
+  if (bound < 0) QC_HIP(hipStreamSynchronize(st));
+  int smax = 0;
+  for (int g = 0; g < G; ++g) smax = std::max(smax, *std::max_element(s_host[g].begin(), s_host[g].end()));
   for (int step = 0; step < smax; ++step) {
-    const int64_t active = std::count_if(s_host.begin(), s_host.end(), [step](int s) { return s > step; });
-    auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
-    p.lda = d; p.ldb = d; p.ldc = d;
-    p.sA = dd; p.sB = dd; p.sC = dd;
-    p.sq = 1; p.sq_s = w.s_ws; p.sq_step = step; p.sq_p0 = sq0; p.sq_p1 = sq1;
-    QC_HIP((launch_cgemm<T>(p, st, active)));
+    int64_t active[kMaxGroups];
+    for (int g = 0; g < G; ++g) {
+      const int64_t d = ch[g].d, dd = d * d;
+      active[g] = std::count_if(s_host[g].begin(), s_host[g].end(), [step](int s) { return s > step; });
+      p[g] = gemm_params<T>(int(d), int(d), int(d), int(ch[g].nb), cfg);
+      p[g].lda = d; p[g].ldb = d; p[g].ldc = d;
+      p[g].sA = dd; p[g].sB = dd; p[g].sC = dd;
+      p[g].sq = 1; p[g].sq_s = ch[g].w.s_ws; p[g].sq_step = step; p[g].sq_p0 = sq0[g]; p[g].sq_p1 = sq1[g];
+    }
+    QC_HIP(launch_stage<T>(p, G, st, active));
   }
   if constexpr (sizeof(T) == 4) {
     if (refine) {
@@ -716,37 +929,45 @@ int expm_chunk_run(const typename Cx<T>::t* omega, typename Cx<T>::t* U, int32_t
       // from the FP32 result R (in sq0), then U = R + (1/2) E R.  U64 and
       // U^dag sit side by side in the augmented-system buffer; E64 takes the
       // space of A and A^2 (one complex128 matrix per item), E32 that of A^4.
-      hipLaunchKernelGGL(refine_prep_kernel, dim3(nblocks(d, 32), nblocks(d, 32), unsigned(nb)), dim3(256), 0, st,
-                         reinterpret_cast<const float2*>(sq0), int(d), w.aug);
-      QC_HIP(hipGetLastError());
-      double2* E64 = reinterpret_cast<double2*>(w.X[0]);
-      {
-        auto p = gemm_params<double>(int(d), int(d), int(d), int(nb), rule_cfg(d));
-        p.A = w.aug; p.lda = d; p.sA = 2 * dd;
-        p.B = w.aug + dd; p.ldb = d; p.sB = 2 * dd;
-        p.C = E64; p.ldc = d; p.sC = dd;
-        p.alpha = -1.0; p.gamma = 1.0; p.herm = 1;
-        QC_HIP((launch_cgemm<double>(p, st)));
+      GemmParams<double> pd[kMaxGroups];
+      int64_t dmax = 0;
+      for (int g = 0; g < G; ++g) dmax = std::max(dmax, ch[g].d);
+      for (int g = 0; g < G; ++g) {
+        auto& w = ch[g].w;
+        const int64_t d = ch[g].d, dd = d * d;
+        hipLaunchKernelGGL(refine_prep_kernel, dim3(nblocks(d, 32), nblocks(d, 32), unsigned(ch[g].nb)), dim3(256), 0,
+                           st, reinterpret_cast<const float2*>(sq0[g]), int(d), w.aug);
+        pd[g] = gemm_params<double>(int(d), int(d), int(d), int(ch[g].nb), rule_cfg(dmax));
+        pd[g].A = w.aug; pd[g].lda = d; pd[g].sA = 2 * dd;
+        pd[g].B = w.aug + dd; pd[g].ldb = d; pd[g].sB = 2 * dd;
+        pd[g].C = reinterpret_cast<double2*>(w.X[0]); pd[g].ldc = d; pd[g].sC = dd;
+        pd[g].alpha = -1.0; pd[g].gamma = 1.0; pd[g].herm = 1;
       }
-      float2* E32 = reinterpret_cast<float2*>(w.X[2]);
-      hipLaunchKernelGGL(to_c64_kernel, dim3(unsigned(std::min<int64_t>(nblocks(nb * dd, 256), 8192))), dim3(256), 0,
-                         st, E64, E32, nb * dd);
       QC_HIP(hipGetLastError());
-      auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
-      p.A = E32; p.lda = d; p.sA = dd;
-      p.B = sq0; p.ldb = d; p.sB = dd;
-      p.C = U64 ? sq0 : U; p.ldc = d; p.sC = dd;
-      p.alpha = T(0.5);
-      p.nx = 1; p.X[0] = sq0; p.xc[0] = T(1);
-      if (U64) {   // R + (1/2) E R formed and kept in FP64: no final rounding to FP32
-        p.epi = EPI_OUT64;
-        p.aug = U64; p.ld_aug = d; p.s_aug = dd;
+      QC_HIP(launch_stage<double>(pd, G, st));
+      for (int g = 0; g < G; ++g) {
+        auto& w = ch[g].w;
+        const int64_t d = ch[g].d, dd = d * d;
+        const int64_t n = ch[g].nb * dd;
+        hipLaunchKernelGGL(to_c64_kernel, dim3(unsigned(std::min<int64_t>(nblocks(n, 256), 8192))), dim3(256), 0, st,
+                           reinterpret_cast<double2*>(w.X[0]), reinterpret_cast<float2*>(w.X[2]), n);
+        p[g] = chunk_product<T>(cfg, 0, ch[g].U64 ? sq0[g] : ch[g].U, w.X[2], sq0[g], d, ch[g].nb);
+        p[g].alpha = T(0.5);
+        p[g].nx = 1; p[g].X[0] = sq0[g]; p[g].xc[0] = T(1);
+        if (ch[g].U64) {   // R + (1/2) E R formed and kept in FP64: no final rounding to FP32
+          p[g].epi = EPI_OUT64;
+          p[g].aug = ch[g].U64; p[g].ld_aug = d; p[g].s_aug = dd;
+        }
       }
-      QC_HIP((launch_cgemm<T>(p, st)));
+      QC_HIP(hipGetLastError());
+      QC_HIP(launch_stage<T>(p, G, st));
     }
   }
-  if (mu) {
-    hipLaunchKernelGGL(phase_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, U, dd, mu);
+  for (int g = 0; g < G; ++g) {
+    if (!mu[g]) continue;
+    const int64_t dd = ch[g].d * ch[g].d;
+    const unsigned sblocks = unsigned(std::min<int64_t>(nblocks(dd, 256), 1024));
+    hipLaunchKernelGGL(phase_kernel<C2>, dim3(sblocks, unsigned(ch[g].nb)), dim3(256), 0, st, ch[g].U, dd, mu[g]);
     QC_HIP(hipGetLastError());
   }
   return QCHEFF_OK;
@@ -768,15 +989,100 @@ int run_expm(const void* omega, int64_t batch, int64_t d, void* U, int32_t* s_ou
   // a chunk's items ride on the grid's y (or z) dimension
   const int64_t chunk = std::min<int64_t>(expm_chunk(ws_bytes, batch, d, dtype), 65535);
   const int64_t dd = d * d;
-  ExpmWs<T> w;
-  if (!carve_expm<T>(ws, ws_bytes, chunk, d, w)) return fail(QCHEFF_EWORKSPACE, "workspace carving failed");
+  ExpmChunk<T> ch{};
+  if (!carve_expm<T>(ws, ws_bytes, chunk, d, ch.w)) return fail(QCHEFF_EWORKSPACE, "workspace carving failed");
+  int cfg = -1;
   for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
-    const int64_t nb = std::min(chunk, batch - b0);
-    int r = expm_chunk_run<T>(static_cast<const C2*>(omega) + b0 * dd,
-                              out64 ? nullptr : static_cast<C2*>(U) + b0 * dd, s_out ? s_out + b0 : nullptr, nb, d,
-                              w, skew, bound, bf16x3, refine, out64 ? static_cast<double2*>(U) + b0 * dd : nullptr,
-                              st);
-    if (r) return r;
+    ch.nb = std::min(chunk, batch - b0);
+    ch.d = d;
+    ch.omega = static_cast<const C2*>(omega) + b0 * dd;
+    ch.U = out64 ? nullptr : static_cast<C2*>(U) + b0 * dd;
+    ch.U64 = out64 ? static_cast<double2*>(U) + b0 * dd : nullptr;
+    ch.s_out = s_out ? s_out + b0 : nullptr;
+    if (int r = expm_round<T>(&ch, 1, &cfg, bf16x3, skew, bound, refine, st)) return r;
+  }
+  return QCHEFF_OK;
+}
+
+// qcheff_expm_grouped: the groups with d <= 32 through the fused kernel, the
+// others in rounds of expm_round.  The number of rounds R is the smallest for
+// which every group's slice (its batch / R, rounded up) fits the workspace
+// together with the others'.
+template <typename T>
+int run_expm_grouped(int G, const void* const* omega, const int64_t* batch, const int64_t* d, void* const* U,
+                     int32_t* const* s_out, void* ws, size_t ws_bytes, int dtype, bool skew, int bound, bool bf16x3,
+                     bool refine, bool out64, hipStream_t st) {
+  using C2 = typename Cx<T>::t;
+  int big[kMaxGroups];
+  int nbig = 0;
+  int64_t most = 0;
+  for (int g = 0; g < G; ++g) {
+    if (batch[g] == 0) continue;
+    if (d[g] <= kSmallD) {
+      if (int r = run_expm<T>(omega[g], batch[g], d[g], U[g], s_out ? s_out[g] : nullptr, nullptr, 0, dtype, skew,
+                              bound, bf16x3, refine, out64, st))
+        return r;
+    } else {
+      big[nbig++] = g;
+      most = std::max(most, batch[g]);
+    }
+  }
+  if (nbig == 0) return QCHEFF_OK;
+  auto slice = [&](int g, int64_t R) { return std::min<int64_t>((batch[g] + R - 1) / R, 65535); };
+  auto need = [&](int64_t R) {
+    size_t n = 0;
+    for (int k = 0; k < nbig; ++k) n += expm_ws_bytes(slice(big[k], R), d[big[k]], dtype);
+    return n;
+  };
+  int64_t R = 1;
+  while (R < most && need(R) > ws_bytes) {
+    // shrink geometrically, then settle on the smallest R that fits
+    const int64_t next = std::min(most, R * 2);
+    if (need(next) > ws_bytes) { R = next; continue; }
+    int64_t lo = R + 1, hi = next;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) / 2;
+      if (need(mid) <= ws_bytes) hi = mid; else lo = mid + 1;
+    }
+    R = lo;
+    break;
+  }
+  if (need(R) > ws_bytes) return fail(QCHEFF_EWORKSPACE, "qcheff_expm_grouped: workspace carving failed");
+  ExpmWs<T> w[kMaxGroups];
+  int64_t chunk[kMaxGroups];
+  {
+    char* at = static_cast<char*>(ws);
+    size_t left = ws_bytes;
+    for (int k = 0; k < nbig; ++k) {
+      const int g = big[k];
+      chunk[k] = slice(g, R);
+      const size_t n = expm_ws_bytes(chunk[k], d[g], dtype);
+      if (n > left || !carve_expm<T>(at, n, chunk[k], d[g], w[k]))
+        return fail(QCHEFF_EWORKSPACE, "qcheff_expm_grouped: workspace carving failed");
+      at += n;
+      left -= n;
+    }
+  }
+  int cfg = -1;   // every group has items in the first round, which picks the tile
+  for (int64_t r = 0;; ++r) {
+    ExpmChunk<T> ch[kMaxGroups];
+    int n = 0;
+    for (int k = 0; k < nbig; ++k) {
+      const int g = big[k];
+      const int64_t b0 = r * chunk[k];
+      if (b0 >= batch[g]) continue;
+      const int64_t dd = d[g] * d[g];
+      ExpmChunk<T>& c = ch[n++];
+      c.nb = std::min(chunk[k], batch[g] - b0);
+      c.d = d[g];
+      c.omega = static_cast<const C2*>(omega[g]) + b0 * dd;
+      c.U = out64 ? nullptr : static_cast<C2*>(U[g]) + b0 * dd;
+      c.U64 = out64 ? static_cast<double2*>(U[g]) + b0 * dd : nullptr;
+      c.s_out = (s_out && s_out[g]) ? s_out[g] + b0 : nullptr;
+      c.w = w[k];
+    }
+    if (n == 0) break;
+    if (int e = expm_round<T>(ch, n, &cfg, bf16x3, skew, bound, refine, st)) return e;
   }
   return QCHEFF_OK;
 }
@@ -1106,6 +1412,37 @@ int qcheff_expm_batched(const void* omega, int64_t batch, int64_t d, int dtype, 
              ? run_expm<double>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, skew, bound, false, false, false, st)
              : run_expm<float>(omega, batch, d, U, s_out, ws, ws_bytes, dtype, skew, bound, bf16x3, refine, out64,
                                st);
+}
+
+int qcheff_expm_grouped(int G, const void* const* omega, const int64_t* batch, const int64_t* d, int dtype,
+                        void* const* U, int32_t* const* s_out, void* ws, size_t ws_bytes, void* stream) {
+  const bool skew = (dtype & QCHEFF_SKEW_HERMITIAN) != 0;
+  const bool refine = (dtype & QCHEFF_UNITARY_REFINE) != 0;
+  const bool out64 = (dtype & QCHEFF_OUT_C128) != 0;
+  const int bound = ((dtype >> 16) & 0xff) - 1;   // -1: none
+  dtype &= ~(QCHEFF_SKEW_HERMITIAN | QCHEFF_UNITARY_REFINE | QCHEFF_OUT_C128 | (0xff << 16));
+  const bool bf16x3 = dtype == QCHEFF_C64_BF16X3;
+  if (bf16x3) dtype = QCHEFF_C64;
+  if (refine && (dtype != QCHEFF_C64 || !skew))
+    return fail(QCHEFF_EINVAL, "QCHEFF_UNITARY_REFINE takes QCHEFF_C64 (or _BF16X3) with QCHEFF_SKEW_HERMITIAN");
+  if (out64 && !refine) return fail(QCHEFF_EINVAL, "QCHEFF_OUT_C128 needs QCHEFF_UNITARY_REFINE");
+  Check c = check_expm_grouped(G, omega, batch, d, dtype, U, ws, ws_bytes, out64 ? QCHEFF_C128 : dtype);
+  if (c.status) return fail(c);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  bool any_big = false;
+  for (int g = 0; g < G; ++g) any_big = any_big || (batch[g] > 0 && d[g] > kSmallD);
+  if (bound < 0 && any_big) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    QC_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+      return fail(Check::fail(QCHEFF_EUNSUPPORTED,
+                              "qcheff_expm_grouped: a stream under graph capture needs QCHEFF_SQUARING_BOUND(n)"));
+  }
+  return dtype == QCHEFF_C128
+             ? run_expm_grouped<double>(G, omega, batch, d, U, s_out, ws, ws_bytes, dtype, skew, bound, false, false,
+                                        false, st)
+             : run_expm_grouped<float>(G, omega, batch, d, U, s_out, ws, ws_bytes, dtype, skew, bound, bf16x3, refine,
+                                       out64, st);
 }
 
 int qcheff_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, void* x, void* traj, void* ws,

@@ -62,15 +62,14 @@ template <typename T> struct TileJob {
   C2* C;
 };
 
-// Fills `j` for this workgroup; false when it has nothing to do (past the last
-// item, or an item whose squarings are done).  With a (skew-)Hermitian result
-// only the tiles on and above the diagonal run; each element above the diagonal
-// is also written, conjugated, below it.
+// Fills `j` for logical tile `bid` (item-major, then tile); false when it has
+// nothing to do (past the last item, or an item whose squarings are done).
+// With a (skew-)Hermitian result only the tiles on and above the diagonal run;
+// each element above the diagonal is also written, conjugated, below it.
 template <typename T, int BM, int BN>
-__device__ __forceinline__ bool tile_job(const GemmParams<T>& p, TileJob<T>& j) {
+__device__ __forceinline__ bool tile_job(const GemmParams<T>& p, int bid, TileJob<T>& j) {
   using C2 = typename Cx<T>::t;
   const int tiles = p.herm ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int b = bid / tiles;
   if (b >= p.batch) return false;
   const int t = bid - b * tiles;
@@ -185,9 +184,12 @@ __device__ __forceinline__ void tile_epilogue(const GemmParams<T>& p, const Tile
   }
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int WAVES_PER_EU>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU))) void cgemm_kernel(
-    GemmParams<T> p) {
+// One tile of C through the K loop and the epilogue (the LDS buffers belong to
+// the calling kernel).
+template <typename T, int BM, int BN, int BK, int WM, int WN, int NT>
+__device__ __forceinline__ void cgemm_tile(const GemmParams<T>& p, const TileJob<T>& jb,
+                                           typename Cx<T>::t (&As)[2][BK][BM + 1],
+                                           typename Cx<T>::t (&Bs)[2][BK][BN]) {
   using C2 = typename Cx<T>::t;
   using Acc = typename Cx<T>::acc;
   constexpr int WAVES_N = BN / WN;
@@ -196,11 +198,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
   constexpr int LA = BM * BK / NT, LB = BK * BN / NT;
   static_assert(LA * NT == BM * BK && LB * NT == BK * BN, "tile loads must divide evenly");
 
-  __shared__ C2 As[2][BK][BM + 1];
-  __shared__ C2 Bs[2][BK][BN];
-
-  TileJob<T> jb;
-  if (!tile_job<T, BM, BN>(p, jb)) return;
   const int row0 = jb.row0, col0 = jb.col0;
   const C2* A = jb.A;
   const C2* B = jb.B;
@@ -329,6 +326,56 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
   }
 
   tile_epilogue<T, TM, TN>(p, jb, accr, acci, wm, wn, lane);
+}
+
+template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int WAVES_PER_EU>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU))) void cgemm_kernel(
+    GemmParams<T> p) {
+  using C2 = typename Cx<T>::t;
+  __shared__ C2 As[2][BK][BM + 1];
+  __shared__ C2 Bs[2][BK][BN];
+  TileJob<T> jb;
+  if (!tile_job<T, BM, BN>(p, xcd_remap(blockIdx.x, gridDim.x), jb)) return;
+  cgemm_tile<T, BM, BN, BK, WM, WN, NT>(p, jb, As, Bs);
+}
+
+// Grouped products: up to kMaxGroups batches of different shapes (the
+// dimension groups of an uneven sweep) in one persistent launch.  The hardware
+// hands workgroups to the eight XCDs in turn, and the grid is a multiple of
+// eight, so tile slot t runs on XCD t % 8.  Every group's items are split evenly
+// over the XCDs (XCD x takes items [item0[x][g], item0[x][g] + count) of group
+// g), so each XCD gets the same mix of cheap and costly tiles, and an item's
+// tiles share one L2.  XCD x walks its slots j = t / 8: group g holds slots
+// [base[x][g], base[x][g + 1]), item-major.
+constexpr int kMaxGroups = 8;
+constexpr int kXcds = 8;
+template <typename T> struct GemmGroups {
+  int G;
+  int per_xcd;                        // slots of the busiest XCD
+  int base[kXcds][kMaxGroups + 1];
+  int item0[kXcds][kMaxGroups];
+  GemmParams<T> p[kMaxGroups];
+};
+
+template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int WAVES_PER_EU>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU))) void cgemm_grouped_kernel(
+    GemmGroups<T> gg) {
+  using C2 = typename Cx<T>::t;
+  __shared__ C2 As[2][BK][BM + 1];
+  __shared__ C2 Bs[2][BK][BN];
+  for (int t = blockIdx.x; t < kXcds * gg.per_xcd; t += gridDim.x) {
+    const int x = t % kXcds, j = t / kXcds;
+    if (j >= gg.base[x][gg.G]) continue;   // this XCD has fewer slots
+    int g = 0;
+    while (g + 1 < gg.G && j >= gg.base[x][g + 1]) ++g;
+    const GemmParams<T>& p = gg.p[g];
+    const int tiles = p.herm ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
+    const int local = j - gg.base[x][g];
+    TileJob<T> jb;
+    if (!tile_job<T, BM, BN>(p, (gg.item0[x][g] + local / tiles) * tiles + local % tiles, jb)) continue;
+    cgemm_tile<T, BM, BN, BK, WM, WN, NT>(p, jb, As, Bs);
+    __syncthreads();   // the next tile refills the LDS buffers
+  }
 }
 
 // Tile configurations per precision: cfg 0 is the large tile, cfg 1 the small

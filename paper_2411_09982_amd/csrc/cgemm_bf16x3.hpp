@@ -118,7 +118,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void cg
   __shared__ __attribute__((aligned(16))) C2 Bs[2][BK][BN];
 
   TileJob<float> jb;
-  if (!tile_job<float, BM, BN>(p, jb)) return;
+  if (!tile_job<float, BM, BN>(p, xcd_remap(blockIdx.x, gridDim.x), jb)) return;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void cg
   __shared__ u32x4 Bs[6][BN * (BK / 8)];
 
   TileJob<float> jb;
-  if (!tile_job<float, BM, BN>(p, jb)) return;
+  if (!tile_job<float, BM, BN>(p, xcd_remap(blockIdx.x, gridDim.x), jb)) return;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;

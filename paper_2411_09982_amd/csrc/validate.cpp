@@ -117,6 +117,23 @@ Check check_expm(const void* omega, int64_t batch, int64_t d, int dtype, const v
   return Check::ok();
 }
 
+Check check_expm_grouped(int G, const void* const* omega, const int64_t* batch, const int64_t* d, int dtype,
+                         void* const* U, const void* ws, size_t ws_bytes, int out_dtype) {
+  if (G < 1 || G > 8) return Check::fail(QCHEFF_EINVAL, "G must be in [1, 8]");
+  if (!omega || !batch || !d || !U) return Check::fail(QCHEFF_EINVAL, "omega, batch, d and U must not be NULL");
+  size_t need = 0;
+  for (int g = 0; g < G; ++g) {
+    // the per-group checks of qcheff_expm_batched, the workspace aside
+    Check c = check_expm(omega[g], batch[g], d[g], dtype, U[g], ws ? ws : omega, ~size_t(0), out_dtype);
+    if (c.status) return Check::fail(c.status, "group " + std::to_string(g) + ": " + c.message);
+    if (batch[g] > 0 && d[g] > 32) need += expm_ws_bytes(1, d[g], dtype);
+  }
+  if (need > 0 && !ws) return Check::fail(QCHEFF_EWORKSPACE, "workspace must not be NULL");
+  if (need > ws_bytes)
+    return Check::fail(QCHEFF_EWORKSPACE, "workspace smaller than one item of every group with d > 32 needs");
+  return Check::ok();
+}
+
 size_t propagate_ws_bytes(int64_t M, int64_t d, int dtype, int mode) {
   if (M < 0 || d < 1 || elem_bytes(dtype) == 0) return 0;
   if (mode == QCHEFF_STATE) return align256(size_t(2 * d) * 16);

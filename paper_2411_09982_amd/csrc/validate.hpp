@@ -42,6 +42,11 @@ Check check_generators(const void* H0, const void* Hk, int64_t d, int64_t K, int
 // of the FP32 path); 0 means dtype.
 Check check_expm(const void* omega, int64_t batch, int64_t d, int dtype, const void* U,
                  const void* ws, size_t ws_bytes, int out_dtype = 0);
+// qcheff_expm_grouped: G in [1, 8], every group valid for qcheff_expm_batched
+// (apart from the workspace), and the workspace at least one item of every
+// group with d > 32 (dtype without flags, out_dtype of the results).
+Check check_expm_grouped(int G, const void* const* omega, const int64_t* batch, const int64_t* d, int dtype,
+                         void* const* U, const void* ws, size_t ws_bytes, int out_dtype);
 // ws_given = false: the caller passes no workspace (the allocation-free entry
 // point brings its own scratch), so the workspace checks are skipped.
 Check check_propagate(const void* U, int64_t M, int64_t d, int dtype, int mode, const void* x,

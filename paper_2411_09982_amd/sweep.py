@@ -2,18 +2,20 @@
 
 Jobs are grouped by Hilbert-space dimension.  Within a group every job's
 coefficients and generators are written into one contiguous [jobs * M][d][d]
-buffer, all of the group's interval exponentials run as one batched call
-(d <= 32: one fused workgroup per matrix; larger d: the MFMA GEMM path in
-chunks), and all of the group's state chains advance in one launch
-(qcheff_propagate_batched).  Every step is a call of the C ABI.
+buffer, and all of the group's state chains advance in one launch
+(qcheff_propagate_batched).  The exponentials of all groups run in one call of
+qcheff_expm_grouped (``grouped=True``, the default): in each round every
+product stage is one persistent launch over all groups' tiles (d <= 32 groups
+take the fused one-workgroup kernel).  With ``grouped=False`` each group calls
+qcheff_expm_batched on its own.  Every step is a call of the C ABI.
 
-``capture()`` records each group's whole sequence into a HIP graph (via
-torch.cuda.CUDAGraph), after one eager pass has tuned the GEMM tiles and shown
-the largest scaling exponent of the group.  The graphs take the exponentials
-with a squaring bound (that exponent plus a margin), so nothing in them waits
-on the host; ``run()`` then replays them, and a group whose replay reports an
-exponent above its bound (new controls with larger norms) is run eagerly and
-captured again.
+``capture()`` records the whole sweep (grouped) or each group's sequence (per
+group) into HIP graphs (via torch.cuda.CUDAGraph), after one eager pass has
+tuned the GEMM tiles and shown the largest scaling exponent.  The graphs take
+the exponentials with a squaring bound (that exponent plus a margin), so
+nothing in them waits on the host; ``run()`` then replays them, and a replay
+that reports an exponent above its bound (new controls with larger norms) is
+redone eagerly and captured again.
 """
 from __future__ import annotations
 
@@ -30,7 +32,7 @@ class Sweep:
     exponentials are taken with the skew-Hermitian structure of the generators.
     """
 
-    def __init__(self, jobs, dtype, chunk: int = 256, device: str = "cuda:0"):
+    def __init__(self, jobs, dtype, chunk: int = 256, device: str = "cuda:0", grouped: bool = True):
         import torch
         import paper_2411_09982_amd as q
         self.q, self.torch = q, torch
@@ -63,8 +65,8 @@ class Sweep:
             gw = q.workspace_bytes(q.FN_GENERATORS, 1, d, Kmax, 2, q.C128)
             g["gen_ws"] = torch.empty(max(gw, 1), dtype=torch.uint8, device=device)
             nb = min(chunk, len(idx) * M)
-            g["exp_ws"] = torch.empty(q.workspace_bytes(q.FN_EXPM, nb, d, 1, 1, code), dtype=torch.uint8,
-                                      device=device)
+            g["exp_ws"] = None if grouped else torch.empty(q.workspace_bytes(q.FN_EXPM, nb, d, 1, 1, code),
+                                                           dtype=torch.uint8, device=device)
             g["s"] = torch.empty(len(idx) * M, dtype=torch.int32, device=device)
             g["graph"] = None
             g["bound"] = None
@@ -75,21 +77,58 @@ class Sweep:
         self.margin = 1
         self.replays = 0
         self.recaptures = 0
+        self.grouped = grouped
+        # one workspace for the grouped exponential: a chunk of each group per round
+        self.exp_ws = torch.empty(max(1, q.expm_grouped_ws_bytes(
+            [(g["d"], len(g["idx"]) * g["M"]) for g in self.groups], code, chunk)), dtype=torch.uint8,
+            device=device) if grouped else None
+        self.graph = None
+        self.bound = None
 
-    def _enqueue(self, g, bound=None) -> None:
-        """The group's whole sequence on the current stream."""
+    def _generators(self, g) -> None:
         q = self.q
-        M, d = g["M"], g["d"]
+        M = g["M"]
         for k, i in enumerate(g["idx"]):
             j = self.jobs[i]
             H0, Hk, u = g["ops"][k]
             q.magnus_coeffs(u, j.dt_sample, M, j.order, c1=g["c1"][k], c2=g["c2"][k])
             q.magnus_generators(H0, Hk, g["c1"][k], g["c2"][k], j.dt_interval, j.order, self.dtype,
                                 omega=g["omega"][k * M:(k + 1) * M], ws=g["gen_ws"])
-        q.expm_batched(g["omega"], U=g["U"], s_out=g["s"], ws=g["exp_ws"], skew_hermitian=True,
-                       squaring_bound=bound, unitary_refine=self.refine, out_c128=self.refine)
+
+    def _chains(self, g) -> None:
+        M, d = g["M"], g["d"]
         g["psi"].copy_(g["psi0"])
-        q.propagate_batched(g["U"].view(len(g["idx"]), M, d, d), g["psi"])
+        self.q.propagate_batched(g["U"].view(len(g["idx"]), M, d, d), g["psi"])
+
+    def _enqueue(self, g, bound=None) -> None:
+        """One group's whole sequence on the current stream (per-group mode)."""
+        self._generators(g)
+        self.q.expm_batched(g["omega"], U=g["U"], s_out=g["s"], ws=g["exp_ws"], skew_hermitian=True,
+                            squaring_bound=bound, unitary_refine=self.refine, out_c128=self.refine)
+        self._chains(g)
+
+    def _enqueue_all(self, bound=None) -> None:
+        """The whole sweep on the current stream (grouped mode): every group's
+        generators, one grouped exponential, every group's chains."""
+        for g in self.groups:
+            self._generators(g)
+        self.q.expm_grouped([g["omega"] for g in self.groups], Us=[g["U"] for g in self.groups],
+                            s_outs=[g["s"] for g in self.groups], ws=self.exp_ws, skew_hermitian=True,
+                            squaring_bound=bound, unitary_refine=self.refine, out_c128=self.refine)
+        for g in self.groups:
+            self._chains(g)
+
+    def _capture_all(self) -> None:
+        torch = self.torch
+        self.bound = max(int(g["s"].cpu().numpy().max()) for g in self.groups) + self.margin
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()   # default priority
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                self._enqueue_all(self.bound)
+        torch.cuda.current_stream().wait_stream(side)
+        self.graph = graph
 
     def _capture(self, g) -> None:
         torch = self.torch
@@ -104,8 +143,14 @@ class Sweep:
         g["graph"] = graph
 
     def capture(self) -> None:
-        """One eager pass per group, then a graph per group (see the module doc)."""
+        """One eager pass, then the graphs (see the module doc)."""
         torch = self.torch
+        if self.grouped:
+            self._enqueue_all()
+            torch.cuda.synchronize()
+            self._capture_all()
+            torch.cuda.synchronize()
+            return
         for g in self.groups:
             self._enqueue(g)
             torch.cuda.synchronize()
@@ -113,9 +158,25 @@ class Sweep:
         torch.cuda.synchronize()
 
     def run(self) -> dict:
-        """One pass over every job (graph replays once captured); returns per-group
-        wall times (s) measured with host clocks."""
+        """One pass over every job (graph replays once captured); returns wall
+        times (s) measured with host clocks: per group, or {"all": t} when grouped."""
         torch = self.torch
+        if self.grouped:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if self.graph is None:
+                self._enqueue_all()
+            else:
+                self.graph.replay()
+                self.replays += 1
+            torch.cuda.synchronize()
+            if self.graph is not None and any((g["s"].cpu().numpy() == -2).any() for g in self.groups if g["d"] > 32):
+                # an exponent above the bound: redo eagerly, capture with the new maximum
+                self._enqueue_all()
+                torch.cuda.synchronize()
+                self._capture_all()
+                self.recaptures += 1
+            return {"all": time.perf_counter() - t0}
         times = {}
         for g in self.groups:
             torch.cuda.synchronize()

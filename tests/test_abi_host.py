@@ -17,7 +17,7 @@ def test_exports_every_header_symbol():
                           "qcheff_propagate", "qcheff_workspace_bytes", "qcheff_last_error",
                           "qcheff_timing_enable", "qcheff_timing_read", "qcheff_propagate_batched",
                           "qcheff_propagate_action", "qcheff_sync_status", "qcheff_propagate_state_noalloc",
-                          "qcheff_npad_eliminate", "qcheff_npad_largest"}
+                          "qcheff_npad_eliminate", "qcheff_npad_largest", "qcheff_expm_grouped"}
     L = q.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -59,6 +59,43 @@ def test_generators_validation():
     assert g(FAKE, FAKE, 4, 1, q.C128, FAKE, FAKE, 3, 0.1, 1, q.C64, FAKE, None, 0, 4, None) == q.EINVAL
     assert g(None, FAKE, 4, 1, q.C128, FAKE, FAKE, 3, 0.1, 1, q.C64, FAKE, None, 0, 0, None) == q.EINVAL
     assert g(FAKE, FAKE, 4, 1, q.C128, FAKE, None, 3, 0.1, 2, q.C64, FAKE, FAKE, need, 0, None) == q.EINVAL
+
+
+def test_expm_grouped_validation():
+    # qcheff_expm_grouped: G in [1, 8], the per-group checks of qcheff_expm_batched,
+    # and one workspace holding at least one item of every group with d > 32
+    L = q.lib()
+    e = L.qcheff_expm_grouped
+    arr = ctypes.c_void_p * 3
+    i64 = ctypes.c_int64 * 3
+    cast = lambda x: ctypes.cast(x, ctypes.c_void_p)
+    base = FAKE.value
+    om = arr(base, base + (1 << 28), base + (2 << 28))
+    us = arr(base + (3 << 28), base + (4 << 28), base + (5 << 28))
+    dims, batch = i64(20, 40, 100), i64(3, 2, 5)
+    need = q.workspace_bytes(q.FN_EXPM, 1, 40, 1, 1, q.C64) + q.workspace_bytes(q.FN_EXPM, 1, 100, 1, 1, q.C64)
+    call = lambda G, o=om, b=batch, d=dims, u=us, ws=FAKE, n=need, dt=q.C64: e(
+        G, cast(o), cast(b), cast(d), dt, cast(u), None, ws, n, None)
+    assert call(0) == q.EINVAL and call(9) == q.EINVAL
+    assert e(3, None, cast(batch), cast(dims), q.C64, cast(us), None, FAKE, need, None) == q.EINVAL
+    assert e(3, cast(om), cast(batch), None, q.C64, cast(us), None, FAKE, need, None) == q.EINVAL
+    # the d = 20 group runs in the fused kernel and needs no workspace; the others one item each
+    assert call(3, n=need - 1) == q.EWORKSPACE
+    assert call(3, ws=None, n=0) == q.EWORKSPACE
+    # per-group checks, with the group named in the message
+    bad = i64(20, 0, 100)
+    assert call(3, d=bad) == q.EINVAL and b"group 1" in L.qcheff_last_error()
+    over = arr(base + (3 << 28), base + (4 << 28), base + (2 << 28) + 64)   # U of group 2 overlaps its omega
+    assert call(3, u=over) == q.EINVAL and b"group 2" in L.qcheff_last_error()
+    neg = i64(3, -1, 5)
+    assert call(3, b=neg) == q.EINVAL
+    # the flags of qcheff_expm_batched
+    assert call(3, dt=q.C64 | q.UNITARY_REFINE) == q.EINVAL          # refinement needs the skew flag
+    assert call(3, dt=q.C128 | q.SKEW_HERMITIAN | q.UNITARY_REFINE) == q.EINVAL
+    assert call(3, dt=q.C64 | q.SKEW_HERMITIAN | q.OUT_C128) == q.EINVAL   # complex128 output needs refinement
+    # empty groups launch nothing
+    zero = i64(0, 0, 0)
+    assert call(3, b=zero, ws=None, n=0) == q.OK
 
 
 def test_expm_validation_and_workspace():

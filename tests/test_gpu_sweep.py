@@ -1,4 +1,6 @@
-"""Batched sweep of uneven dimensions: grouped results equal the one-job path and the oracle."""
+"""Batched sweep of uneven dimensions: results equal the one-job path and the oracle,
+with the exponentials of all groups in one qcheff_expm_grouped call (the default)
+or per group, eagerly and from captured graphs."""
 import numpy as np
 import pytest
 import torch
@@ -38,12 +40,35 @@ def _states_equal(a, b):
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
-def test_sweep_graph_replays_match_eager(dtype):
+def test_sweep_grouped_matches_per_group_and_oracle(dtype):
+    # several groups above the fused small-d limit share every product launch;
+    # against each group run alone (whose products may take another tile) and
+    # against the oracle's chain of every job
+    jobs = wl.sweep_instances(9, M=10, config_id=37, dims=(64, 128, 256))
+    say(f"grouped sweep of {len(jobs)} jobs, d = {sorted({j.d for j in jobs})}, {dtype}")
+    sw = Sweep(jobs, dtype, chunk=8)
+    sw.run()
+    got = sw.states()
+    alone = Sweep(jobs, dtype, chunk=8, grouped=False)
+    alone.run()
+    ref_alone = alone.states()
+    for i, j in enumerate(jobs):
+        if dtype == torch.complex128:
+            assert np.abs(ref_alone[i] - got[i]).max() <= 1e-12, i
+        ref = oracle.run(j.H0, j.Hk, j.u, j.dt_sample, j.M, j.order, psi0=j.psi0)
+        inf = abs(oracle.state_infidelity(ref["psi"], got[i]))
+        assert inf <= (1e-12 if dtype == torch.complex128 else 1e-6), (i, j.d, inf)
+        assert abs(oracle.state_infidelity(ref_alone[i], got[i])) <= (1e-12 if dtype == torch.complex128 else 1e-6)
+
+
+@pytest.mark.parametrize("grouped", [True, False])
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_sweep_graph_replays_match_eager(dtype, grouped):
     # groups below and above the fused small-d limit; every replay is checked,
     # with eager work and synchronizations between the replays
     jobs = wl.sweep_instances(10, M=8, config_id=41, dims=(16, 64, 128))
-    say(f"sweep graph, {len(jobs)} jobs, {dtype}")
-    sw = Sweep(jobs, dtype, chunk=8)
+    say(f"sweep graph, {len(jobs)} jobs, {dtype}, grouped={grouped}")
+    sw = Sweep(jobs, dtype, chunk=8, grouped=grouped)
     sw.run()
     eager = sw.states()
     sw.capture()
@@ -53,27 +78,29 @@ def test_sweep_graph_replays_match_eager(dtype):
         assert _states_equal(eager, sw.states()), r
         q.expm_batched(other, skew_hermitian=True)     # unrelated eager work between replays
         torch.cuda.synchronize()
-    assert sw.replays == 3 * len(sw.groups) and sw.recaptures == 0
+    assert sw.replays == 3 * (1 if grouped else len(sw.groups)) and sw.recaptures == 0
 
 
-def test_sweep_graph_recaptures_when_norms_grow():
+@pytest.mark.parametrize("grouped", [True, False])
+def test_sweep_graph_recaptures_when_norms_grow(grouped):
     # new controls with larger amplitude (same operators) push the scaling
-    # exponent above the captured bound: the group runs eagerly and is captured
+    # exponent above the captured bound: the sweep runs eagerly and is captured
     # again, and the result equals a fresh eager sweep of the new controls
     dtype = torch.complex64
     jobs = wl.sweep_instances(4, M=8, config_id=43, dims=(64,))
-    say("sweep graph recapture")
-    sw = Sweep(jobs, dtype, chunk=8)
+    say(f"sweep graph recapture, grouped={grouped}")
+    sw = Sweep(jobs, dtype, chunk=8, grouped=grouped)
     sw.capture()
-    b0 = sw.groups[0]["bound"]
+    bound = (lambda: sw.bound) if grouped else (lambda: sw.groups[0]["bound"])
+    b0 = bound()
     # x1024 raises the largest exponent of these jobs from 9 to 11 (oracle)
     for k in range(len(jobs)):
         sw.groups[0]["ops"][k][2].mul_(1024.0)
     for j in jobs:
         j.u = j.u * 1024.0
     sw.run()
-    assert sw.recaptures == 1 and sw.groups[0]["bound"] > b0
-    fresh = Sweep(jobs, dtype, chunk=8)
+    assert sw.recaptures == 1 and bound() > b0
+    fresh = Sweep(jobs, dtype, chunk=8, grouped=grouped)
     fresh.run()
     assert _states_equal(fresh.states(), sw.states())
     sw.run()                                           # the new graph holds

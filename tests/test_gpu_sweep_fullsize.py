@@ -1,7 +1,8 @@
 """Full-size parity of the batched sweep: the 512 transmon-chain instances of
 uneven dimension (d in {16, 32, 64, 128, 256, 512}, M = 256, order 2, complex64)
 in the launch configuration `bench.py --sweep` times (one `Sweep` over all jobs,
-eager and then replayed from the captured per-group graphs).
+the exponentials of all groups in one grouped call, eager and then replayed from
+the captured graph).
 
 The oracle runs the whole chain of one job per dimension; every job's final
 state is checked against the norm bound of the FP32 path, and the graph replay
@@ -47,7 +48,7 @@ def test_sweep_512_instances_full_size():
         inf = abs(oracle.state_infidelity(ref["psi"], eager[i]))
         say(f"  job {i}: d={d}, 256-interval chain state infidelity {inf:.3e}")
         assert inf <= 1e-6, (i, d, inf)
-    # the captured graphs replay the same states
+    # the captured graph replays the same states
     sw.capture()
     sw.run()
     replay = sw.states()
