@@ -143,16 +143,20 @@ constexpr double kTheta13 = 5.371920351148152;
 // -------------------------------------------------------------- tile tuner
 //
 // The square batched products of one exponential call all share a shape.  The
-// first call for a (precision, d) pair times every tile configuration on the
-// chunk's own A*A product (two launches each, the second one timed with HIP
-// events) and keeps the fastest for the rest of the process.  Every
+// first call for a (precision, d, Hermitian or not) triple times every tile
+// configuration of kTunedCfgs on the chunk's own A*A product (for skew-Hermitian
+// inputs its upper half and the whole product, summed; two launches of each,
+// the second one timed with HIP events) and keeps the fastest for the rest of
+// the process.  Every
 // configuration accumulates each output element over k in the same order, so
 // the choice changes speed only, never a bit of the result.
 // QCHEFF_AUTOTUNE=0 replaces the timing with a size rule; QCHEFF_TUNE_FILE
-// names a text file of "precision d cfg" lines read at first use and appended
+// names a text file of "key d cfg" lines (key: the precision code, plus 100 for
+// Hermitian-half products) read at first use and appended
 // to after each new decision.
 std::mutex g_tune_mu;
 std::map<std::pair<int, int64_t>, int> g_tune;
+constexpr int kTuneHermKey = 100;   // added to the precision code of Hermitian-half products
 bool g_tune_loaded = false;
 
 int rule_cfg(int64_t d) { return d <= 96 ? 1 : 0; }
@@ -166,7 +170,7 @@ void tune_load_locked() {
     int prec, cfg;
     long long d;
     while (std::fscanf(fp, "%d %lld %d", &prec, &d, &cfg) == 3)
-      if (cfg == 0 || cfg == 1) g_tune[{prec, int64_t(d)}] = cfg;
+      if (cfg == 0 || cfg == 1 || cfg == 4) g_tune[{prec, int64_t(d)}] = cfg;
     std::fclose(fp);
   }
 }
@@ -182,9 +186,11 @@ void tune_store_locked(int prec, int64_t d, int cfg) {
 }
 
 template <typename T>
-int square_cfg(int64_t d, int64_t nb, const typename Cx<T>::t* A, typename Cx<T>::t* scratch, hipStream_t st,
-               int* cfg_out) {
-  const int prec = sizeof(T) == 8 ? QCHEFF_C128 : QCHEFF_C64;
+int square_cfg(int64_t d, int64_t nb, const typename Cx<T>::t* A, typename Cx<T>::t* scratch, bool herm,
+               hipStream_t st, int* cfg_out) {
+  // the key tells Hermitian-half products (skew-Hermitian inputs: five of the six
+  // Pade products) from general ones: larger tiles lose more on the diagonal
+  const int prec = (sizeof(T) == 8 ? QCHEFF_C128 : QCHEFF_C64) + (herm ? kTuneHermKey : 0);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_locked();
@@ -209,19 +215,28 @@ int square_cfg(int64_t d, int64_t nb, const typename Cx<T>::t* A, typename Cx<T>
     hipEvent_t e0, e1;
     QC_HIP(hipEventCreate(&e0));
     QC_HIP(hipEventCreate(&e1));
-    for (int cfg = 0; cfg < 2; ++cfg) {
-      auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
-      p.A = A; p.lda = d; p.sA = d * d;
-      p.B = A; p.ldb = d; p.sB = d * d;
-      p.C = scratch; p.ldc = d; p.sC = d * d;
-      QC_HIP((launch_cgemm<T>(p, st, 0)));
-      QC_HIP(hipEventRecord(e0, st));
-      QC_HIP((launch_cgemm<T>(p, st, 0)));
-      QC_HIP(hipEventRecord(e1, st));
-      QC_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      QC_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best_ms) { best_ms = ms; best = cfg; }
+    // the call's products as they come: with a Hermitian-half product first
+    // (skew-Hermitian inputs: five of the six Pade products), then a general one
+    // (the squarings); each timed after one untimed launch, the sum compared
+    for (const int cfg : kTunedCfgs) {
+      float total = 0.f;
+      for (const int hm : {herm ? 1 : 0, 0}) {
+        auto p = gemm_params<T>(int(d), int(d), int(d), int(nb), cfg);
+        p.A = A; p.lda = d; p.sA = d * d;
+        p.B = A; p.ldb = d; p.sB = d * d;
+        p.C = scratch; p.ldc = d; p.sC = d * d;
+        p.herm = hm;
+        QC_HIP((launch_cgemm<T>(p, st, 0)));
+        QC_HIP(hipEventRecord(e0, st));
+        QC_HIP((launch_cgemm<T>(p, st, 0)));
+        QC_HIP(hipEventRecord(e1, st));
+        QC_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        QC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        total += ms;
+        if (!herm) break;   // general products only
+      }
+      if (total < best_ms) { best_ms = total; best = cfg; }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -717,7 +732,9 @@ hipError_t launch_stage(GemmParams<T>* p, int G, hipStream_t st, const int64_t* 
   gg.per_xcd = int(most);
   LaunchTimer tm;
   tm.begin(st);
-  const hipError_t e = p[0].cfg == 1 ? launch_grouped_cfg<T, 1>(gg, st) : launch_grouped_cfg<T, 0>(gg, st);
+  const hipError_t e = p[0].cfg == 1   ? launch_grouped_cfg<T, 1>(gg, st)
+                      : p[0].cfg == 4 ? launch_grouped_cfg<T, 4>(gg, st)
+                                      : launch_grouped_cfg<T, 0>(gg, st);
   if (tm.on) tm.end(st, sizeof(T) == 8 ? KERNEL_GEMM_F64 : KERNEL_GEMM_F32, flops, bytes);
   return e;
 }
@@ -742,7 +759,7 @@ GemmParams<T> chunk_product(int cfg, int herm, typename Cx<T>::t* out, const typ
 // The product tile of a round: the split-BF16 kernel, or the configuration the
 // tuner picked for the group with the most product work.
 template <typename T>
-int round_cfg(ExpmChunk<T>* ch, int G, bool bf16x3, hipStream_t st, int* cfg) {
+int round_cfg(ExpmChunk<T>* ch, int G, bool bf16x3, bool skew, hipStream_t st, int* cfg) {
   if (bf16x3) {
     *cfg = bf16x3_cfg();
     return QCHEFF_OK;
@@ -752,7 +769,7 @@ int round_cfg(ExpmChunk<T>* ch, int G, bool bf16x3, hipStream_t st, int* cfg) {
     if (double(ch[g].d) * ch[g].d * ch[g].d * ch[g].nb > double(ch[gmax].d) * ch[gmax].d * ch[gmax].d * ch[gmax].nb)
       gmax = g;
   // the tuner times on the scaled A of that group, into its W (free before the products)
-  return square_cfg<T>(ch[gmax].d, ch[gmax].nb, ch[gmax].w.X[0], ch[gmax].w.X[4], st, cfg);
+  return square_cfg<T>(ch[gmax].d, ch[gmax].nb, ch[gmax].w.X[0], ch[gmax].w.X[4], skew, st, cfg);
 }
 
 // The exponentials of one round: a chunk of each of G dimension groups (G = 1
@@ -810,7 +827,7 @@ int expm_round(ExpmChunk<T>* ch, int G, int* cfg_io, bool bf16x3, bool skew, int
     QC_HIP(hipGetLastError());
   }
   if (*cfg_io < 0)   // a split-BF16 tile, or the tuned FP32 / FP64 one
-    if (int r = round_cfg<T>(ch, G, bf16x3, st, cfg_io)) return r;
+    if (int r = round_cfg<T>(ch, G, bf16x3, skew, st, cfg_io)) return r;
   const int cfg = *cfg_io;
   // For skew-Hermitian A every even power, W and V are Hermitian (and A W
   // skew-Hermitian): only half of each of those products is formed.

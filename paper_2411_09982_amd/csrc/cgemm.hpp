@@ -414,13 +414,27 @@ template <> struct GemmTile<double, 0> {
 template <> struct GemmTile<double, 1> {
   static constexpr int BM = 32, BN = 32, BK = 8, WM = 16, WN = 16, NT = 256, WPE = 8;
 };
+// cfg 4: the third candidate of the tile tuner (square, as the products of
+// (skew-)Hermitian results need).  FP32: 128x128 with eight waves of 64x32 and K
+// steps of 16 (four waves per SIMD, more operand reuse per LDS read); FP64:
+// 128x128 with sixteen waves of 32x32 (a quarter of the L2 traffic per flop of
+// the 64x64 tile).
+template <> struct GemmTile<float, 4> {
+  static constexpr int BM = 128, BN = 128, BK = 16, WM = 64, WN = 32, NT = 512, WPE = 4;
+};
+template <> struct GemmTile<double, 4> {
+  static constexpr int BM = 128, BN = 128, BK = 8, WM = 32, WN = 32, NT = 1024, WPE = 4;
+};
+constexpr int kTunedCfgs[3] = {0, 1, 4};   // the configurations the tuner times
 
 template <typename T> GemmParams<T> gemm_params(int M, int N, int K, int batch, int cfg = 0) {
   GemmParams<T> p{};
   p.M = M; p.N = N; p.K = K; p.batch = batch;
   p.cfg = cfg;
-  const int bm = cfg >= 2 ? 128 : cfg ? GemmTile<T, 1>::BM : GemmTile<T, 0>::BM;
-  const int bn = cfg >= 2 ? 128 : cfg ? GemmTile<T, 1>::BN : GemmTile<T, 0>::BN;
+  int bm = GemmTile<T, 0>::BM, bn = GemmTile<T, 0>::BN;
+  if (cfg == 1) { bm = GemmTile<T, 1>::BM; bn = GemmTile<T, 1>::BN; }
+  if (cfg == 2 || cfg == 3) { bm = 128; bn = 128; }   // split-BF16 tiles
+  if (cfg == 4) { bm = GemmTile<T, 4>::BM; bn = GemmTile<T, 4>::BN; }
   p.tiles_m = (M + bm - 1) / bm;
   p.tiles_n = (N + bn - 1) / bn;
   p.alpha = T(1); p.beta = T(0); p.gamma = T(0); p.nx = 0;

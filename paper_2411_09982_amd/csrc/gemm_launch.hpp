@@ -1,6 +1,6 @@
 // Launch of the batched complex GEMM: picks the kernel of the tile
-// configuration (FP32 cfg 0 / 1 on FP32 MFMA, FP32 cfg 2 on split BF16 MFMA,
-// FP64 cfg 0 / 1) and records the timing instrumentation.
+// configuration (FP32 cfg 0 / 1 / 4 on FP32 MFMA, FP32 cfg 2 / 3 on split BF16
+// MFMA, FP64 cfg 0 / 1 / 4) and records the timing instrumentation.
 #pragma once
 
 #include <type_traits>
@@ -44,6 +44,8 @@ hipError_t launch_cgemm(const GemmParams<T>& p, hipStream_t stream, int64_t acti
   }
   if (p.cfg == 1)
     launch_tile<T, 1>(p, unsigned(blocks), stream);
+  else if (p.cfg == 4)
+    launch_tile<T, 4>(p, unsigned(blocks), stream);
   else if (p.cfg == 0)
     launch_tile<T, 0>(p, unsigned(blocks), stream);
   const hipError_t e = hipGetLastError();
