@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <cstring>
@@ -620,36 +621,77 @@ int lu_solve(double2* aug, int* piv, int64_t d, int64_t nb, hipStream_t st) {
   return trsm_upper(c, 0, d, d, 2 * d);                      // R = U^{-1} Y
 }
 
-// Side streams of the current device for the grouped exponential (created on
-// first use, default priority, kept for the life of the process) and the
-// events that fork work onto them and join it back.
+// Side streams of one exponential call on the current device (default
+// priority), the events that fork work onto them and join it back, and pinned
+// host buffers for the squaring counts.  A call leases one set from a per-device
+// pool for its duration and hands it back at the end, so concurrent calls from
+// several host threads never share a set; sets are created on demand and kept
+// for the life of the process.  A set goes back with work still queued on its
+// streams, which only orders the next user's work behind it; every copy into
+// its pinned buffers has been waited on by then.
 struct SideStreams {
   static constexpr int kCount = 4;
-  hipStream_t stream[kCount];
-  hipEvent_t fork;
-  hipEvent_t join[kCount];
-  std::mutex mu;   // held from the fork to the join, so concurrent calls do not mix their events
+  hipStream_t stream[kCount] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kCount] = {};
+  hipEvent_t counts = nullptr;     // the squaring counts have reached the host
+  int* pinned = nullptr;           // host copies of the squaring counts
+  size_t pinned_n = 0;
 };
 
-int side_streams(SideStreams** out) {
-  static std::mutex mu;
-  static std::map<int, SideStreams*> by_dev;
+struct SideLease {
+  SideStreams* s = nullptr;
   int dev = 0;
-  QC_HIP(hipGetDevice(&dev));
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = by_dev.find(dev);
-  if (it != by_dev.end()) {
-    *out = it->second;
-    return QCHEFF_OK;
+  SideLease() = default;
+  SideLease(const SideLease&) = delete;
+  SideLease& operator=(const SideLease&) = delete;
+  ~SideLease();
+};
+
+std::mutex g_side_mu;
+std::map<int, std::vector<SideStreams*>> g_side_free;
+
+SideLease::~SideLease() {
+  if (!s) return;
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  g_side_free[dev].push_back(s);
+}
+
+int lease_side(SideLease& out) {
+  if (out.s) return QCHEFF_OK;
+  QC_HIP(hipGetDevice(&out.dev));
+  {
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    auto& v = g_side_free[out.dev];
+    if (!v.empty()) {
+      out.s = v.back();
+      v.pop_back();
+      return QCHEFF_OK;
+    }
   }
   auto* s = new SideStreams{};
   for (int k = 0; k < SideStreams::kCount; ++k) {
     QC_HIP(hipStreamCreateWithFlags(&s->stream[k], hipStreamNonBlocking));
     QC_HIP(hipEventCreateWithFlags(&s->join[k], hipEventDisableTiming));
   }
+  QC_HIP(hipEventCreateWithFlags(&s->counts, hipEventDisableTiming));
   QC_HIP(hipEventCreateWithFlags(&s->fork, hipEventDisableTiming));
-  by_dev[dev] = s;
-  *out = s;
+  out.s = s;
+  return QCHEFF_OK;
+}
+
+// A pinned host buffer of at least n ints (grown on demand: every copy into the
+// old one has been waited on before the set went back to the pool).
+int pinned_counts(SideStreams* s, size_t n, int** out) {
+  if (s->pinned_n < n) {
+    if (s->pinned) QC_HIP(hipHostFree(s->pinned));
+    s->pinned = nullptr;
+    s->pinned_n = 0;
+    QC_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->pinned), std::max<size_t>(n, 1024) * sizeof(int),
+                         hipHostMallocDefault));
+    s->pinned_n = std::max<size_t>(n, 1024);
+  }
+  *out = s->pinned;
   return QCHEFF_OK;
 }
 
@@ -772,28 +814,41 @@ int round_cfg(ExpmChunk<T>* ch, int G, bool bf16x3, bool skew, hipStream_t st, i
   return square_cfg<T>(ch[gmax].d, ch[gmax].nb, ch[gmax].w.X[0], ch[gmax].w.X[4], skew, st, cfg);
 }
 
-// The exponentials of one round: a chunk of each of G dimension groups (G = 1
-// for qcheff_expm_batched).  The elementwise steps and the FP64 solve run per
-// group; every product stage (the Pade products, each squaring, the
-// refinement's two products) is one launch over all groups.  *cfg is the tile
-// of the products: chosen in the first round (cfg < 0 on entry: after the
-// scaling, by round_cfg) and kept for the later ones, so that an item's
-// rounding does not depend on which round it falls in.
+// The exponential of a round (a chunk of each of G dimension groups; G = 1 for
+// qcheff_expm_batched) runs in three stages:
+//   A  per group the norm, the scaling and the squaring counts (copied to the
+//      host unless a bound is given), then the Pade products and the augmented
+//      system, each product stage one launch over all groups;
+//   B  per group the FP64 solve and the placing of its result (several groups'
+//      solves side by side on the side streams);
+//   C  the squarings (one launch over all groups per step), the refinement and
+//      the phase.
+// The tile of the products is chosen in the first round's stage A (cfg < 0 on
+// entry: after the scaling, by round_cfg) and kept for the later ones, so that
+// an item's rounding does not depend on which round it falls in.
+template <typename T> struct RoundState {
+  using C2 = typename Cx<T>::t;
+  const double2* mu[kMaxGroups] = {};
+  C2* Ubuf[kMaxGroups] = {};
+  C2* sq0[kMaxGroups] = {};
+  C2* sq1[kMaxGroups] = {};
+  int* s_host[kMaxGroups] = {};   // pinned copies of the squaring counts (bound < 0)
+  hipEvent_t s_ready = nullptr;   // recorded after those copies
+};
+
 template <typename T>
-int expm_round(ExpmChunk<T>* ch, int G, int* cfg_io, bool bf16x3, bool skew, int bound, bool refine,
-               hipStream_t st) {
+int expm_stage_a(ExpmChunk<T>* ch, int G, RoundState<T>& rs, int* cfg_io, bool bf16x3, bool skew, int bound,
+                 bool refine, hipStream_t st) {
   using C2 = typename Cx<T>::t;
   double b[14];
   pade_coefficients(13, b);
   const T c[14] = {T(b[0]), T(b[1]), T(b[2]), T(b[3]), T(b[4]), T(b[5]), T(b[6]),
                    T(b[7]), T(b[8]), T(b[9]), T(b[10]), T(b[11]), T(b[12]), T(b[13])};
-  const double2* mu[kMaxGroups] = {};
-  C2* Ubuf[kMaxGroups];
   for (int g = 0; g < G; ++g) {
     ExpmChunk<T>& k = ch[g];
     ExpmWs<T>& w = k.w;
     const int64_t d = k.d, nb = k.nb, dd = d * d;
-    Ubuf[g] = k.U ? k.U : reinterpret_cast<C2*>(k.U64);   // the chunk's destination, as scratch of its own type
+    rs.Ubuf[g] = k.U ? k.U : reinterpret_cast<C2*>(k.U64);   // the chunk's destination, as scratch of its own type
     // norms and smax start at zero (a fill kernel, not a memset)
     hipLaunchKernelGGL(fill_u32_kernel, dim3(nblocks(nb * 2, 256)), dim3(256), 0, st,
                        reinterpret_cast<uint32_t*>(w.norms), nb * 2, 0u);
@@ -808,7 +863,7 @@ int expm_round(ExpmChunk<T>* ch, int G, int* cfg_io, bool bf16x3, bool skew, int
     // in those states than the saved squaring wins.
     if (sizeof(T) == 8) {
       hipLaunchKernelGGL(trace_mean_kernel<C2>, dim3(unsigned(nb)), dim3(256), 0, st, k.omega, int(d), w.mu);
-      mu[g] = w.mu;
+      rs.mu[g] = w.mu;
     }
     {
       // partial column sums per 128-row tile go to the augmented-system buffer,
@@ -816,16 +871,20 @@ int expm_round(ExpmChunk<T>* ch, int G, int* cfg_io, bool bf16x3, bool skew, int
       const unsigned tiles = nblocks(d, kNormRows);
       double* partial = reinterpret_cast<double*>(w.aug);
       hipLaunchKernelGGL(norm1_partial_kernel<C2>, dim3(nblocks(d, 64), tiles, unsigned(nb)), dim3(256), 0, st,
-                         k.omega, int(d), mu[g], partial);
+                         k.omega, int(d), rs.mu[g], partial);
       hipLaunchKernelGGL(norm1_finish_kernel, dim3(unsigned(nb)), dim3(256), 0, st, partial, int(d), int(tiles),
                          w.norms);
     }
     QC_HIP(hipGetLastError());
     const unsigned sblocks = unsigned(std::min<int64_t>(nblocks(dd, 256), 1024));
     hipLaunchKernelGGL(scale_kernel<C2>, dim3(sblocks, unsigned(nb)), dim3(256), 0, st, k.omega, w.X[0], int(d),
-                       mu[g], w.norms, kTheta13, bound, w.s_ws, k.s_out, w.smax);
+                       rs.mu[g], w.norms, kTheta13, bound, w.s_ws, k.s_out, w.smax);
     QC_HIP(hipGetLastError());
+    // Without a bound the host reads the squaring counts back to size the
+    // squaring launches (stage C waits for them, long after they are ready)
+    if (bound < 0) QC_HIP(hipMemcpyAsync(rs.s_host[g], w.s_ws, size_t(nb) * sizeof(int), hipMemcpyDeviceToHost, st));
   }
+  if (bound < 0) QC_HIP(hipEventRecord(rs.s_ready, st));
   if (*cfg_io < 0)   // a split-BF16 tile, or the tuned FP32 / FP64 one
     if (int r = round_cfg<T>(ch, G, bf16x3, skew, st, cfg_io)) return r;
   const int cfg = *cfg_io;
@@ -849,7 +908,7 @@ int expm_round(ExpmChunk<T>* ch, int G, int* cfg_io, bool bf16x3, bool skew, int
     auto& w = ch[g].w;
     const int64_t n = ch[g].nb * ch[g].d * ch[g].d;
     hipLaunchKernelGGL((pade_inner_kernel<C2, T>), dim3(unsigned(std::min<int64_t>(nblocks(n, 256), 8192))),
-                       dim3(256), 0, st, w.X[3], w.X[2], w.X[1], n, c[13], c[11], c[9], c[12], c[10], c[8], Ubuf[g],
+                       dim3(256), 0, st, w.X[3], w.X[2], w.X[1], n, c[13], c[11], c[9], c[12], c[10], c[8], rs.Ubuf[g],
                        w.X[4]);
   }
   QC_HIP(hipGetLastError());
@@ -864,7 +923,7 @@ int expm_round(ExpmChunk<T>* ch, int G, int* cfg_io, bool bf16x3, bool skew, int
   for (int g = 0; g < G; ++g) {
     auto& w = ch[g].w;
     const C2* Xs[3] = {w.X[3], w.X[2], w.X[1]};
-    p[g] = chunk_product<T>(cfg, h, w.X[4], w.X[3], Ubuf[g], ch[g].d, ch[g].nb, 3, Xs, xw, c[1]);
+    p[g] = chunk_product<T>(cfg, h, w.X[4], w.X[3], rs.Ubuf[g], ch[g].d, ch[g].nb, 3, Xs, xw, c[1]);
   }
   QC_HIP(launch_stage<T>(p, G, st));   // W
   // [q | p] = [V - A W | V + A W] in FP64
@@ -880,63 +939,66 @@ int expm_round(ExpmChunk<T>* ch, int G, int* cfg_io, bool bf16x3, bool skew, int
   // The squarings ping-pong between the chunk's U and A; with the unitary
   // refinement they run in W and V instead (the refinement reads the last one
   // and writes U).  W and V are free once the augmented system is formed.
-  C2* sq0[kMaxGroups];
-  C2* sq1[kMaxGroups];
-  // The solves of several groups run side by side on the library's side streams
-  // (forked from and joined back into `st` through events, which graph capture
-  // records as dependencies): a solve is a chain of many small dependent
-  // launches, and the groups' chains fill each other's idle time.
-  SideStreams* side = nullptr;
-  std::unique_lock<std::mutex> side_lock;
-  if (G > 1) {
-    if (int r = side_streams(&side)) return r;
-    side_lock = std::unique_lock<std::mutex>(side->mu);
-    QC_HIP(hipEventRecord(side->fork, st));
+  for (int g = 0; g < G; ++g) {
+    rs.sq0[g] = refine ? ch[g].w.X[4] : ch[g].U;
+    rs.sq1[g] = refine ? ch[g].w.X[5] : ch[g].w.X[0];
   }
+  return QCHEFF_OK;
+}
+
+// Stage B on stream sb.  Several groups' solves run side by side on the side
+// streams, forked from and joined back into sb through events (which graph
+// capture records as dependencies): a solve is a chain of many small dependent
+// launches, and the groups' chains fill each other's idle time.
+template <typename T>
+int expm_stage_b(ExpmChunk<T>* ch, int G, RoundState<T>& rs, SideStreams* set, hipStream_t sb) {
+  using C2 = typename Cx<T>::t;
+  SideStreams* side = G > 1 ? set : nullptr;
+  if (side) QC_HIP(hipEventRecord(side->fork, sb));
   for (int g = 0; g < G; ++g) {
     auto& w = ch[g].w;
     const int64_t d = ch[g].d, dd = d * d;
-    hipStream_t sg = st;
+    hipStream_t sg = sb;
     if (side) {
       sg = side->stream[g % SideStreams::kCount];
       QC_HIP(hipStreamWaitEvent(sg, side->fork, 0));
     }
     if (int r = lu_solve(w.aug, w.piv, d, ch[g].nb, sg)) return r;
-    sq0[g] = refine ? w.X[4] : ch[g].U;
-    sq1[g] = refine ? w.X[5] : w.X[0];
     const unsigned sblocks = unsigned(std::min<int64_t>(nblocks(dd, 256), 1024));
     hipLaunchKernelGGL(place_result_kernel<C2>, dim3(sblocks, unsigned(ch[g].nb)), dim3(256), 0, sg, w.aug, int(d),
-                       w.s_ws, sq0[g], sq1[g]);
+                       w.s_ws, rs.sq0[g], rs.sq1[g]);
     QC_HIP(hipGetLastError());
   }
   if (side) {
     for (int k = 0; k < std::min(G, SideStreams::kCount); ++k) {
       QC_HIP(hipEventRecord(side->join[k], side->stream[k]));
-      QC_HIP(hipStreamWaitEvent(st, side->join[k], 0));
+      QC_HIP(hipStreamWaitEvent(sb, side->join[k], 0));
     }
-    side_lock.unlock();
   }
-  // Without a bound the host reads the squaring counts back to size the
-  // squaring launches; with one it enqueues exactly `bound` passes (an item
-  // leaves the passes once its own count is done) and never waits.
-  std::vector<int> s_host[kMaxGroups];
-  for (int g = 0; g < G; ++g) {
-    s_host[g].assign(size_t(ch[g].nb), bound);
-    if (bound < 0)
-      QC_HIP(hipMemcpyAsync(s_host[g].data(), ch[g].w.s_ws, size_t(ch[g].nb) * sizeof(int), hipMemcpyDeviceToHost, st));
-  }
-  if (bound < 0) QC_HIP(hipStreamSynchronize(st));
+  return QCHEFF_OK;
+}
+
+// Stage C: with a bound exactly `bound` squaring passes are enqueued (an item
+// leaves the passes once its own count is done) and nothing waits; without, the
+// host takes the counts stage A copied.
+template <typename T>
+int expm_stage_c(ExpmChunk<T>* ch, int G, RoundState<T>& rs, int cfg, int bound, bool refine, hipStream_t st) {
+  using C2 = typename Cx<T>::t;
+  if (bound < 0) QC_HIP(hipEventSynchronize(rs.s_ready));
   int smax = 0;
-  for (int g = 0; g < G; ++g) smax = std::max(smax, *std::max_element(s_host[g].begin(), s_host[g].end()));
+  for (int g = 0; g < G; ++g)
+    for (int64_t i = 0; i < ch[g].nb; ++i) smax = std::max(smax, bound < 0 ? rs.s_host[g][i] : bound);
+  GemmParams<T> p[kMaxGroups];
   for (int step = 0; step < smax; ++step) {
     int64_t active[kMaxGroups];
     for (int g = 0; g < G; ++g) {
       const int64_t d = ch[g].d, dd = d * d;
-      active[g] = std::count_if(s_host[g].begin(), s_host[g].end(), [step](int s) { return s > step; });
+      active[g] = bound >= 0 ? ch[g].nb
+                             : std::count_if(rs.s_host[g], rs.s_host[g] + ch[g].nb, [step](int s) { return s > step; });
       p[g] = gemm_params<T>(int(d), int(d), int(d), int(ch[g].nb), cfg);
       p[g].lda = d; p[g].ldb = d; p[g].ldc = d;
       p[g].sA = dd; p[g].sB = dd; p[g].sC = dd;
-      p[g].sq = 1; p[g].sq_s = ch[g].w.s_ws; p[g].sq_step = step; p[g].sq_p0 = sq0[g]; p[g].sq_p1 = sq1[g];
+      p[g].sq = 1; p[g].sq_s = ch[g].w.s_ws; p[g].sq_step = step; p[g].sq_p0 = rs.sq0[g]; p[g].sq_p1 = rs.sq1[g];
     }
     QC_HIP(launch_stage<T>(p, G, st, active));
   }
@@ -953,7 +1015,7 @@ int expm_round(ExpmChunk<T>* ch, int G, int* cfg_io, bool bf16x3, bool skew, int
         auto& w = ch[g].w;
         const int64_t d = ch[g].d, dd = d * d;
         hipLaunchKernelGGL(refine_prep_kernel, dim3(nblocks(d, 32), nblocks(d, 32), unsigned(ch[g].nb)), dim3(256), 0,
-                           st, reinterpret_cast<const float2*>(sq0[g]), int(d), w.aug);
+                           st, reinterpret_cast<const float2*>(rs.sq0[g]), int(d), w.aug);
         pd[g] = gemm_params<double>(int(d), int(d), int(d), int(ch[g].nb), rule_cfg(dmax));
         pd[g].A = w.aug; pd[g].lda = d; pd[g].sA = 2 * dd;
         pd[g].B = w.aug + dd; pd[g].ldb = d; pd[g].sB = 2 * dd;
@@ -968,9 +1030,9 @@ int expm_round(ExpmChunk<T>* ch, int G, int* cfg_io, bool bf16x3, bool skew, int
         const int64_t n = ch[g].nb * dd;
         hipLaunchKernelGGL(to_c64_kernel, dim3(unsigned(std::min<int64_t>(nblocks(n, 256), 8192))), dim3(256), 0, st,
                            reinterpret_cast<double2*>(w.X[0]), reinterpret_cast<float2*>(w.X[2]), n);
-        p[g] = chunk_product<T>(cfg, 0, ch[g].U64 ? sq0[g] : ch[g].U, w.X[2], sq0[g], d, ch[g].nb);
+        p[g] = chunk_product<T>(cfg, 0, ch[g].U64 ? rs.sq0[g] : ch[g].U, w.X[2], rs.sq0[g], d, ch[g].nb);
         p[g].alpha = T(0.5);
-        p[g].nx = 1; p[g].X[0] = sq0[g]; p[g].xc[0] = T(1);
+        p[g].nx = 1; p[g].X[0] = rs.sq0[g]; p[g].xc[0] = T(1);
         if (ch[g].U64) {   // R + (1/2) E R formed and kept in FP64: no final rounding to FP32
           p[g].epi = EPI_OUT64;
           p[g].aug = ch[g].U64; p[g].ld_aug = d; p[g].s_aug = dd;
@@ -981,13 +1043,41 @@ int expm_round(ExpmChunk<T>* ch, int G, int* cfg_io, bool bf16x3, bool skew, int
     }
   }
   for (int g = 0; g < G; ++g) {
-    if (!mu[g]) continue;
+    if (!rs.mu[g]) continue;
     const int64_t dd = ch[g].d * ch[g].d;
     const unsigned sblocks = unsigned(std::min<int64_t>(nblocks(dd, 256), 1024));
-    hipLaunchKernelGGL(phase_kernel<C2>, dim3(sblocks, unsigned(ch[g].nb)), dim3(256), 0, st, ch[g].U, dd, mu[g]);
+    hipLaunchKernelGGL(phase_kernel<C2>, dim3(sblocks, unsigned(ch[g].nb)), dim3(256), 0, st, ch[g].U, dd, rs.mu[g]);
     QC_HIP(hipGetLastError());
   }
   return QCHEFF_OK;
+}
+
+// Host-side state of a round: the pinned count buffer and its event, from the
+// call's set of side streams.
+template <typename T>
+int round_state(ExpmChunk<T>* ch, int G, int bound, SideStreams* side, RoundState<T>& rs) {
+  if (bound >= 0) return QCHEFF_OK;
+  size_t total = 0;
+  for (int g = 0; g < G; ++g) total += size_t(ch[g].nb);
+  int* buf = nullptr;
+  if (int r = pinned_counts(side, total, &buf)) return r;
+  for (int g = 0; g < G; ++g) {
+    rs.s_host[g] = buf;
+    buf += ch[g].nb;
+  }
+  rs.s_ready = side->counts;
+  return QCHEFF_OK;
+}
+
+// One round, the three stages in order on `st`.
+template <typename T>
+int expm_round(ExpmChunk<T>* ch, int G, int* cfg_io, bool bf16x3, bool skew, int bound, bool refine,
+               SideStreams* side, hipStream_t st) {
+  RoundState<T> rs;
+  if (int r = round_state<T>(ch, G, bound, side, rs)) return r;
+  if (int r = expm_stage_a<T>(ch, G, rs, cfg_io, bf16x3, skew, bound, refine, st)) return r;
+  if (int r = expm_stage_b<T>(ch, G, rs, side, st)) return r;
+  return expm_stage_c<T>(ch, G, rs, *cfg_io, bound, refine, st);
 }
 
 template <typename T>
@@ -1003,20 +1093,25 @@ int run_expm(const void* omega, int64_t batch, int64_t d, void* U, int32_t* s_ou
     QC_HIP(hipGetLastError());
     return QCHEFF_OK;
   }
+  const int64_t dd = d * d;
+  SideLease lease;
+  if (int r = lease_side(lease)) return r;
+  auto chunk_at = [&](ExpmChunk<T>& c, int64_t b0, int64_t nb) {
+    c.nb = nb;
+    c.d = d;
+    c.omega = static_cast<const C2*>(omega) + b0 * dd;
+    c.U = out64 ? nullptr : static_cast<C2*>(U) + b0 * dd;
+    c.U64 = out64 ? static_cast<double2*>(U) + b0 * dd : nullptr;
+    c.s_out = s_out ? s_out + b0 : nullptr;
+  };
+  int cfg = -1;
   // a chunk's items ride on the grid's y (or z) dimension
   const int64_t chunk = std::min<int64_t>(expm_chunk(ws_bytes, batch, d, dtype), 65535);
-  const int64_t dd = d * d;
   ExpmChunk<T> ch{};
   if (!carve_expm<T>(ws, ws_bytes, chunk, d, ch.w)) return fail(QCHEFF_EWORKSPACE, "workspace carving failed");
-  int cfg = -1;
   for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
-    ch.nb = std::min(chunk, batch - b0);
-    ch.d = d;
-    ch.omega = static_cast<const C2*>(omega) + b0 * dd;
-    ch.U = out64 ? nullptr : static_cast<C2*>(U) + b0 * dd;
-    ch.U64 = out64 ? static_cast<double2*>(U) + b0 * dd : nullptr;
-    ch.s_out = s_out ? s_out + b0 : nullptr;
-    if (int r = expm_round<T>(&ch, 1, &cfg, bf16x3, skew, bound, refine, st)) return r;
+    chunk_at(ch, b0, std::min(chunk, batch - b0));
+    if (int r = expm_round<T>(&ch, 1, &cfg, bf16x3, skew, bound, refine, lease.s, st)) return r;
   }
   return QCHEFF_OK;
 }
@@ -1080,6 +1175,8 @@ int run_expm_grouped(int G, const void* const* omega, const int64_t* batch, cons
       left -= n;
     }
   }
+  SideLease lease;
+  if (int e = lease_side(lease)) return e;
   int cfg = -1;   // every group has items in the first round, which picks the tile
   for (int64_t r = 0;; ++r) {
     ExpmChunk<T> ch[kMaxGroups];
@@ -1099,7 +1196,7 @@ int run_expm_grouped(int G, const void* const* omega, const int64_t* batch, cons
       c.w = w[k];
     }
     if (n == 0) break;
-    if (int e = expm_round<T>(ch, n, &cfg, bf16x3, skew, bound, refine, st)) return e;
+    if (int e = expm_round<T>(ch, n, &cfg, bf16x3, skew, bound, refine, lease.s, st)) return e;
   }
   return QCHEFF_OK;
 }

@@ -1,6 +1,7 @@
 // Host-side argument checks and workspace sizes (see validate.hpp).
 #include "validate.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
