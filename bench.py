@@ -714,7 +714,7 @@ def main():
             second["mixed_speedup"] = round(second[a.dtype]["value"] / second["c128"]["value"], 3)
         extra["second_workload"] = second
 
-    if a.line_serve_rate > 0:
+    if a.line_serve_rate > 0 and a.line_serve_requests > 0:
         # serving (the metric's p50/p99 latency): one Poisson stream below saturation
         extra["serving"] = serve_pass(a.line_serve_rate, a.line_serve_requests, 2411, a.serve_dmax, a.serve_mmax)
 

@@ -24,8 +24,8 @@
  *     qcheff_workspace_bytes().  It keeps no per-job state between calls.
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every call
  *     enqueues work on that stream and returns without waiting for it, except
- *     qcheff_expm_batched, which waits on the stream once per chunk to read the
- *     largest squaring count (see there).
+ *     qcheff_expm_batched and qcheff_expm_grouped, which wait once per chunk
+ *     (round) for its squaring counts to reach the host (see there).
  *   - Errors: every shape, pointer and workspace check runs on the host before
  *     anything is enqueued; on failure nothing is launched and the call returns
  *     a negative status.  qcheff_last_error() gives a message for the calling
@@ -208,8 +208,11 @@ int qcheff_magnus_generators(const void* H0, const void* Hk, int64_t d, int64_t 
  *              -1 where the norm was not finite (that item's U is NaN).
  *   ws         workspace of at least qcheff_workspace_bytes(QCHEFF_FN_EXPM, 1, d, ..);
  *              items are processed in chunks of as many as the workspace holds.
- *   The call waits on `stream` once per chunk (to read the largest squaring
- *   count of the chunk); everything else is enqueued.
+ *   Per chunk the squaring counts go to pinned host memory right after the
+ *   scaling; the call waits for them (not for the stream) before it enqueues the
+ *   squarings, by which time they are long there.  Everything else is enqueued.
+ *   Every launch goes to `stream` (side streams are used by qcheff_expm_grouped
+ *   alone).
  *   Returns QCHEFF_OK, QCHEFF_EINVAL, QCHEFF_EWORKSPACE, QCHEFF_EDEVICE.
  */
 int qcheff_expm_batched(const void* omega, int64_t batch, int64_t d, int dtype, void* U,
@@ -243,10 +246,12 @@ int qcheff_expm_batched(const void* omega, int64_t batch, int64_t d, int dtype, 
  *   groups' tiles (a work list of (group, item, tile) with each group's d and
  *   each item's squaring count); the elementwise steps and the LU solve run per
  *   group.  Split-BF16 products are launched per group.  Results equal those of
- *   qcheff_expm_batched on each group up to the rounding of the tile shape the
- *   round uses (the one tuned for its largest group).
- *   Without a squaring bound the call waits on the stream once per round; with
- *   QCHEFF_SQUARING_BOUND(n) it never waits (graph-capturable).
+ *   qcheff_expm_batched on each group bit for bit (every tile shape accumulates
+ *   in the same order).  The groups' solves run side by side on side streams of
+ *   the library's own, forked from `stream` and joined back through events.
+ *   Without a squaring bound the call waits once per round for the squaring
+ *   counts (as qcheff_expm_batched); with QCHEFF_SQUARING_BOUND(n) it never
+ *   waits (graph-capturable).
  *   Returns QCHEFF_OK, QCHEFF_EINVAL, QCHEFF_EWORKSPACE, QCHEFF_EUNSUPPORTED
  *   (graph capture without a bound), QCHEFF_EDEVICE.
  */
