@@ -93,6 +93,8 @@ def parse():
                     help="batched-sweep mode: 512 transmon-chain instances, d in {16..512}, M = 256, order 2; "
                          "prints one JSON line")
     ap.add_argument("--sweep-jobs", type=int, default=512)
+    ap.add_argument("--sweep-mode", choices=("both", "grouped", "per-group"), default="both",
+                    help="which exponential schedule the sweep mode times (both: per group, then grouped)")
     ap.add_argument("--action", action="store_true",
                     help="state-only mode: the first intervals of the d = 4096 job by the Taylor action vs the "
                          "propagator path; prints one JSON line")
@@ -375,7 +377,8 @@ def sweep(a):
     # call per pass (one persistent launch per product stage, the groups' solves
     # side by side); eagerly and replayed from captured graphs.  The last line
     # (grouped, replayed) is the figure of this mode.
-    for grouped in (False, True):
+    modes = {"both": (False, True), "grouped": (True,), "per-group": (False,)}[a.sweep_mode]
+    for grouped in modes:
         sw = Sweep(jobs, dtype, grouped=grouped)
         name = "grouped" if grouped else "per group"
         timed_runs(sw, f"eager, {name}")

@@ -189,8 +189,8 @@ void tune_store_locked(int prec, int64_t d, int cfg) {
 template <typename T>
 int square_cfg(int64_t d, int64_t nb, const typename Cx<T>::t* A, typename Cx<T>::t* scratch, bool herm,
                hipStream_t st, int* cfg_out) {
-  // the key tells Hermitian-half products (skew-Hermitian inputs: five of the six
-  // Pade products) from general ones: larger tiles lose more on the diagonal
+  // the key tells Hermitian-half products (skew-Hermitian inputs: all six Pade
+  // products) from general ones: larger tiles lose more on the diagonal
   const int prec = (sizeof(T) == 8 ? QCHEFF_C128 : QCHEFF_C64) + (herm ? kTuneHermKey : 0);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -217,8 +217,8 @@ int square_cfg(int64_t d, int64_t nb, const typename Cx<T>::t* A, typename Cx<T>
     QC_HIP(hipEventCreate(&e0));
     QC_HIP(hipEventCreate(&e1));
     // the call's products as they come: with a Hermitian-half product first
-    // (skew-Hermitian inputs: five of the six Pade products), then a general one
-    // (the squarings); each timed after one untimed launch, the sum compared
+    // (skew-Hermitian inputs: the six Pade products), then a general one (the
+    // squarings); each timed after one untimed launch, the sum compared
     for (const int cfg : kTunedCfgs) {
       float total = 0.f;
       for (const int hm : {herm ? 1 : 0, 0}) {

@@ -7,8 +7,8 @@ touches no other, and the squaring bound behaves as in qcheff_expm_batched.
 
 Tolerances are those of the expm parity tests (tests/test_gpu_parity.py):
 per-item infidelity 1e-12 (FP64) or 1e-6 (FP32 products, refined), unrefined
-FP32 max(1e-6, 4 2^s u32); against qcheff_expm_batched, which may tile the
-products of a group differently, the same bounds."""
+FP32 max(1e-6, 4 2^s u32); against qcheff_expm_batched bit for bit (every
+tile shape accumulates each element in the same order)."""
 import numpy as np
 import pytest
 import torch
@@ -58,15 +58,11 @@ def test_grouped_matches_oracle_and_batched(dtype, mode):
         assert np.all(inf <= tol), (d, inf)
         if dtype == torch.complex128:
             assert np.abs(Ug - ref).max() <= 1e-10
-        # the same group alone through qcheff_expm_batched
+        # the same group alone through qcheff_expm_batched, whose products may take
+        # another tile: every tile shape accumulates in the same order, so the bits agree
         U1, s1 = q.expm_batched(om.clone(), **kw)
         torch.cuda.synchronize()
-        assert torch.equal(s1, s)
-        U1g = host(U1).astype(np.complex128)
-        inf1 = np.abs(oracle.propagator_infidelity(U1g, Ug))
-        assert np.all(inf1 <= tol), (d, inf1)
-        if dtype == torch.complex128:
-            assert np.abs(U1g - Ug).max() <= 1e-12
+        assert torch.equal(s1, s) and torch.equal(U1, U), d
     assert q.sync_status() == q.OK
 
 
