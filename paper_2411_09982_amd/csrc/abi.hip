@@ -735,7 +735,7 @@ hipError_t launch_grouped_cfg(const GemmGroups<T>& gg, hipStream_t st) {
 template <typename T>
 hipError_t launch_stage(GemmParams<T>* p, int G, hipStream_t st, const int64_t* active = nullptr) {
   if (G == 1) return launch_cgemm<T>(p[0], st, active ? active[0] : -1);
-  if (p[0].cfg >= 2) {   // split-BF16 tiles (FP32 only): per group
+  if (split_bf16_cfg(p[0].cfg)) {   // split-BF16 tiles (FP32 only): per group
     for (int g = 0; g < G; ++g)
       if (hipError_t e = launch_cgemm<T>(p[g], st, active ? active[g] : -1)) return e;
     return hipSuccess;

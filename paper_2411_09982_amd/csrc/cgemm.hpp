@@ -184,6 +184,17 @@ __device__ __forceinline__ void tile_epilogue(const GemmParams<T>& p, const Tile
   }
 }
 
+// Sub-tile positions (row * 4 + column in a 4 x 4 grid) of the sixteen waves of
+// a 16-wave tile, four bits per wave.  A workgroup's waves are dealt to the four
+// SIMDs round-robin (waves w, w + 4, w + 8 and w + 12 share one; measured with
+// the hardware id register), and in a diagonal tile of a (skew-)Hermitian result
+// only the 10 positions on or above the diagonal do MFMA work.  In row-major
+// order one SIMD would carry four busy waves and another one; in this order
+// every SIMD carries two or three (so does every set {w : w / 4 = k}): +3-4 %
+// on Hermitian-half products at d = 512-1024, general ones unchanged.  Which
+// wave computes an element does not change how: results are the same bits.
+constexpr uint64_t kWavePos16 = 0xEFADB3C5'78916420ull;
+
 // One tile of C through the K loop and the epilogue (the LDS buffers belong to
 // the calling kernel).
 template <typename T, int BM, int BN, int BK, int WM, int WN, int NT>
@@ -204,7 +215,17 @@ __device__ __forceinline__ void cgemm_tile(const GemmParams<T>& p, const TileJob
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
+  int wm, wn;
+  if constexpr (BM / WM == 4 && WAVES_N == 4) {
+    // sixteen waves: sub-tile position kWavePos16[wave], so that the waves of a
+    // diagonal tile that have work (10 of 16) spread 2-3 to every SIMD
+    const int pos = int((kWavePos16 >> (4 * wave)) & 15);
+    wm = (pos >> 2) * WM;
+    wn = (pos & 3) * WN;
+  } else {
+    wm = (wave / WAVES_N) * WM;
+    wn = (wave % WAVES_N) * WN;
+  }
   // in a diagonal tile of a (skew-)Hermitian result a wave whose sub-tile lies
   // wholly below the diagonal has nothing to compute (it still helps load)
   const bool idle = p.herm && jb.tm == jb.tn && wm >= wn + WN;
@@ -426,6 +447,8 @@ template <> struct GemmTile<double, 4> {
   static constexpr int BM = 128, BN = 128, BK = 8, WM = 32, WN = 32, NT = 1024, WPE = 4;
 };
 constexpr int kTunedCfgs[3] = {0, 1, 4};   // the configurations the tuner times
+// the FP32 configurations on the BF16 matrix cores (split operands)
+constexpr bool split_bf16_cfg(int cfg) { return cfg == 2 || cfg == 3; }
 
 template <typename T> GemmParams<T> gemm_params(int M, int N, int K, int batch, int cfg = 0) {
   GemmParams<T> p{};

@@ -58,7 +58,8 @@ hipError_t launch_cgemm(const GemmParams<T>& p, hipStream_t stream, int64_t acti
     double bytes = elems * es;
     if (p.epi == EPI_AUG) bytes += mn * 32.0;  // V is the generic M N term; two FP64 halves are written
     if (p.epi == EPI_OUT64) bytes += mn * 8.0; // the result is written in FP64 (X_0 counted with nx)
-    const int kid = sizeof(T) == 8 ? KERNEL_GEMM_F64 : p.cfg >= 2 ? KERNEL_GEMM_BF16X3 : KERNEL_GEMM_F32;
+    const int kid = sizeof(T) == 8 ? KERNEL_GEMM_F64 : split_bf16_cfg(p.cfg) ? KERNEL_GEMM_BF16X3
+                                                      : KERNEL_GEMM_F32;
     tm.end(stream, kid, flops, bytes * double(active));
   }
   return e;

@@ -120,3 +120,59 @@ def test_grouped_nonfinite_item_and_bound():
         assert np.array_equal(host(se[g]) == -2, over)
         if over.any():
             assert torch.isnan(Ue[g][torch.from_numpy(over).to(DEV)]).all()
+
+
+_FORCED_TILE_CHILD = r"""
+import json, sys
+import numpy as np
+import torch
+import paper_2411_09982_amd as q
+import workloads as wl
+groups = [(40, 7), (64, 6), (100, 4), (130, 3)]
+out = {}
+for dtype in (torch.complex64, torch.complex128):
+    print("forced tile, grouped expm", dtype, groups, file=sys.stderr, flush=True)
+    oms = [torch.from_numpy(wl.random_skew_hermitian_batch(B, d, np.geomspace(0.05, 300.0, B), config_id=950 + k))
+           .to("cuda:0").to(dtype) for k, (d, B) in enumerate(groups)]
+    kw = dict(skew_hermitian=True, unitary_refine=dtype == torch.complex64, out_c128=dtype == torch.complex64)
+    q.expm_grouped([o.clone() for o in oms], **kw)
+    torch.cuda.synchronize()
+    q.timing_enable(True)
+    Us, ss = q.expm_grouped([o.clone() for o in oms], **kw)
+    torch.cuda.synchronize()
+    rec = {k: q.timing_read(k)["launches"] for k in (q.KERNEL_GEMM_F32, q.KERNEL_GEMM_BF16X3)}
+    q.timing_enable(False)
+    same = all(torch.equal(q.expm_batched(o.clone(), **kw)[0], U) for o, U in zip(oms, Us))
+    torch.cuda.synchronize()
+    out[str(dtype)] = dict(f32=rec[q.KERNEL_GEMM_F32], bf16=rec[q.KERNEL_GEMM_BF16X3], same=same,
+                           smax=max(int(s.max()) for s in ss), status=q.sync_status())
+print(json.dumps(out), flush=True)
+"""
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 4])
+def test_grouped_with_each_tuned_tile(tmp_path, cfg):
+    # every tile the tuner may pick, forced through the tune file in a fresh
+    # process (the table is read once per process): the grouped call launches
+    # each FP32 product stage once over all groups, records it as an FP32 GEMM,
+    # and gives the per-group bits
+    import json
+    import os
+    import subprocess
+    import sys
+    from tests.conftest import ROOT
+    say(f"expm grouped with tile configuration {cfg} forced")
+    tune = tmp_path / "tune.txt"
+    tune.write_text("".join(f"{prec} {d} {cfg}\n" for prec in (q.C64, q.C64 + 100, q.C128, q.C128 + 100)
+                            for d in (40, 64, 100, 130)))
+    env = dict(os.environ, QCHEFF_TUNE_FILE=str(tune), PYTHONPATH=ROOT)
+    r = subprocess.run([sys.executable, "-c", _FORCED_TILE_CHILD], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=180)
+    assert r.returncode == 0, r.stderr[-3000:]
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    c64, c128 = out[str(torch.complex64)], out[str(torch.complex128)]
+    assert c64["same"] and c128["same"]
+    assert c64["status"] == q.OK and c128["status"] == q.OK
+    # one round: six Pade stages, the squaring passes, the refinement's correction
+    assert c64["bf16"] == 0 and c64["f32"] == 6 + c64["smax"] + 1, c64
+    assert c128["f32"] == 0 and c128["bf16"] == 0
