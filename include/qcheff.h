@@ -242,7 +242,7 @@ int qcheff_expm_batched(const void* omega, int64_t batch, int64_t d, int dtype, 
  *   every unfinished group, as large as the workspace allows with the same
  *   number of rounds for all.  In a round every product stage (A^2, A^4, A^6,
  *   the two Pade polynomials, the augmented system, each squaring, the two
- *   products of the unitary refinement) is ONE persistent launch over all
+ *   products of the unitary refinement) is ONE launch over all
  *   groups' tiles (a work list of (group, item, tile) with each group's d and
  *   each item's squaring count); the elementwise steps and the LU solve run per
  *   group.  Split-BF16 products are launched per group.  Results equal those of

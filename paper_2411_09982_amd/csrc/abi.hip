@@ -708,27 +708,13 @@ template <typename T> struct ExpmChunk {
 };
 
 // One product stage over the round's groups: a single group takes the
-// per-launch kernel (with the timing record), several the persistent grouped
-// kernel, whose grid is as many workgroups as the chip holds at once.
-template <typename T, int CFG>
+// per-launch kernel (with the timing record), several the grouped kernel, a
+// workgroup per tile slot (eight times the busiest XCD's slot count).
+template <typename T, int CFG, int MODE = 0>
 hipError_t launch_grouped_cfg(const GemmGroups<T>& gg, hipStream_t st) {
   using G = GemmTile<T, CFG>;
-  auto kern = cgemm_grouped_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT, G::WPE>;
-  static int per_cu = 0;
-  if (per_cu == 0) {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(kern), G::NT, 0) !=
-            hipSuccess || n < 1)
-      n = 1;
-    per_cu = n;
-  }
-  int dev = 0, cus = 256;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  // as many workgroups as the chip holds at once, a multiple of the XCD count
-  const int slots = kXcds * gg.per_xcd;
-  const int grid = std::max(kXcds, std::min(slots, per_cu * cus) / kXcds * kXcds);
-  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(G::NT), 0, st, gg);
+  auto kern = cgemm_grouped_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT, G::WPE, MODE>;
+  hipLaunchKernelGGL(kern, dim3(unsigned(kXcds * gg.per_xcd)), dim3(G::NT), 0, st, gg);
   return hipGetLastError();
 }
 
@@ -774,9 +760,22 @@ hipError_t launch_stage(GemmParams<T>* p, int G, hipStream_t st, const int64_t* 
   gg.per_xcd = int(most);
   LaunchTimer tm;
   tm.begin(st);
-  const hipError_t e = p[0].cfg == 1   ? launch_grouped_cfg<T, 1>(gg, st)
-                      : p[0].cfg == 4 ? launch_grouped_cfg<T, 4>(gg, st)
-                                      : launch_grouped_cfg<T, 0>(gg, st);
+  hipError_t e;
+  if constexpr (sizeof(T) == 8) {
+    if (p[0].mode == 1) {   // FP64 products of complex64 operands: cfg 0 or 1
+      for (int g = 0; g < G; ++g)
+        if (p[g].mode != 1 || p[g].cfg != p[0].cfg || !p[g].a32 || p[g].M != p[g].N || p[g].N != p[g].K)
+          return hipErrorInvalidValue;
+      e = p[0].cfg == 1 ? launch_grouped_cfg<T, 1, 1>(gg, st)
+        : p[0].cfg == 0 ? launch_grouped_cfg<T, 0, 1>(gg, st)
+                        : hipErrorInvalidValue;
+      if (tm.on) tm.end(st, KERNEL_GEMM_F64, flops, bytes);
+      return e;
+    }
+  }
+  e = p[0].cfg == 1   ? launch_grouped_cfg<T, 1>(gg, st)
+    : p[0].cfg == 4 ? launch_grouped_cfg<T, 4>(gg, st)
+                    : launch_grouped_cfg<T, 0>(gg, st);
   if (tm.on) tm.end(st, sizeof(T) == 8 ? KERNEL_GEMM_F64 : KERNEL_GEMM_F32, flops, bytes);
   return e;
 }
@@ -1004,32 +1003,30 @@ int expm_stage_c(ExpmChunk<T>* ch, int G, RoundState<T>& rs, int cfg, int bound,
   }
   if constexpr (sizeof(T) == 4) {
     if (refine) {
-      // One Newton step of the polar decomposition: E = I - R R^dag in FP64
-      // from the FP32 result R (in sq0), then U = R + (1/2) E R.  U64 and
-      // U^dag sit side by side in the augmented-system buffer; E64 takes the
-      // space of A and A^2 (one complex128 matrix per item), E32 that of A^4.
+      // One Newton step of the polar decomposition: E = I - R R^dag for the FP32
+      // result R (in sq0), then U = R + (1/2) E R.  E is formed on the FP64
+      // matrix cores straight from R's complex64 values (their products are exact
+      // in FP64, so the sum carries FP64 accuracy) and written in complex64,
+      // enough for the small correction product; it takes the space of A^4.
       GemmParams<double> pd[kMaxGroups];
       int64_t dmax = 0;
       for (int g = 0; g < G; ++g) dmax = std::max(dmax, ch[g].d);
       for (int g = 0; g < G; ++g) {
         auto& w = ch[g].w;
         const int64_t d = ch[g].d, dd = d * d;
-        hipLaunchKernelGGL(refine_prep_kernel, dim3(nblocks(d, 32), nblocks(d, 32), unsigned(ch[g].nb)), dim3(256), 0,
-                           st, reinterpret_cast<const float2*>(rs.sq0[g]), int(d), w.aug);
         pd[g] = gemm_params<double>(int(d), int(d), int(d), int(ch[g].nb), rule_cfg(dmax));
-        pd[g].A = w.aug; pd[g].lda = d; pd[g].sA = 2 * dd;
-        pd[g].B = w.aug + dd; pd[g].ldb = d; pd[g].sB = 2 * dd;
-        pd[g].C = reinterpret_cast<double2*>(w.X[0]); pd[g].ldc = d; pd[g].sC = dd;
+        pd[g].mode = 1;
+        pd[g].a32 = reinterpret_cast<const float2*>(rs.sq0[g]); pd[g].ld32 = d; pd[g].s32 = dd;
+        pd[g].lda = d; pd[g].ldb = d;
+        pd[g].epi = EPI_C32;
+        pd[g].c32 = reinterpret_cast<float2*>(w.X[2]);
+        pd[g].C = reinterpret_cast<double2*>(w.X[2]); pd[g].ldc = d; pd[g].sC = dd;   // not written
         pd[g].alpha = -1.0; pd[g].gamma = 1.0; pd[g].herm = 1;
       }
-      QC_HIP(hipGetLastError());
       QC_HIP(launch_stage<double>(pd, G, st));
       for (int g = 0; g < G; ++g) {
         auto& w = ch[g].w;
         const int64_t d = ch[g].d, dd = d * d;
-        const int64_t n = ch[g].nb * dd;
-        hipLaunchKernelGGL(to_c64_kernel, dim3(unsigned(std::min<int64_t>(nblocks(n, 256), 8192))), dim3(256), 0, st,
-                           reinterpret_cast<double2*>(w.X[0]), reinterpret_cast<float2*>(w.X[2]), n);
         p[g] = chunk_product<T>(cfg, 0, ch[g].U64 ? rs.sq0[g] : ch[g].U, w.X[2], rs.sq0[g], d, ch[g].nb);
         p[g].alpha = T(0.5);
         p[g].nx = 1; p[g].X[0] = rs.sq0[g]; p[g].xc[0] = T(1);
@@ -1038,7 +1035,6 @@ int expm_stage_c(ExpmChunk<T>* ch, int G, RoundState<T>& rs, int cfg, int bound,
           p[g].aug = ch[g].U64; p[g].ld_aug = d; p[g].s_aug = dd;
         }
       }
-      QC_HIP(hipGetLastError());
       QC_HIP(launch_stage<T>(p, G, st));
     }
   }

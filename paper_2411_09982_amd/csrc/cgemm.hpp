@@ -3,6 +3,11 @@
 //   C_b = alpha * A_b B_b + beta * C_b + sum_i xc[i] X_{i,b} + gamma * I      (EPI_STD)
 //   aug_b[:, :N] = V_b - A_b B_b,  aug_b[:, off:off+N] = V_b + A_b B_b (FP64)  (EPI_AUG)
 //   aug_b = X_{0,b} + alpha * A_b B_b, formed and written in FP64            (EPI_OUT64)
+//   c32_b = EPI_STD's value, written in complex64                            (EPI_C32)
+//
+// The FP64 kernels with MODE 1 take complex64 operands A_b = R_b, B_b = R_b^dag
+// (R = a32) and widen them to FP64 as they load: the products of FP32 values are
+// exact in FP64, so R R^dag is formed to FP64 accuracy without an FP64 copy of R.
 //
 // A complex product is four real MFMA products on planar operands:
 //   Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br.
@@ -19,7 +24,7 @@
 
 namespace qcheff {
 
-enum { EPI_STD = 0, EPI_AUG = 1, EPI_OUT64 = 2 };
+enum { EPI_STD = 0, EPI_AUG = 1, EPI_OUT64 = 2, EPI_C32 = 3 };
 
 // Kernel ids of the timing instrumentation (match QCHEFF_KERNEL_* in qcheff.h).
 enum { KERNEL_GEMM_F32 = 1, KERNEL_GEMM_F64 = 2, KERNEL_GEMM_BF16X3 = 3, KERNEL_ACTION = 4 };
@@ -51,6 +56,11 @@ template <typename T> struct GemmParams {
   double2* aug; int64_t ld_aug, s_aug, aug_off;
   // squaring mode: A = B = in, C = out, chosen per item from the remaining count
   const int* sq_s; int sq_step; C2* sq_p0; C2* sq_p1;
+  // EPI_C32 target (ldc, sC)
+  float2* c32;
+  // mode 1 (FP64 kernels only): A = R, B = R^dag for the complex64 matrices R
+  int mode;
+  const float2* a32; int64_t ld32, s32;
 };
 
 // The item and tile a workgroup computes, and its operand pointers.
@@ -60,6 +70,7 @@ template <typename T> struct TileJob {
   const C2* A;
   const C2* B;
   C2* C;
+  const float2* R;   // mode 1: the item's complex64 operand
 };
 
 // Fills `j` for logical tile `bid` (item-major, then tile); false when it has
@@ -105,19 +116,25 @@ __device__ __forceinline__ bool tile_job(const GemmParams<T>& p, int bid, TileJo
     j.B = p.B + b * p.sB;
     j.C = p.C + b * p.sC;
   }
+  j.R = p.mode == 1 ? p.a32 + b * p.s32 : nullptr;
   return true;
 }
 
 // Writes a wave's TM x TN blocks of 16 x 16 accumulators (rows as acc_row<T>,
-// column lane % 16) through the epilogue the parameters select.
+// column lane % 16) through the epilogue the parameters select.  The mirror
+// half of a (skew-)Hermitian EPI_STD / EPI_C32 result goes through `scr`, the
+// wave's 16 x 16 LDS block: written transposed, it is read back so that 16
+// lanes store 16 consecutive elements of one row (written straight from the
+// accumulators, each lane's four values would land in four rows).
 template <typename T, int TM, int TN>
 __device__ __forceinline__ void tile_epilogue(const GemmParams<T>& p, const TileJob<T>& jb,
                                               const typename Cx<T>::acc (&accr)[TM][TN],
                                               const typename Cx<T>::acc (&acci)[TM][TN], int wm, int wn,
-                                              int lane) {
+                                              int lane, typename Cx<T>::t* scr = nullptr) {
   using C2 = typename Cx<T>::t;
   const int b = jb.b;
   C2* C = jb.C;
+  const bool lds_mirror = scr && p.herm && (p.epi == EPI_STD || p.epi == EPI_C32);
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
 #pragma unroll
@@ -169,16 +186,47 @@ __device__ __forceinline__ void tile_epilogue(const GemmParams<T>& p, const Tile
           if (p.herm && r == c) {   // a Hermitian diagonal is real, a skew-Hermitian one imaginary
             if (p.herm > 0) vi = T(0); else vr = T(0);
           }
-          C2 o;
-          o.x = vr;
-          o.y = vi;
-          C[off] = o;
-          if (p.herm && r != c) {
-            o.x = p.herm > 0 ? vr : -vr;
-            o.y = p.herm > 0 ? -vi : vi;
-            C[int64_t(c) * p.ldc + r] = o;
+          if (p.epi == EPI_C32) {
+            p.c32[b * p.sC + off] = make_float2(float(vr), float(vi));
+          } else {
+            C2 o;
+            o.x = vr;
+            o.y = vi;
+            C[off] = o;
+          }
+          if (p.herm && r != c) {   // the value of (c, r)
+            C2 m;
+            m.x = p.herm > 0 ? vr : -vr;
+            m.y = p.herm > 0 ? -vi : vi;
+            const int64_t moff = int64_t(c) * p.ldc + r;
+            if (lds_mirror)   // at the block's transposed place, stored below
+              scr[(lane & 15) * 16 + (acc_row<T>(lane, e) ^ (lane & 15))] = m;
+            else if (p.epi == EPI_C32)
+              p.c32[b * p.sC + moff] = make_float2(float(m.x), float(m.y));
+            else
+              C[moff] = m;
           }
         }
+      }
+      if (lds_mirror) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int R0 = jb.row0 + wm + i * 16, C0 = jb.col0 + wn + j * 16;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int tr = acc_row<T>(lane, e), tc = lane & 15;
+          const int r = R0 + tc, c = C0 + tr;   // the element whose mirror lands at (c, r)
+          const C2 m = scr[tr * 16 + (tc ^ tr)];
+          if (r < c && r < p.M && c < p.N) {
+            const int64_t moff = int64_t(c) * p.ldc + r;
+            if (p.epi == EPI_C32)
+              p.c32[b * p.sC + moff] = make_float2(float(m.x), float(m.y));
+            else
+              C[moff] = m;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
   }
@@ -197,10 +245,10 @@ constexpr uint64_t kWavePos16 = 0xEFADB3C5'78916420ull;
 
 // One tile of C through the K loop and the epilogue (the LDS buffers belong to
 // the calling kernel).
-template <typename T, int BM, int BN, int BK, int WM, int WN, int NT>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int MODE>
 __device__ __forceinline__ void cgemm_tile(const GemmParams<T>& p, const TileJob<T>& jb,
                                            typename Cx<T>::t (&As)[2][BK][BM + 1],
-                                           typename Cx<T>::t (&Bs)[2][BK][BN]) {
+                                           typename Cx<T>::t (&Bs)[2][BK][BN + (MODE == 1)]) {
   using C2 = typename Cx<T>::t;
   using Acc = typename Cx<T>::acc;
   constexpr int WAVES_N = BN / WN;
@@ -250,7 +298,8 @@ __device__ __forceinline__ void cgemm_tile(const GemmParams<T>& p, const TileJob
   // with the clamped form throughout)
   const C2* pa[LA];
   const C2* pb[LB];
-  if constexpr (sizeof(T) == 8) {
+  static_assert(MODE == 0 || sizeof(T) == 8, "complex64 operands widen into the FP64 kernel only");
+  if constexpr (sizeof(T) == 8 && MODE == 0) {
 #pragma unroll
     for (int q = 0; q < LA; ++q) {
       const int e = tid + NT * q;
@@ -262,8 +311,60 @@ __device__ __forceinline__ void cgemm_tile(const GemmParams<T>& p, const TileJob
       pb[q] = B + (e / BN) * ldb + min(col0 + e % BN, p.N - 1);   // B[k0 + kb][col] at pb[q][k0 ldb]
     }
   }
+  // mode 1: A = R and B = R^dag from the complex64 R (M = N = K); both tiles
+  // read R row-wise, k fastest (B's element (k, c) is conj R[c][k]), and B goes
+  // to LDS transposed, as A does (hence its padded rows).  Rows of R past M only
+  // feed outputs that are not stored: inside K their clamped addresses are fixed.
+  const float2* qa[MODE == 1 ? LA : 1];
+  const float2* qb[MODE == 1 ? LB : 1];
+  if constexpr (MODE == 1) {
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int e = tid + NT * q;
+      qa[q] = jb.R + min(row0 + e / BK, p.M - 1) * int(p.ld32) + e % BK;
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int e = tid + NT * q;
+      qb[q] = jb.R + min(col0 + e / BK, p.N - 1) * int(p.ld32) + e % BK;
+    }
+  }
   auto load = [&](int k0) {
-    if constexpr (sizeof(T) == 8) {
+    if constexpr (MODE == 1) {
+      if (k0 + BK <= p.K) {
+#pragma unroll
+        for (int q = 0; q < LA; ++q) {
+          const float2 v = qa[q][k0];
+          ra[q] = make_double2(double(v.x), double(v.y));
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+          const float2 v = qb[q][k0];
+          rb[q] = make_double2(double(v.x), -double(v.y));
+        }
+        return;
+      }
+      const float2* R = jb.R;
+      const int ld = int(p.ld32);
+#pragma unroll
+      for (int q = 0; q < LA; ++q) {
+        const int e = tid + NT * q, r = e / BK, k = e % BK;
+        const int gr = row0 + r, gk = k0 + k;
+        const bool in = gr < p.M && gk < p.K;
+        const float2 v = R[min(gr, p.M - 1) * ld + max(0, min(gk, p.K - 1))];
+        ra[q] = in ? make_double2(double(v.x), double(v.y)) : czero<C2>();
+      }
+#pragma unroll
+      for (int q = 0; q < LB; ++q) {
+        const int e = tid + NT * q, c = e / BK, k = e % BK;
+        const int gc = col0 + c, gk = k0 + k;
+        const bool in = gc < p.N && gk < p.K;
+        const float2 v = R[min(gc, p.N - 1) * ld + max(0, min(gk, p.K - 1))];
+        rb[q] = in ? make_double2(double(v.x), -double(v.y)) : czero<C2>();
+      }
+      return;
+    }
+    if constexpr (sizeof(T) == 8 && MODE == 0) {
       if (k0 + BK <= p.K) {
 #pragma unroll
         for (int q = 0; q < LA; ++q) ra[q] = pa[q][k0];
@@ -298,7 +399,10 @@ __device__ __forceinline__ void cgemm_tile(const GemmParams<T>& p, const TileJob
 #pragma unroll
     for (int q = 0; q < LB; ++q) {
       const int e = tid + NT * q;
-      Bs[buf][e / BN][e % BN] = rb[q];
+      if constexpr (MODE == 1)
+        Bs[buf][e % BK][e / BK] = rb[q];
+      else
+        Bs[buf][e / BN][e % BN] = rb[q];
     }
   };
 
@@ -346,28 +450,34 @@ __device__ __forceinline__ void cgemm_tile(const GemmParams<T>& p, const TileJob
     __syncthreads();
   }
 
-  tile_epilogue<T, TM, TN>(p, jb, accr, acci, wm, wn, lane);
+  // the LDS tiles are free now (the last K step ended on a barrier): each wave
+  // takes a 16 x 16 block of them for the mirror stores
+  constexpr int kScrA = 2 * BK * (BM + 1) / 256, kScrB = 2 * BK * BN / 256;
+  static_assert(NT / 64 <= kScrA + kScrB, "a 16 x 16 LDS block per wave");
+  C2* scr = wave < kScrA ? &As[0][0][0] + wave * 256 : &Bs[0][0][0] + (wave - kScrA) * 256;
+  tile_epilogue<T, TM, TN>(p, jb, accr, acci, wm, wn, lane, scr);
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int WAVES_PER_EU>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int WAVES_PER_EU, int MODE = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU))) void cgemm_kernel(
     GemmParams<T> p) {
   using C2 = typename Cx<T>::t;
   __shared__ C2 As[2][BK][BM + 1];
-  __shared__ C2 Bs[2][BK][BN];
+  __shared__ C2 Bs[2][BK][BN + (MODE == 1)];
   TileJob<T> jb;
   if (!tile_job<T, BM, BN>(p, xcd_remap(blockIdx.x, gridDim.x), jb)) return;
-  cgemm_tile<T, BM, BN, BK, WM, WN, NT>(p, jb, As, Bs);
+  cgemm_tile<T, BM, BN, BK, WM, WN, NT, MODE>(p, jb, As, Bs);
 }
 
 // Grouped products: up to kMaxGroups batches of different shapes (the
-// dimension groups of an uneven sweep) in one persistent launch.  The hardware
-// hands workgroups to the eight XCDs in turn, and the grid is a multiple of
-// eight, so tile slot t runs on XCD t % 8.  Every group's items are split evenly
-// over the XCDs (XCD x takes items [item0[x][g], item0[x][g] + count) of group
-// g), so each XCD gets the same mix of cheap and costly tiles, and an item's
-// tiles share one L2.  XCD x walks its slots j = t / 8: group g holds slots
-// [base[x][g], base[x][g + 1]), item-major.
+// dimension groups of an uneven sweep) in one launch, a workgroup per tile
+// slot.  The hardware hands workgroups to the eight XCDs in turn, so slot t
+// runs on XCD t % 8.  Every group's items are split evenly over the XCDs (XCD x
+// takes items [item0[x][g], item0[x][g] + count) of group g), so each XCD gets
+// the same mix of cheap and costly tiles, and an item's tiles share one L2.
+// XCD x's slots are j = t / 8: group g holds slots [base[x][g], base[x][g + 1]),
+// item-major.  (A persistent form, a grid of resident workgroups walking the
+// slots, ran 2-4 % slower: values it hoisted out of its tile loop spilled.)
 constexpr int kMaxGroups = 8;
 constexpr int kXcds = 8;
 template <typename T> struct GemmGroups {
@@ -378,25 +488,23 @@ template <typename T> struct GemmGroups {
   GemmParams<T> p[kMaxGroups];
 };
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int WAVES_PER_EU>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int WAVES_PER_EU, int MODE = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU))) void cgemm_grouped_kernel(
     GemmGroups<T> gg) {
   using C2 = typename Cx<T>::t;
   __shared__ C2 As[2][BK][BM + 1];
-  __shared__ C2 Bs[2][BK][BN];
-  for (int t = blockIdx.x; t < kXcds * gg.per_xcd; t += gridDim.x) {
-    const int x = t % kXcds, j = t / kXcds;
-    if (j >= gg.base[x][gg.G]) continue;   // this XCD has fewer slots
-    int g = 0;
-    while (g + 1 < gg.G && j >= gg.base[x][g + 1]) ++g;
-    const GemmParams<T>& p = gg.p[g];
-    const int tiles = p.herm ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
-    const int local = j - gg.base[x][g];
-    TileJob<T> jb;
-    if (!tile_job<T, BM, BN>(p, (gg.item0[x][g] + local / tiles) * tiles + local % tiles, jb)) continue;
-    cgemm_tile<T, BM, BN, BK, WM, WN, NT>(p, jb, As, Bs);
-    __syncthreads();   // the next tile refills the LDS buffers
-  }
+  __shared__ C2 Bs[2][BK][BN + (MODE == 1)];
+  const int t = blockIdx.x;
+  const int x = t % kXcds, j = t / kXcds;
+  if (j >= gg.base[x][gg.G]) return;   // this XCD has fewer slots
+  int g = 0;
+  while (g + 1 < gg.G && j >= gg.base[x][g + 1]) ++g;
+  const GemmParams<T>& p = gg.p[g];
+  const int tiles = p.herm ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
+  const int local = j - gg.base[x][g];
+  TileJob<T> jb;
+  if (!tile_job<T, BM, BN>(p, (gg.item0[x][g] + local / tiles) * tiles + local % tiles, jb)) return;
+  cgemm_tile<T, BM, BN, BK, WM, WN, NT, MODE>(p, jb, As, Bs);
 }
 
 // Tile configurations per precision: cfg 0 is the large tile, cfg 1 the small

@@ -18,7 +18,14 @@ template <typename T, int CFG> void launch_tile(const GemmParams<T>& p, unsigned
   else if constexpr (std::is_same_v<T, float> && CFG == 2)
     hipLaunchKernelGGL((cgemm_bf16x3_kernel<G::BM, G::BN, G::WM, G::WN, G::NT>), dim3(blocks), dim3(G::NT), 0, stream,
                        p);
-  else
+  else if constexpr (sizeof(T) == 8 && (CFG == 0 || CFG == 1)) {
+    if (p.mode == 1)
+      hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT, G::WPE, 1>), dim3(blocks),
+                         dim3(G::NT), 0, stream, p);
+    else
+      hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT, G::WPE>), dim3(blocks),
+                         dim3(G::NT), 0, stream, p);
+  } else
     hipLaunchKernelGGL((cgemm_kernel<T, G::BM, G::BN, G::BK, G::WM, G::WN, G::NT, G::WPE>), dim3(blocks), dim3(G::NT),
                        0, stream, p);
 }
@@ -32,6 +39,10 @@ hipError_t launch_cgemm(const GemmParams<T>& p, hipStream_t stream, int64_t acti
       p.ldc * int64_t(p.M) >= (int64_t(1) << 31))
     return hipErrorInvalidValue;
   if (p.herm && (p.M != p.N || p.tiles_m != p.tiles_n)) return hipErrorInvalidValue;
+  // mode 1: FP64 kernels of cfg 0 / 1 only, square products of one matrix
+  if (p.mode == 1 && (sizeof(T) != 8 || (p.cfg != 0 && p.cfg != 1) || p.M != p.N || p.N != p.K || !p.a32))
+    return hipErrorInvalidValue;
+  if (p.epi == EPI_C32 && !p.c32) return hipErrorInvalidValue;
   const int64_t tiles = p.herm ? int64_t(p.tiles_m) * (p.tiles_m + 1) / 2 : int64_t(p.tiles_m) * p.tiles_n;
   const int64_t blocks = tiles * p.batch;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
@@ -58,6 +69,8 @@ hipError_t launch_cgemm(const GemmParams<T>& p, hipStream_t stream, int64_t acti
     double bytes = elems * es;
     if (p.epi == EPI_AUG) bytes += mn * 32.0;  // V is the generic M N term; two FP64 halves are written
     if (p.epi == EPI_OUT64) bytes += mn * 8.0; // the result is written in FP64 (X_0 counted with nx)
+    if (p.mode == 1) bytes -= (double(p.M) * p.K + double(p.K) * p.N) * (es - 8.0);   // complex64 operands
+    if (p.epi == EPI_C32) bytes -= mn * (es - 8.0);                                   // complex64 result
     const int kid = sizeof(T) == 8 ? KERNEL_GEMM_F64 : split_bf16_cfg(p.cfg) ? KERNEL_GEMM_BF16X3
                                                       : KERNEL_GEMM_F32;
     tm.end(stream, kid, flops, bytes * double(active));

@@ -467,48 +467,9 @@ __global__ __launch_bounds__(256) void place_result_kernel(const double2* __rest
 // each step, so after s of them the propagator is off unitarity by about
 // 2^s u32.  One Newton step of the polar decomposition removes that radial
 // error: with E = I - U U^dag (formed in FP64 from the FP32 values),
-// U' = U + (1/2) E U is unitary up to O(|E|^2).  These kernels stage it.
-
-// U64 = U and UH64 = U^dag in complex128, out[b] = [U64 | UH64] (two d x d
-// matrices per item), through 32 x 32 LDS tiles so that the transposed write
-// runs along rows too.
-__global__ __launch_bounds__(256) void refine_prep_kernel(const float2* __restrict__ U, int d,
-                                                          double2* __restrict__ out) {
-  __shared__ double2 t[32][33];
-  const int64_t dd = int64_t(d) * d;
-  const float2* Ub = U + int64_t(blockIdx.z) * dd;
-  double2* U64 = out + int64_t(blockIdx.z) * 2 * dd;
-  double2* UH = U64 + dd;
-  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int r = ty; r < 32; r += 8) {
-    const int i = i0 + r, j = j0 + tx;
-    if (i < d && j < d) {
-      const float2 v = Ub[int64_t(i) * d + j];
-      const double2 w = make_double2(double(v.x), double(v.y));
-      U64[int64_t(i) * d + j] = w;
-      t[r][tx] = w;
-    }
-  }
-  __syncthreads();
-  for (int r = ty; r < 32; r += 8) {
-    const int j = j0 + r, i = i0 + tx;   // UH[j][i] = conj(U[i][j])
-    if (i < d && j < d) {
-      const double2 w = t[tx][r];
-      UH[int64_t(j) * d + i] = make_double2(w.x, -w.y);
-    }
-  }
-}
-
-// n complex128 values rounded to complex64 (the FP64 defect E, whose entries
-// are of the size of the radial error, before the FP32 correction product).
-__global__ __launch_bounds__(256) void to_c64_kernel(const double2* __restrict__ x, float2* __restrict__ y,
-                                                     int64_t n) {
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x) {
-    const double2 v = x[e];
-    y[e] = make_float2(float(v.x), float(v.y));
-  }
-}
+// U' = U + (1/2) E U is unitary up to O(|E|^2).  Both steps are GEMMs: the
+// FP64 kernel reads U's complex64 values itself and writes E in complex64, and
+// the FP32 kernel adds (1/2) E U to U in FP64 (cgemm.hpp, EPI_C32, EPI_OUT64).
 
 // ---------------------------------------------------------------- chain
 //

@@ -5,7 +5,7 @@ coefficients and generators are written into one contiguous [jobs * M][d][d]
 buffer, and all of the group's state chains advance in one launch
 (qcheff_propagate_batched).  The exponentials of all groups run in one call of
 qcheff_expm_grouped (``grouped=True``, the default): in each round every
-product stage is one persistent launch over all groups' tiles (d <= 32 groups
+product stage is one launch over all groups' tiles (d <= 32 groups
 take the fused one-workgroup kernel).  With ``grouped=False`` each group calls
 qcheff_expm_batched on its own.  Every step is a call of the C ABI.
 

@@ -1,5 +1,5 @@
 """qcheff_expm_grouped: several batches of different dimension in one call,
-every product stage one persistent launch over all groups.  Checked against
+every product stage one launch over all groups.  Checked against
 the oracle (exp by eigendecomposition, oracle/magnus.py) per item, against
 qcheff_expm_batched per group, and for its own invariants: the result does not
 depend on how the workspace cuts the groups into rounds, a non-finite item
