@@ -1400,18 +1400,25 @@ int run_action(const void* Ov, int64_t M, int64_t d, void* x, void* traj, double
   return QCHEFF_OK;
 }
 
-// y = U x: 16-byte row loads where the rows are 16-byte aligned (complex128, or
-// complex64 with an even d), x in LDS up to d = 2048.
+// y = U x: a workgroup per row with 16-byte row loads where the rows are
+// 16-byte aligned (complex128, or complex64 with an even d), about eight loads
+// per thread (64 to 512 threads per row); one element per lane per step
+// otherwise.
 template <typename C2>
 void launch_matvec(const C2* U, const double2* x, double2* y, int64_t d, hipStream_t st) {
-  const dim3 grid(nblocks(d, 4)), block(256);
   if ((sizeof(C2) == 16 || d % 2 == 0) && reinterpret_cast<uintptr_t>(U) % 16 == 0) {
-    if (d <= 2048)
-      hipLaunchKernelGGL((matvec16_kernel<C2, true>), grid, block, size_t(d) * 16, st, U, x, y, int(d));
+    const int64_t pieces = sizeof(C2) == 16 ? d : d / 2;
+    const dim3 grid{unsigned(d)};
+    if (pieces <= 512)
+      hipLaunchKernelGGL((matvec_rows_kernel<C2, 64>), grid, dim3(64), 0, st, U, x, y, int(d));
+    else if (pieces <= 1024)
+      hipLaunchKernelGGL((matvec_rows_kernel<C2, 128>), grid, dim3(128), 0, st, U, x, y, int(d));
+    else if (pieces <= 2048)
+      hipLaunchKernelGGL((matvec_rows_kernel<C2, 256>), grid, dim3(256), 0, st, U, x, y, int(d));
     else
-      hipLaunchKernelGGL((matvec16_kernel<C2, false>), grid, block, 0, st, U, x, y, int(d));
+      hipLaunchKernelGGL((matvec_rows_kernel<C2, 512>), grid, dim3(512), 0, st, U, x, y, int(d));
   } else {
-    hipLaunchKernelGGL(matvec_kernel<C2>, grid, block, 0, st, U, x, y, int(d));
+    hipLaunchKernelGGL(matvec_kernel<C2>, dim3(nblocks(d, 4)), dim3(256), 0, st, U, x, y, int(d));
   }
 }
 

@@ -473,55 +473,54 @@ __global__ __launch_bounds__(256) void place_result_kernel(const double2* __rest
 
 // ---------------------------------------------------------------- chain
 //
-// y = U x with U in C2 (FP32 or FP64) and x, y in FP64; one wave per row.
-// A lane reads the row in 16-byte pieces (two complex64 values or one
-// complex128), 8 (complex64) or 16 (complex128) pieces in flight before any
-// arithmetic, so a d = 1024 row is one round; x is staged in LDS when it fits
-// (XLDS).  Complex64 rows need an even d (16-byte aligned rows);
-// matvec_kernel below takes any d.
+// y = U x with U in C2 (FP32 or FP64) and x, y in FP64.  Vec16: the 16-byte
+// piece of a row (two complex64 values or one complex128).
 template <typename C2> struct Vec16;
-template <> struct Vec16<float2> { using t = float4; static constexpr int per = 2; static constexpr int inflight = 8; };
-template <> struct Vec16<double2> { using t = double2; static constexpr int per = 1; static constexpr int inflight = 16; };
+template <> struct Vec16<float2> { using t = float4; static constexpr int per = 2; };
+template <> struct Vec16<double2> { using t = double2; static constexpr int per = 1; };
 
-template <typename C2, bool XLDS>
-__global__ __launch_bounds__(256) void matvec16_kernel(const C2* __restrict__ U, const double2* __restrict__ x,
-                                                       double2* __restrict__ y, int d) {
-  using V = typename Vec16<C2>::t;
-  constexpr int PER = Vec16<C2>::per, NL = Vec16<C2>::inflight;
-  extern __shared__ double2 xs[];   // [d] when XLDS
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + wave;
-  const bool active = row < d;
-  const int nch = d / PER;   // 16-byte pieces per row
-  const V* ur = reinterpret_cast<const V*>(U + int64_t(active ? row : 0) * d);
-  V buf[NL];
-  auto load = [&](int c0) {
-#pragma unroll
-    for (int t = 0; t < NL; ++t) {
-      const int c = c0 + lane + 64 * t;
-      buf[t] = ur[c < nch ? c : 0];
-    }
-  };
-  load(0);   // the first pieces are in flight while x is staged
-  if constexpr (XLDS) {
-    for (int i = threadIdx.x; i < d; i += blockDim.x) xs[i] = x[i];
-    __syncthreads();
-  }
-  const double2* xv = XLDS ? xs : x;
+// y = U x with a workgroup of NT threads per row: thread t takes the row's
+// 16-byte pieces t, t + NT, ... (eight in flight per round, U read with
+// nontemporal loads: each element is used once) with the matching entries of x
+// (from L2), and the workgroup sums its waves' parts in LDS.  With about eight
+// pieces per thread (NT = 128 at d = 1024 in complex128) the chip holds a few
+// waves per SIMD instead of the one a wave per row leaves it (complex128 at
+// d = 1024: 5.0 against 6.6 us per product).  Rows must be 16-byte aligned:
+// complex128, or complex64 with an even d.
+template <typename C2> struct Nt16;
+template <> struct Nt16<float2> { typedef float t __attribute__((ext_vector_type(4))); };
+template <> struct Nt16<double2> { typedef double t __attribute__((ext_vector_type(2))); };
+
+template <typename C2, int NT>
+__global__ __launch_bounds__(NT) void matvec_rows_kernel(const C2* __restrict__ U, const double2* __restrict__ x,
+                                                         double2* __restrict__ y, int d) {
+  using V = typename Nt16<C2>::t;
+  using T = decltype(C2().x);
+  constexpr int PER = Vec16<C2>::per, MAXP = 8;
+  const int row = blockIdx.x;
+  const V* ur = reinterpret_cast<const V*>(U + int64_t(row) * d);
+  const int nch = d / PER;
   double ar = 0.0, ai = 0.0;
-  for (int c0 = 0; c0 < nch; c0 += 64 * NL) {
-    if (c0 > 0) load(c0);
+  for (int base = 0; base < nch; base += NT * MAXP) {
+    V ub[MAXP];
+    double2 xb[MAXP][PER];
 #pragma unroll
-    for (int t = 0; t < NL; ++t) {
-      const int c = c0 + lane + 64 * t;
+    for (int t = 0; t < MAXP; ++t) {
+      const int c = base + int(threadIdx.x) + NT * t;
+      const int cc = c < nch ? c : 0;
+      ub[t] = __builtin_nontemporal_load(ur + cc);
+#pragma unroll
+      for (int q = 0; q < PER; ++q) xb[t][q] = x[cc * PER + q];
+    }
+#pragma unroll
+    for (int t = 0; t < MAXP; ++t) {
+      const int c = base + int(threadIdx.x) + NT * t;
       if (c < nch) {
-        const C2* e = reinterpret_cast<const C2*>(&buf[t]);
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-          const double2 v = xv[c * PER + q];
-          const double ur_ = double(e[q].x), ui_ = double(e[q].y);
-          ar += ur_ * v.x - ui_ * v.y;
-          ai += ur_ * v.y + ui_ * v.x;
+          const double ur_ = double(T(ub[t][2 * q])), ui_ = double(T(ub[t][2 * q + 1]));
+          ar += ur_ * xb[t][q].x - ui_ * xb[t][q].y;
+          ai += ur_ * xb[t][q].y + ui_ * xb[t][q].x;
         }
       }
     }
@@ -530,7 +529,19 @@ __global__ __launch_bounds__(256) void matvec16_kernel(const C2* __restrict__ U,
     ar += __shfl_down(ar, off);
     ai += __shfl_down(ai, off);
   }
-  if (active && lane == 0) y[row] = make_double2(ar, ai);
+  __shared__ double2 part[NT / 64];
+  const int wave = int(threadIdx.x) >> 6, lane = int(threadIdx.x) & 63;
+  if (lane == 0) part[wave] = make_double2(ar, ai);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 sum = part[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) {
+      sum.x += part[w].x;
+      sum.y += part[w].y;
+    }
+    y[row] = sum;
+  }
 }
 
 // Any d: one 8- or 16-byte element per lane per step.
