@@ -348,6 +348,26 @@ def test_propagate_parity(M, d, dtype):
     assert np.abs(host(P).astype(np.complex128) - P_o).max() <= ptol
 
 
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("d", [1000, 1030, 2100, 4100])
+def test_propagate_state_row_widths(d, dtype):
+    # the state chain takes 64 to 512 threads per row by the row's 16-byte piece
+    # count (complex64 with an odd d: one element per lane); a few intervals at
+    # each width, with a ragged last round of pieces, against the oracle's chain
+    M = 3
+    say(f"propagate state M={M} d={d} {dtype}")
+    g = np.random.default_rng(d)
+    Uo = (g.standard_normal((M, d, d)) + 1j * g.standard_normal((M, d, d))) / math.sqrt(2 * d)
+    Ud = gpu(Uo).to(dtype)
+    Uref = host(Ud).astype(np.complex128)
+    psi0 = wl.random_state(d, 11)
+    psi = gpu(psi0)
+    q.propagate(Ud, q.STATE, psi)
+    torch.cuda.synchronize()
+    psi_o = oracle.propagate_state(Uref, psi0)
+    assert np.abs(host(psi) - psi_o).max() <= 1e-13 * M * math.sqrt(d)
+
+
 # --------------------------------------------------------------- end to end
 
 def _evolve(w, dtype, chunk=None):
