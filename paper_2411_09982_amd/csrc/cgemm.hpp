@@ -477,7 +477,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
 // the same mix of cheap and costly tiles, and an item's tiles share one L2.
 // XCD x's slots are j = t / 8: group g holds slots [base[x][g], base[x][g + 1]),
 // item-major.  (A persistent form, a grid of resident workgroups walking the
-// slots, ran 2-4 % slower: values it hoisted out of its tile loop spilled.)
+// slots, ran 1-2 % slower on d = 1000-1024 products: values it hoisted out of
+// its tile loop spilled.)
 constexpr int kMaxGroups = 8;
 constexpr int kXcds = 8;
 template <typename T> struct GemmGroups {
@@ -509,7 +510,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU
 
 // Tile configurations per precision: cfg 0 is the large tile, cfg 1 the small
 // one (for small matrices, where the large tile would be mostly padding).
-// FP32 cfg 0: 128x128 tile, sixteen waves of 32x32 and K steps of 8: 60
+// FP32 cfg 0: 128x128 tile, sixteen waves of 32x32 and K steps of 8: 62
 // registers and 33 KB of LDS per workgroup, so two workgroups share a CU and
 // eight waves each SIMD (measured on batched d = 512..1024 products: 128-134
 // TFLOP/s general and 100-115 on (skew-)Hermitian halves, 2-10 % above eight
