@@ -135,6 +135,9 @@ __device__ __forceinline__ void tile_epilogue(const GemmParams<T>& p, const Tile
   const int b = jb.b;
   C2* C = jb.C;
   const bool lds_mirror = scr && p.herm && (p.epi == EPI_STD || p.epi == EPI_C32);
+  // (the LDS path for the augmented system's two FP64 mirrors fits the
+  // registers of 32 x 32 wave tiles; larger ones store them directly)
+  const bool aug_mirror = TM * TN <= 4 && scr && p.herm && p.epi == EPI_AUG;
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
 #pragma unroll
@@ -166,7 +169,7 @@ __device__ __forceinline__ void tile_epilogue(const GemmParams<T>& p, const Tile
           const double2 pp = make_double2(double(v.x) + pr, double(v.y) + pi);
           base[int64_t(r) * p.ld_aug + c] = q;
           base[int64_t(r) * p.ld_aug + p.aug_off + c] = pp;
-          if (p.herm && r != c) {
+          if (p.herm && r != c && !aug_mirror) {
             base[int64_t(c) * p.ld_aug + r] = make_double2(pp.x, -pp.y);
             base[int64_t(c) * p.ld_aug + p.aug_off + r] = make_double2(q.x, -q.y);
           }
@@ -227,6 +230,48 @@ __device__ __forceinline__ void tile_epilogue(const GemmParams<T>& p, const Tile
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      if constexpr (TM * TN <= 4) if (aug_mirror) {
+        // the two FP64 mirrors, q(c, r) = conj(p(r, c)) and p(c, r) = conj(q(r, c)),
+        // through 2 KB of the wave's LDS block (8 x 16 complex128) at a time: for
+        // each value and each half of the block's columns, the lanes holding those
+        // columns recompute it (V read again) and write it transposed, then all
+        // lanes read back rows and store 16 consecutive elements of each
+        double2* s2 = reinterpret_cast<double2*>(scr);
+        const int R0 = jb.row0 + wm + i * 16, C0 = jb.col0 + wn + j * 16;
+        double2* base = p.aug + b * p.s_aug;
+        const int cl = lane & 15;
+#pragma unroll
+        for (int which = 0; which < 2; ++which) {   // 0: conj(p) into q's half, 1: conj(q) into p's
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            if ((cl >> 3) == h) {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const int rl = acc_row<T>(lane, e);
+                const int r = R0 + rl, c = C0 + cl;
+                if (r >= p.M || c >= p.N || r >= c) continue;   // no mirror to write
+                const C2 v = p.X[0][b * p.sC + int64_t(r) * p.ldc + c];
+                const double pr = double(accr[i][j][e]), pi = double(acci[i][j][e]);
+                const double2 m = which == 0 ? make_double2(double(v.x) + pr, -(double(v.y) + pi))
+                                             : make_double2(double(v.x) - pr, -(double(v.y) - pi));
+                s2[(cl - 8 * h) * 16 + (rl ^ (cl - 8 * h))] = m;
+              }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+              const int tr = (lane >> 4) + 4 * k, tc = lane & 15;   // block column 8 h + tr, row tc
+              const int r = R0 + tc, c = C0 + 8 * h + tr;           // the element whose mirror this is
+              const double2 m = s2[tr * 16 + (tc ^ tr)];
+              if (r < c && r < p.M && c < p.N)
+                base[int64_t(c) * p.ld_aug + (which == 0 ? 0 : p.aug_off) + r] = m;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          }
+        }
       }
     }
   }
@@ -462,8 +507,8 @@ template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int WAVES_
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU))) void cgemm_kernel(
     GemmParams<T> p) {
   using C2 = typename Cx<T>::t;
-  __shared__ C2 As[2][BK][BM + 1];
-  __shared__ C2 Bs[2][BK][BN + (MODE == 1)];
+  __shared__ __attribute__((aligned(16))) C2 As[2][BK][BM + 1];
+  __shared__ __attribute__((aligned(16))) C2 Bs[2][BK][BN + (MODE == 1)];
   TileJob<T> jb;
   if (!tile_job<T, BM, BN>(p, xcd_remap(blockIdx.x, gridDim.x), jb)) return;
   cgemm_tile<T, BM, BN, BK, WM, WN, NT, MODE>(p, jb, As, Bs);
@@ -493,8 +538,8 @@ template <typename T, int BM, int BN, int BK, int WM, int WN, int NT, int WAVES_
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU))) void cgemm_grouped_kernel(
     GemmGroups<T> gg) {
   using C2 = typename Cx<T>::t;
-  __shared__ C2 As[2][BK][BM + 1];
-  __shared__ C2 Bs[2][BK][BN + (MODE == 1)];
+  __shared__ __attribute__((aligned(16))) C2 As[2][BK][BM + 1];
+  __shared__ __attribute__((aligned(16))) C2 Bs[2][BK][BN + (MODE == 1)];
   const int t = blockIdx.x;
   const int x = t % kXcds, j = t / kXcds;
   if (j >= gg.base[x][gg.G]) return;   // this XCD has fewer slots
