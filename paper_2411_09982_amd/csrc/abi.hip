@@ -508,6 +508,9 @@ struct LuCtx {
   hipStream_t st;
   int panel_nb;     // leaf width of the factorization
   int panel_rows;   // register panel: rows per item it can hold (0: global-memory panel)
+  // where the backward solve's leaves also place R (at most one of the two)
+  const LuPlace<float2>* place32 = nullptr;
+  const LuPlace<double2>* place64 = nullptr;
 };
 
 int lu_gemm_update(const LuCtx& c, int64_t r0, int64_t r1, int64_t c0, int64_t c1, int64_t k0, int64_t k1) {
@@ -562,12 +565,21 @@ int trsm_lower(const LuCtx& c, int64_t r0, int64_t r1, int64_t c0, int64_t c1) {
 int trsm_upper(const LuCtx& c, int64_t r0, int64_t r1, int64_t c0, int64_t c1) {
   if (r1 - r0 <= kTrsmNb) {
     const dim3 grid(nblocks(c1 - c0, 256), unsigned(c.nb));
-    if (r1 - r0 == kTrsmNb)
-      hipLaunchKernelGGL(trsm_upper_kernel, grid, dim3(256), 0, c.st, c.aug, c.ld, c.stride, int(r0), int(c0),
-                         int(c1));
+    auto leaf = [&](auto pl) {
+      using O = std::remove_pointer_t<decltype(pl.u0)>;
+      if (r1 - r0 == kTrsmNb)
+        hipLaunchKernelGGL(trsm_upper_kernel<O>, grid, dim3(256), 0, c.st, c.aug, c.ld, c.stride, int(r0), int(c0),
+                           int(c1), pl);
+      else
+        hipLaunchKernelGGL(trsm_upper_ragged_kernel<O>, grid, dim3(256), 0, c.st, c.aug, c.ld, c.stride, int(r0),
+                           int(r1), int(c0), int(c1), pl);
+    };
+    if (c.place32)
+      leaf(*c.place32);
+    else if (c.place64)
+      leaf(*c.place64);
     else
-      hipLaunchKernelGGL(trsm_upper_ragged_kernel, grid, dim3(256), 0, c.st, c.aug, c.ld, c.stride, int(r0), int(r1),
-                         int(c0), int(c1));
+      leaf(LuPlace<void>{nullptr, nullptr, nullptr, 0});
     QC_HIP(hipGetLastError());
     return QCHEFF_OK;
   }
@@ -613,8 +625,9 @@ int lu_factor(const LuCtx& c, int64_t k0, int64_t k1, int64_t cend) {
   return lu_pivots(c, km, k1, k0, km);                       // right pivots on the left half's L
 }
 
-int lu_solve(double2* aug, int* piv, int64_t d, int64_t nb, hipStream_t st) {
-  LuCtx c{aug, piv, d, 2 * d, 2 * d * d, nb, st, 32, 0};
+int lu_solve(double2* aug, int* piv, int64_t d, int64_t nb, hipStream_t st,
+             const LuPlace<float2>* place32 = nullptr, const LuPlace<double2>* place64 = nullptr) {
+  LuCtx c{aug, piv, d, 2 * d, 2 * d * d, nb, st, 32, 0, place32, place64};
   if (d <= 1024) { c.panel_nb = 16; c.panel_rows = 1024; }
   int r;
   if ((r = lu_factor(c, 0, d, 2 * d))) return r;             // P, L^{-1} on p along the way
@@ -962,11 +975,14 @@ int expm_stage_b(ExpmChunk<T>* ch, int G, RoundState<T>& rs, SideStreams* set, h
       sg = side->stream[g % SideStreams::kCount];
       QC_HIP(hipStreamWaitEvent(sg, side->fork, 0));
     }
-    if (int r = lu_solve(w.aug, w.piv, d, ch[g].nb, sg)) return r;
-    const unsigned sblocks = unsigned(std::min<int64_t>(nblocks(dd, 256), 1024));
-    hipLaunchKernelGGL(place_result_kernel<C2>, dim3(sblocks, unsigned(ch[g].nb)), dim3(256), 0, sg, w.aug, int(d),
-                       w.s_ws, rs.sq0[g], rs.sq1[g]);
-    QC_HIP(hipGetLastError());
+    // the solve's last leaves place R where the squarings start
+    const LuPlace<C2> pl{w.s_ws, rs.sq0[g], rs.sq1[g], int(d)};
+    int r;
+    if constexpr (std::is_same_v<C2, float2>)
+      r = lu_solve(w.aug, w.piv, d, ch[g].nb, sg, &pl, nullptr);
+    else
+      r = lu_solve(w.aug, w.piv, d, ch[g].nb, sg, nullptr, &pl);
+    if (r) return r;
   }
   if (side) {
     for (int k = 0; k < std::min(G, SideStreams::kCount); ++k) {

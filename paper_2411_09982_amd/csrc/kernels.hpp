@@ -444,23 +444,6 @@ __global__ __launch_bounds__(256) void pade_inner_kernel(const C2* __restrict__ 
   }
 }
 
-// R = aug[:, d:2d] written (cast) to the buffer where the squarings must start
-// so that the last one lands in U: U if s is even (or no squaring), else P1.
-template <typename C2>
-__global__ __launch_bounds__(256) void place_result_kernel(const double2* __restrict__ aug, int d,
-                                                           const int* __restrict__ s_ws, C2* U, C2* P1) {
-  const int b = blockIdx.y;
-  const int64_t dd = int64_t(d) * d;
-  const int s = s_ws[b];
-  C2* dst = ((s > 0 && (s & 1)) ? P1 : U) + b * dd;
-  const double2* src = aug + b * 2 * dd;
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < dd; e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t i = e / d, j = e % d;
-    const double2 v = src[i * 2 * d + d + j];
-    dst[e] = to_c2<C2>(v.x, v.y);
-  }
-}
-
 // ------------------------------------------------------ unitary refinement
 //
 // The FP32 squarings double the deviation of every |eigenvalue| of R from 1 at

@@ -353,11 +353,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void t
     store_at(A + int64_t(r0 + j) * ld, off, x[j]);
 }
 
+// Placement of the solution by the last leaves of the backward solve: besides
+// the FP64 rows the recursion above still reads, each leaf writes its final
+// rows of R (the right half, columns d .. 2d) in the chunk's element type O to
+// item b's buffer u1 when its squaring count s is odd and positive, else u0,
+// where the squarings start (O = void: no placement).
+template <typename O> struct LuPlace {
+  const int* s;
+  O* u0;
+  O* u1;
+  int d;
+};
+template <typename O> __device__ __forceinline__ O narrow_c(double2 v);
+template <> __device__ __forceinline__ float2 narrow_c<float2>(double2 v) { return make_float2(float(v.x), float(v.y)); }
+template <> __device__ __forceinline__ double2 narrow_c<double2>(double2 v) { return v; }
+template <typename O>
+__device__ __forceinline__ O* place_base(const LuPlace<O>& pl, int b) {
+  const int s = pl.s[b];
+  return ((s > 0 && (s & 1)) ? pl.u1 : pl.u0) + int64_t(b) * pl.d * pl.d;
+}
+
 // X <- U^{-1} X for rows [r0, r0 + 32), U = upper part of the diagonal block
 // (non-unit diagonal, its reciprocals kept in LDS), columns [c0, c1); one thread
 // per column, no per-row guard.
+template <typename O>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void trsm_upper_kernel(
-    double2* aug, int64_t ld, int64_t stride, int r0, int c0, int c1) {
+    double2* aug, int64_t ld, int64_t stride, int r0, int c0, int c1, LuPlace<O> pl) {
   const int b = blockIdx.y;
   double2* A = aug + b * stride;
   __shared__ double2 Ub[kTrsmNb][kTrsmNb];
@@ -392,6 +413,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void t
 #pragma unroll
   for (int j = 0; j < kTrsmNb; ++j)
     store_at(A + int64_t(r0 + j) * ld, off, x[j]);
+  if constexpr (!std::is_void_v<O>) {
+    O* dst = place_base(pl, b) + (c - pl.d);
+#pragma unroll
+    for (int j = 0; j < kTrsmNb; ++j) dst[int64_t(r0 + j) * pl.d] = narrow_c<O>(x[j]);
+  }
 }
 
 // The same two leaves for fewer than 32 rows (the last leaf of a size that is not
@@ -429,8 +455,9 @@ __global__ __launch_bounds__(256) void trsm_lower_unit_ragged_kernel(double2* au
 }
 
 // X <- U^{-1} X, U upper with a non-unit diagonal, fewer than 32 rows.
+template <typename O>
 __global__ __launch_bounds__(256) void trsm_upper_ragged_kernel(double2* aug, int64_t ld, int64_t stride, int r0, int r1,
-                                                         int c0, int c1) {
+                                                         int c0, int c1, LuPlace<O> pl) {
   const int b = blockIdx.y;
   double2* A = aug + b * stride;
   const int nb = r1 - r0;
@@ -466,6 +493,12 @@ __global__ __launch_bounds__(256) void trsm_upper_ragged_kernel(double2* aug, in
 #pragma unroll
   for (int j = 0; j < kTrsmNb; ++j)
     if (j < nb) A[int64_t(r0 + j) * ld + c] = x[j];
+  if constexpr (!std::is_void_v<O>) {
+    O* dst = place_base(pl, b) + (c - pl.d);
+#pragma unroll
+    for (int j = 0; j < kTrsmNb; ++j)
+      if (j < nb) dst[int64_t(r0 + j) * pl.d] = narrow_c<O>(x[j]);
+  }
 }
 
 }  // namespace qcheff
